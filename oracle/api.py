@@ -1,0 +1,75 @@
+"""Top-level oracle calls mirroring the C ABI: environment, expectation values
+and cluster windows.  Test infrastructure only (see the package docstring).
+
+* ``env_boundary`` - boundaries from the top and from the bottom with bond chi
+  (Sec. 2, the sandwich contraction from both sides).
+* ``expect`` - log <psi|psi> and its sign from the row in the centre, <S^z>
+  on every site from its row sandwich, horizontal bond energies from the row
+  sandwich and vertical ones from the two-row sandwich (readings, see
+  ``sandwich``).
+* ``cluster_env`` - per-site n x n windows closed by CU_0 separable
+  boundaries (``cluster``), Sec. 5.3.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from .boundary import flip_vertical, top_boundaries, whole_lattice, Lattice
+from .sandwich import row_observables, two_row_observables
+
+DEFAULT_SEED = 0x13116696
+DEFAULT_HALFSWEEPS = 4
+
+
+@dataclass
+class Env:
+    lat: Lattice
+    top: list      # top[r+1] = (tensors, log_scale, info) of T_r, r = -1..Lr-2
+    bottom: list   # bottom[k] = boundary of the flipped lattice, k-1 rows absorbed
+    chi: int
+
+    def T(self, r):
+        """Top boundary with rows 0..r absorbed (r = -1 is the top closing)."""
+        return self.top[r + 1]
+
+    def B(self, r):
+        """Bottom boundary with rows r..Lr-1 absorbed (r = Lr is the closing),
+        tensors [o, d, g, o'] with d,g the down legs of row r-1."""
+        return self.bottom[self.lat.rows - r]
+
+
+def env_boundary(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED):
+    lat = lat_or_A if isinstance(lat_or_A, Lattice) else whole_lattice(lat_or_A)
+    top = top_boundaries(lat, chi, halfsweeps, seed, side=0)
+    bottom = top_boundaries(flip_vertical(lat), chi, halfsweeps, seed, side=1)
+    return Env(lat, top, bottom, chi)
+
+
+def expect(env, rows=None):
+    """Observables of an environment; ``rows`` limits the single-row sandwiches."""
+    lat = env.lat
+    Lr, Lc = lat.rows, lat.cols
+    sz = np.full((Lr, Lc), np.nan)
+    bh = np.full((Lr, max(Lc - 1, 0)), np.nan)
+    bv = np.full((max(Lr - 1, 0), Lc), np.nan)
+    log_norm, sign = None, None
+    rc = Lr // 2
+    for r in (range(Lr) if rows is None else rows):
+        T, sT, _ = env.T(r - 1)
+        B, sB, _ = env.B(r + 1)
+        s, h, Z, sLR, _ = row_observables(T, lat.A[r], B, lat.lam[r], lat.rho[r])
+        sz[r], bh[r] = s, h
+        if r == rc:
+            log_norm = sT + sB + sLR + np.log(abs(Z))
+            sign = 1.0 if Z >= 0 else -1.0
+    for r in (range(Lr - 1) if rows is None else [x for x in rows if x < Lr - 1]):
+        T, _, _ = env.T(r - 1)
+        B, _, _ = env.B(r + 2)
+        bv[r] = two_row_observables(T, lat.A[r], lat.A[r + 1], B, lat.lam[r], lat.rho[r],
+                                    lat.lam[r + 1], lat.rho[r + 1])
+    return dict(log_norm=log_norm, sign=sign, sz=sz, bond_h=bh, bond_v=bv)
+
+
+def energy(res):
+    """Total Heisenberg energy sum of bond terms (eq. HeisenbergH)."""
+    return float(np.nansum(res["bond_h"]) + np.nansum(res["bond_v"]))
