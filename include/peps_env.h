@@ -1,0 +1,152 @@
+/*
+ * peps_env.h - C ABI of libpepsenv: boundary-MPS environments of finite,
+ * open-boundary PEPS on one MI355X (gfx950).
+ *
+ * Method: Lubasch, Cirac, Banuls, "Unifying Projected Entangled Pair States
+ * contractions", arXiv:1311.6696.
+ *   - peps_env_boundary: the sandwich contraction of Sec. 2 (fig. Sandwich):
+ *     the norm network <psi|psi> is contracted from the top and from the
+ *     bottom row by row; each MPS-MPO product is truncated back to bond chi
+ *     (the paper's D') by alternating least squares with a QR gauge.
+ *   - peps_expect: the row in the centre is contracted between the two
+ *     boundaries (Sec. 2) giving log <psi|psi>; <S^z> and the Heisenberg bond
+ *     energies of eq. (HeisenbergH) come from row / two-row sandwiches.
+ *   - peps_cluster_env: cluster environments of Sec. 5: separable (D'=1,
+ *     CU_0, Sec. 5.1) boundaries outside an n x n window around each site,
+ *     the sandwich contraction with bond chi inside it (Sec. 5.2, 5.3).
+ *
+ * Conventions
+ *   - Site tensor A[p][l][u][r][d], float64, C order (d fastest), p the
+ *     physical index (p = 0 is spin up), l/u/r/d the left/up/right/down
+ *     virtual legs; "up" points to row 0; site (r, c) is entry r*cols + c.
+ *     Legs on the lattice edge must have dimension 1; neighbouring legs must
+ *     agree.  Entries are real; the bra layer is the same tensor.
+ *   - Site tensors are DEVICE pointers on the context's device; dims and the
+ *     pointer array itself are HOST memory.  Inputs are read during the call
+ *     only (the library keeps packed copies).
+ *   - Results are written to caller-allocated HOST buffers.
+ *   - All work is enqueued on the context's stream; every entry point
+ *     returns only after the results it writes are complete.
+ *
+ * Errors: every entry point returns peps_status.  On error nothing is
+ * written to *out and peps_last_error() describes the failure (thread-local
+ * string valid until the next call on the thread).  Arguments are validated
+ * on the host before any launch.  No C++ exception crosses the ABI.  A
+ * context must be used by one thread at a time.
+ */
+#ifndef PEPS_ENV_H
+#define PEPS_ENV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PEPS_OK = 0,
+  PEPS_ERR_INVALID = -1,      /* bad shape, bond mismatch, chi < 1, bad window, NULL pointer */
+  PEPS_ERR_OOM = -2,          /* device allocation failed or workspace cap exceeded */
+  PEPS_ERR_HIP = -3,          /* a HIP runtime call failed */
+  PEPS_ERR_NONFINITE = -5,    /* NaN/Inf in an input tensor or in a computed norm */
+  PEPS_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+} peps_status;
+
+/* Arithmetic of the bulk contractions.  QR gauge, norms and log-scales are
+ * always float64. */
+typedef enum {
+  PEPS_F64 = 0,   /* float64 operands, float64 MFMA */
+  PEPS_F32 = 1,   /* float32 operands, float32 MFMA, float32 accumulation */
+  PEPS_BF16 = 2   /* bfloat16 operands (RNE from float32), float32 accumulation */
+} peps_dtype;
+
+typedef struct peps_ctx peps_ctx;   /* device, stream, memory pool */
+typedef struct peps_env peps_env;   /* device-resident boundaries of one lattice or window */
+
+/* One open-boundary PEPS. */
+typedef struct {
+  int32_t rows, cols;          /* L_r, L_c >= 1 */
+  int32_t phys;                /* physical dimension d; the observables need d == 2 */
+  const int32_t* dims;         /* host, rows*cols*5 entries (d, Dl, Du, Dr, Dd) per site */
+  const double* const* site;   /* host array of rows*cols device pointers */
+} peps_state;
+
+typedef struct {
+  int32_t chi;          /* boundary bond dimension D' >= 1 */
+  int32_t dtype;        /* peps_dtype */
+  int32_t halfsweeps;   /* ALS half-sweeps per truncated row, >= 1 (default 4 if 0) */
+  int32_t flags;        /* reserved, 0 */
+  uint64_t seed;        /* SplitMix64 key of the ALS start tensors */
+} peps_env_opts;
+
+/* Cluster window around the centre site (ci, cj) of state `state`,
+ * rows r0..r1 and columns c0..c1 inclusive, centre inside the window. */
+typedef struct {
+  int32_t state;
+  int32_t r0, r1, c0, c1;
+  int32_t ci, cj;
+} peps_window;
+
+/* Results of peps_expect for one environment.
+ * Whole lattice: sz has rows*cols entries (row-major); bond has
+ * rows*(cols-1) horizontal bonds (r,c)-(r,c+1) in row-major order followed
+ * by (rows-1)*cols vertical bonds (r,c)-(r+1,c) in row-major order.
+ * Window: sz has 1 entry (centre), bond has 2 (right, down; NaN if the
+ * neighbour lies outside the window).
+ * log_norm = log|<psi|psi>| from row floor(rows/2); norm_sign its sign.
+ * flops = algorithmic flop count of the boundary and expectation work. */
+typedef struct {
+  double log_norm;
+  double norm_sign;
+  double* sz;           /* caller-allocated host buffer */
+  double* bond;         /* caller-allocated host buffer */
+  double flops;
+} peps_result;
+
+/* Create a context on HIP device `device` using stream `hip_stream`
+ * (a hipStream_t, NULL = the null stream).  The stream is borrowed. */
+peps_status peps_ctx_create(int32_t device, void* hip_stream, peps_ctx** out);
+void peps_ctx_destroy(peps_ctx* ctx);
+
+/* Top and bottom boundaries of n_states lattices (one batched run).
+ * opts points to one options record used for all states.  On success
+ * out[i] receives a new environment handle per state. */
+peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_states,
+                              const peps_env_opts* opts, peps_env** out);
+
+/* Cluster environments: the CU_0 separable boundaries of the four
+ * directions of each referenced state, then the boundaries inside every
+ * window (one batched run).  out[i] receives the environment of win[i]. */
+peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int32_t n_states,
+                             const peps_window* win, int32_t n_win,
+                             const peps_env_opts* opts, peps_env** out);
+
+/* Observables of n_env environments (one batched run). */
+peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps_result* out);
+
+void peps_env_free(peps_env* env);
+
+/* Diagnostics of an environment: number of truncated rows, and the squared
+ * norm of the ALS centre tensor after each half-sweep of each truncated row
+ * (host buffer of at least n_rows*halfsweeps doubles; may be NULL). */
+peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas);
+
+/* Profiling of the contraction kernel: when enabled, every contraction
+ * launch is bracketed by HIP events on the context's stream; statistics are
+ * kept per kernel variant, index = prec*8 + out_dtype*4 + tile
+ * (prec: 0 f64, 1 f32, 2 bf16; out_dtype: 0 f64, 1 f32; tile: 0 64x64,
+ * 1 128x32, 2 256x16, 3 32x128).  Enabling clears the statistics. */
+peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
+/* Copies the 24 per-variant statistics: algorithmic flops, milliseconds and
+ * launch counts (host arrays of 24 entries each). */
+peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches);
+/* Upper bound (bytes) of the transient workspace one call may hold for the
+ * chain intermediates of a batch; larger batches run in several groups. */
+peps_status peps_ctx_set_workspace(peps_ctx* ctx, uint64_t bytes);
+
+const char* peps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PEPS_ENV_H */

@@ -1,0 +1,257 @@
+"""ctypes binding of libpepsenv (include/peps_env.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (CUDA/ROCm tensors) and the stream.
+The library must have been built (``paper_1311_6696_amd.build``); loading
+fails loudly otherwise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpepsenv.so")
+
+PEPS_F64, PEPS_F32, PEPS_BF16 = 0, 1, 2
+DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
+STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
+DEFAULT_SEED = 0x13116696
+N_STATS = 24
+
+
+class PepsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class State(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("phys", C.c_int32),
+                ("dims", C.POINTER(C.c_int32)), ("site", C.POINTER(C.c_void_p))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("chi", C.c_int32), ("dtype", C.c_int32), ("halfsweeps", C.c_int32),
+                ("flags", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Window(C.Structure):
+    _fields_ = [("state", C.c_int32), ("r0", C.c_int32), ("r1", C.c_int32), ("c0", C.c_int32),
+                ("c1", C.c_int32), ("ci", C.c_int32), ("cj", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("log_norm", C.c_double), ("norm_sign", C.c_double), ("sz", C.POINTER(C.c_double)),
+                ("bond", C.POINTER(C.c_double)), ("flops", C.c_double)]
+
+
+SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
+           "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_stats", "peps_ctx_set_workspace",
+           "peps_last_error")
+
+_lib = None
+
+
+def load(path=None):
+    """Load the HIP library (once); raises OSError if it is missing."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError(f"{p} not found: build it with `python -m paper_1311_6696_amd.build`")
+    lib = C.CDLL(p)
+    vp, i32, pp = C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)
+    lib.peps_ctx_create.argtypes = [i32, vp, pp]
+    lib.peps_ctx_destroy.argtypes = [vp]
+    lib.peps_ctx_destroy.restype = None
+    lib.peps_env_boundary.argtypes = [vp, C.POINTER(State), i32, C.POINTER(Opts), pp]
+    lib.peps_cluster_env.argtypes = [vp, C.POINTER(State), i32, C.POINTER(Window), i32, C.POINTER(Opts), pp]
+    lib.peps_expect.argtypes = [vp, pp, i32, C.POINTER(Result)]
+    lib.peps_env_free.argtypes = [vp]
+    lib.peps_env_free.restype = None
+    lib.peps_env_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]
+    lib.peps_ctx_profile.argtypes = [vp, i32]
+    lib.peps_ctx_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.peps_ctx_set_workspace.argtypes = [vp, C.c_uint64]
+    lib.peps_last_error.argtypes = []
+    lib.peps_last_error.restype = C.c_char_p
+    for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
+                 "peps_ctx_profile", "peps_ctx_stats", "peps_ctx_set_workspace"):
+        getattr(lib, name).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, code):
+    if code != 0:
+        raise PepsError(code, lib.peps_last_error().decode())
+
+
+class RawState:
+    """A lattice given as device pointers: ``ptrs[r][c]`` and ``shapes[r][c]``
+    (d, Dl, Du, Dr, Dd).  Keeps the ctypes arrays alive."""
+
+    def __init__(self, ptrs, shapes):
+        self.rows, self.cols = len(ptrs), len(ptrs[0])
+        flat_dims = [int(x) for row in shapes for s in row for x in s]
+        self.dims = (C.c_int32 * len(flat_dims))(*flat_dims)
+        flat_ptrs = [int(p) for row in ptrs for p in row]
+        self.site = (C.c_void_p * len(flat_ptrs))(*flat_ptrs)
+        self.phys = int(shapes[0][0][0])
+        self.shapes = shapes
+
+    def struct(self):
+        return State(self.rows, self.cols, self.phys, self.dims, self.site)
+
+
+class Env:
+    def __init__(self, ctx, handle, rows, cols, window=False):
+        self.ctx, self.handle, self.rows, self.cols, self.window = ctx, handle, rows, cols, window
+
+    def info(self):
+        lib = self.ctx.lib
+        n, h = C.c_int32(), C.c_int32()
+        _check(lib, lib.peps_env_info(self.handle, C.byref(n), C.byref(h), None))
+        om = (C.c_double * max(1, n.value * h.value))()
+        _check(lib, lib.peps_env_info(self.handle, None, None, om))
+        return np.array(om[: n.value * h.value]).reshape(n.value, h.value)
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.peps_env_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one device and stream (raw pointer interface)."""
+
+    def __init__(self, device=0, stream=0, lib=None):
+        self.lib = lib or load()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.peps_ctx_create(int(device), C.c_void_p(int(stream) or None), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self.lib.peps_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def opts(chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        return Opts(int(chi), DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(halfsweeps), 0,
+                    int(seed) & ((1 << 64) - 1))
+
+    def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        n = len(states)
+        arr = (State * n)(*[s.struct() for s in states])
+        out = (C.c_void_p * n)()
+        o = self.opts(chi, dtype, halfsweeps, seed)
+        _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, C.byref(o), out))
+        return [Env(self, out[i], s.rows, s.cols) for i, s in enumerate(states)]
+
+    def cluster_env_raw(self, states, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        n = len(states)
+        arr = (State * n)(*[s.struct() for s in states])
+        w = (Window * len(windows))(*[Window(*[int(x) for x in win]) for win in windows])
+        out = (C.c_void_p * len(windows))()
+        o = self.opts(chi, dtype, halfsweeps, seed)
+        _check(self.lib, self.lib.peps_cluster_env(self.handle, arr, n, w, len(windows), C.byref(o), out))
+        return [Env(self, out[i], win[2] - win[1] + 1, win[4] - win[3] + 1, window=True)
+                for i, win in enumerate(windows)]
+
+    def expect(self, envs):
+        n = len(envs)
+        hs = (C.c_void_p * n)(*[e.handle for e in envs])
+        bufs = []
+        res = (Result * n)()
+        for i, e in enumerate(envs):
+            nsz = 1 if e.window else e.rows * e.cols
+            nb = 2 if e.window else e.rows * (e.cols - 1) + (e.rows - 1) * e.cols
+            sz = np.zeros(nsz)
+            bd = np.zeros(max(nb, 1))
+            bufs.append((sz, bd))
+            res[i].sz = sz.ctypes.data_as(C.POINTER(C.c_double))
+            res[i].bond = bd.ctypes.data_as(C.POINTER(C.c_double))
+        _check(self.lib, self.lib.peps_expect(self.handle, hs, n, res))
+        out = []
+        for i, e in enumerate(envs):
+            sz, bd = bufs[i]
+            d = dict(log_norm=res[i].log_norm, sign=res[i].norm_sign, flops=res[i].flops)
+            if e.window:
+                d.update(sz=sz[0], right=bd[0], down=bd[1])
+            else:
+                R, Cc = e.rows, e.cols
+                d.update(sz=sz.reshape(R, Cc), bond_h=bd[: R * (Cc - 1)].reshape(R, Cc - 1),
+                         bond_v=bd[R * (Cc - 1): R * (Cc - 1) + (R - 1) * Cc].reshape(R - 1, Cc))
+            out.append(d)
+        return out
+
+    def profile(self, enable=True):
+        _check(self.lib, self.lib.peps_ctx_profile(self.handle, 1 if enable else 0))
+
+    def stats(self):
+        f = (C.c_double * N_STATS)()
+        m = (C.c_double * N_STATS)()
+        n = (C.c_int64 * N_STATS)()
+        _check(self.lib, self.lib.peps_ctx_stats(self.handle, f, m, n))
+        return np.array(f[:]), np.array(m[:]), np.array(n[:])
+
+    def set_workspace(self, nbytes):
+        _check(self.lib, self.lib.peps_ctx_set_workspace(self.handle, int(nbytes)))
+
+
+# ------------------------------------------------------------ torch layer ---
+
+def to_device(A, device="cuda"):
+    """Site tensors (nested lists of float64 numpy arrays) -> contiguous
+    float64 torch tensors on the GPU."""
+    import torch
+    return [[torch.as_tensor(np.ascontiguousarray(t), dtype=torch.float64, device=device) for t in row] for row in A]
+
+
+def state_of(tensors):
+    """RawState from nested lists of float64 device tensors."""
+    for row in tensors:
+        for t in row:
+            if not t.is_cuda or t.dtype.__str__() != "torch.float64" or not t.is_contiguous():
+                raise ValueError("site tensors must be contiguous float64 GPU tensors")
+    return RawState([[t.data_ptr() for t in row] for row in tensors],
+                    [[tuple(t.shape) for t in row] for row in tensors])
+
+
+class Session:
+    """Context bound to torch's current device and stream."""
+
+    def __init__(self, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to torch: the HIP library needs an MI355X")
+        dev = torch.cuda.current_device() if device is None else device
+        self.torch = torch
+        self.stream = torch.cuda.current_stream(dev)
+        self.ctx = Context(dev, self.stream.cuda_stream)
+
+    def env_boundary(self, tensors_list, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        states = [state_of(t) for t in tensors_list]
+        return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed)
+
+    def cluster_env(self, tensors_list, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        states = [state_of(t) for t in tensors_list]
+        return self.ctx.cluster_env_raw(states, windows, chi, dtype, halfsweeps, seed)
+
+    def expect(self, envs):
+        return self.ctx.expect(envs)

@@ -1,0 +1,264 @@
+// extern "C" entry points of libpepsenv (declared in include/peps_env.h).
+#include <cmath>
+#include <cstdio>
+#include <functional>
+
+#include "../../include/peps_env.h"
+#include "planner.hpp"
+#include "chains.hpp"
+
+namespace pe {
+namespace {
+
+thread_local std::string g_err;
+
+peps_status fail(int code, const std::string& msg) {
+  g_err = msg;
+  return (peps_status)code;
+}
+
+template <class F>
+peps_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    f();
+    return PEPS_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ST_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ST_INVALID, e.what());
+  }
+}
+
+// spin-1/2 operators on the ket physical leg (index 0 = up)
+const double OPS[4][4] = {
+    {1.0, 0.0, 0.0, 1.0},     // identity
+    {0.5, 0.0, 0.0, -0.5},    // S^z
+    {0.0, 1.0, 0.0, 0.0},     // S^+
+    {0.0, 0.0, 1.0, 0.0},     // S^-
+};
+
+void validate_state(const peps_state& s, int idx) {
+  const std::string w = "state " + std::to_string(idx) + ": ";
+  PE_REQUIRE(s.rows >= 1 && s.cols >= 1, w + "rows and cols must be >= 1");
+  PE_REQUIRE(s.dims && s.site, w + "dims and site must not be NULL");
+  if (s.phys != 2) throw Error(ST_UNSUPPORTED, w + "the spin-1/2 observables need phys == 2");
+  for (int r = 0; r < s.rows; ++r)
+    for (int c = 0; c < s.cols; ++c) {
+      const int32_t* d = s.dims + 5 * ((size_t)r * s.cols + c);
+      const std::string at = w + "site (" + std::to_string(r) + "," + std::to_string(c) + ") ";
+      for (int k = 0; k < 5; ++k) PE_REQUIRE(d[k] >= 1 && d[k] <= 4096, at + "has a dimension outside [1, 4096]");
+      PE_REQUIRE(d[0] == s.phys, at + "physical dimension differs from phys");
+      PE_REQUIRE(s.site[(size_t)r * s.cols + c] != nullptr, at + "has a NULL tensor");
+      if (c == 0) PE_REQUIRE(d[1] == 1, at + "left edge leg must have dimension 1");
+      if (c == s.cols - 1) PE_REQUIRE(d[3] == 1, at + "right edge leg must have dimension 1");
+      if (r == 0) PE_REQUIRE(d[2] == 1, at + "top edge leg must have dimension 1");
+      if (r == s.rows - 1) PE_REQUIRE(d[4] == 1, at + "bottom edge leg must have dimension 1");
+      if (c + 1 < s.cols) PE_REQUIRE(d[3] == (d + 5)[1], at + "right leg does not match its neighbour");
+      if (r + 1 < s.rows) PE_REQUIRE(d[4] == (d + 5 * s.cols)[2], at + "down leg does not match its neighbour");
+    }
+}
+
+Opts make_opts(const peps_env_opts* o) {
+  PE_REQUIRE(o != nullptr, "opts must not be NULL");
+  PE_REQUIRE(o->chi >= 1, "chi must be >= 1");
+  PE_REQUIRE(o->dtype >= PEPS_F64 && o->dtype <= PEPS_BF16, "unknown dtype");
+  PE_REQUIRE(o->halfsweeps >= 0 && o->halfsweeps <= 64, "halfsweeps must be in [0, 64]");
+  PE_REQUIRE(o->flags == 0, "flags must be 0");
+  Opts r;
+  r.chi = o->chi;
+  r.dtype = o->dtype;
+  r.halfsweeps = o->halfsweeps == 0 ? 4 : o->halfsweeps;
+  r.seed = o->seed;
+  return r;
+}
+
+// Packs the caller's float64 sites into `owner`'s arena: identity, S^z, S^+,
+// S^- applied to the ket leg, in the contraction dtype.
+struct Packed {
+  std::vector<std::unique_ptr<Site>> sites;
+};
+
+void pack_state(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out) {
+  std::vector<EwDesc> ew;
+  const size_t esz = dtype_size(cdt);
+  for (int i = 0; i < s.rows * s.cols; ++i) {
+    const int32_t* d = s.dims + 5 * i;
+    auto st = std::make_unique<Site>();
+    st->d = d[0];
+    st->Dl = d[1];
+    st->Du = d[2];
+    st->Dr = d[3];
+    st->Dd = d[4];
+    const int64_t n = (int64_t)d[0] * d[1] * d[2] * d[3] * d[4];
+    for (int op = 0; op < 4; ++op) {
+      st->op[op] = arena.alloc(esz * n);
+      EwDesc e = ew_desc(op == 0 ? EW_COPY : EW_PHYS, s.site[i], DT_F64, st->op[op], cdt, n);
+      for (int k = 0; k < 4; ++k) e.op[k] = OPS[op][k];
+      ew.push_back(e);
+    }
+    out.push_back(std::move(st));
+  }
+  rec.ew(ew);
+}
+
+void* make_one(Rec& rec, Arena& arena, int cdt) {
+  void* p = arena.alloc(16);
+  std::vector<EwDesc> ew{ew_desc(EW_FILL, nullptr, cdt, p, cdt, 1)};
+  ew[0].a = 1.0;
+  rec.ew(ew);
+  return p;
+}
+
+}  // namespace
+
+void validate_state_public(const peps_state& s, int idx) { validate_state(s, idx); }
+Opts make_opts_public(const peps_env_opts* o) { return make_opts(o); }
+void pack_state_public(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out) {
+  pack_state(rec, arena, s, cdt, out);
+}
+void* make_one_public(Rec& rec, Arena& arena, int cdt) { return make_one(rec, arena, cdt); }
+peps_status guarded_public(const std::function<void()>& f) { return guarded(f); }
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+const char* peps_last_error(void) { return g_err.c_str(); }
+
+peps_status peps_ctx_create(int32_t device, void* hip_stream, peps_ctx** out) {
+  return guarded([&] {
+    PE_REQUIRE(out != nullptr, "out must not be NULL");
+    *out = nullptr;
+    const int n = dev::device_count();
+    PE_REQUIRE(device >= 0 && device < n, "no such HIP device");
+    dev::set_device(device);
+    auto* c = new peps_ctx();
+    c->c = std::make_shared<Ctx>();
+    c->c->device = device;
+    c->c->stream = (hipStream_t)hip_stream;
+    *out = c;
+  });
+}
+
+void peps_ctx_destroy(peps_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    dev::sync(ctx->c->stream);
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_states, const peps_env_opts* opts,
+                              peps_env** out) {
+  std::vector<peps_env*> made;
+  peps_status s = guarded([&] {
+    PE_REQUIRE(ctx && st && out, "ctx, st and out must not be NULL");
+    PE_REQUIRE(n_states >= 1, "n_states must be >= 1");
+    const Opts o = make_opts(opts);
+    for (int i = 0; i < n_states; ++i) validate_state(st[i], i);
+    dev::set_device(ctx->c->device);
+    Arena tmp(&ctx->c->pool);
+    Rec rec(ctx->c.get());
+    for (int i = 0; i < n_states; ++i) {
+      auto* e = new peps_env(ctx->c);
+      made.push_back(e);
+      e->opts = o;
+      pack_state(rec, e->arena, st[i], o.cdt(), e->sites);
+      void* one = make_one(rec, e->arena, o.cdt());
+      Lattice& L = e->lat;
+      L.Lr = st[i].rows;
+      L.Lc = st[i].cols;
+      for (auto& p : e->sites) L.s.push_back(p.get());
+      L.lam.assign(L.Lr, one);
+      L.rho.assign(L.Lr, one);
+      L.tau.assign(L.Lc, one);
+      L.beta.assign(L.Lc, one);
+    }
+    rec.run(tmp);
+    plan_boundaries(*ctx->c, made);
+    for (int i = 0; i < n_states; ++i) out[i] = made[i];
+  });
+  if (s != PEPS_OK)
+    for (peps_env* e : made) delete e;
+  return s;
+}
+
+peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps_result* out) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && env && out, "ctx, env and out must not be NULL");
+    PE_REQUIRE(n_env >= 1, "n_env must be >= 1");
+    std::vector<peps_env*> es;
+    for (int i = 0; i < n_env; ++i) {
+      PE_REQUIRE(env[i] != nullptr, "NULL environment");
+      PE_REQUIRE(env[i]->ctx == ctx->c.get(), "environment belongs to another context");
+      PE_REQUIRE(out[i].sz && out[i].bond, "result buffers must not be NULL");
+      es.push_back(env[i]);
+    }
+    dev::set_device(ctx->c->device);
+    std::vector<double> f0;
+    for (peps_env* e : es) f0.push_back(e->flops);
+    std::vector<ExpectOut> res;
+    plan_expect(*ctx->c, es, res);
+    for (int i = 0; i < n_env; ++i) {
+      const ExpectOut& r = res[i];
+      for (double v : r.sz)
+        if (!std::isfinite(v) && !es[i]->window) throw Error(ST_NONFINITE, "non-finite <S^z>");
+      out[i].log_norm = r.log_norm;
+      out[i].norm_sign = r.sign;
+      std::memcpy(out[i].sz, r.sz.data(), sizeof(double) * r.sz.size());
+      std::memcpy(out[i].bond, r.bond.data(), sizeof(double) * r.bond.size());
+      out[i].flops = es[i]->flops;
+      es[i]->flops = f0[i];   // boundary flops stay; this call's sandwich flops are reported once
+    }
+  });
+}
+
+void peps_env_free(peps_env* env) { delete env; }
+
+peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas) {
+  return guarded([&] {
+    PE_REQUIRE(env != nullptr, "env must not be NULL");
+    if (n_rows) *n_rows = env->n_trunc;
+    if (halfsweeps) *halfsweeps = env->opts.halfsweeps;
+    if (omegas) std::memcpy(omegas, env->omegas.data(), sizeof(double) * env->omegas.size());
+  });
+}
+
+peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable) {
+  return guarded([&] {
+    PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    ctx->c->profile = enable != 0;
+    for (int i = 0; i < Ctx::NSTAT; ++i) {
+      ctx->c->st_flops[i] = 0.0;
+      ctx->c->st_ms[i] = 0.0;
+      ctx->c->st_launch[i] = 0;
+    }
+  });
+}
+
+peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && flops && ms && launches, "arguments must not be NULL");
+    for (int i = 0; i < Ctx::NSTAT; ++i) {
+      flops[i] = ctx->c->st_flops[i];
+      ms[i] = ctx->c->st_ms[i];
+      launches[i] = ctx->c->st_launch[i];
+    }
+  });
+}
+
+peps_status peps_ctx_set_workspace(peps_ctx* ctx, uint64_t bytes) {
+  return guarded([&] {
+    PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    PE_REQUIRE(bytes >= (uint64_t(1) << 20), "workspace budget below 1 MiB");
+    ctx->c->scratch_budget = bytes;
+  });
+}
+
+}  // extern "C"

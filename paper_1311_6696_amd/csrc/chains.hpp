@@ -1,0 +1,162 @@
+// Stage builders shared by the boundary, sandwich and cluster planners: each
+// appends the descriptors of one job to per-stage vectors (one grouped
+// launch per stage for a whole batch of jobs).
+#pragma once
+#include <algorithm>
+#include <cmath>
+
+#include "planner.hpp"
+
+namespace pe {
+
+constexpr int OP_ID = 0, OP_SZ = 1, OP_SP = 2, OP_SM = 3;
+// Heisenberg bond S.S = Sz Sz + (S+ S- + S- S+)/2: (weight, first, second)
+constexpr double BOND_W[3] = {1.0, 0.5, 0.5};
+constexpr int BOND_O1[3] = {OP_SZ, OP_SP, OP_SM};
+constexpr int BOND_O2[3] = {OP_SZ, OP_SM, OP_SP};
+
+inline int64_t prod(const std::vector<int64_t>& v) {
+  int64_t n = 1;
+  for (auto x : v) n *= x;
+  return n;
+}
+
+// Site view with labels "plurd"-like; flip swaps the up and down legs.
+inline TV site_tv(const Site& s, int op, bool flip, int dt, const std::string& lbl) {
+  TV v = dense(s.op[op], dt, lbl, {s.d, s.Dl, s.Du, s.Dr, s.Dd});
+  if (flip) {
+    std::swap(v.dim[2], v.dim[4]);
+    std::swap(v.str[2], v.str[4]);
+  }
+  return v;
+}
+
+inline double tc_flops(const TcDesc& d) { return 2.0 * d.M * (double)d.N * d.K; }
+
+// Per-stage descriptor lists of one batched chain; `flops` sums the
+// algorithmic flops of every descriptor pushed through add().
+struct St {
+  std::vector<std::vector<TcDesc>> s;
+  double flops = 0.0;
+  explicit St(int n) : s(n) {}
+  void add(int stage, const TcDesc& d) {
+    s[stage].push_back(d);
+    flops += tc_flops(d);
+  }
+  void record(Rec& rec, int prec, int cdt) {
+    for (auto& v : s) rec.tc(prec, cdt, v);
+  }
+};
+
+// Y3[x][d][g][r][s][e] = sum E[x][l][m][a] T[a][u][v][e] Ak[p][l][u][r][d] Ab[p][m][v][s][g]
+inline TV chain_left(St& st, const TV& E, const TV& T, const TV& Ak, const TV& Ab, void* P, void* Q, int dt) {
+  const int64_t X = E.dim[0], Dl = E.dim[1], Du = T.dim[1], Ee = T.dim[3];
+  const int64_t p = Ak.dim[0], Dr = Ak.dim[3], Dd = Ak.dim[4];
+  TV y1 = dense(P, dt, "xlmuve", {X, Dl, Dl, Du, Du, Ee});
+  st.add(0, tc_build(y1, E, T));
+  TV z = dense(Q, dt, "xdrpmve", {X, Dd, Dr, p, Dl, Du, Ee});
+  st.add(1, tc_build(z, y1, Ak));
+  TV y3 = dense(P, dt, "xdgrse", {X, Dd, Dd, Dr, Dr, Ee});
+  st.add(2, tc_build(y3, z, Ab));
+  return y3;
+}
+
+// Y3[y][d][g][l][m][a] = sum F[y][r][s][e] T[a][u][v][e] Ak[p][l][u][r][d] Ab[p][m][v][s][g]
+inline TV chain_right(St& st, const TV& F, const TV& T, const TV& Ak, const TV& Ab, void* P, void* Q, int dt) {
+  const int64_t Y = F.dim[0], Dr = F.dim[1], Du = T.dim[1], Aa = T.dim[0];
+  const int64_t p = Ak.dim[0], Dl = Ak.dim[1], Dd = Ak.dim[4];
+  TV y1 = dense(P, dt, "yrsuva", {Y, Dr, Dr, Du, Du, Aa});
+  st.add(0, tc_build(y1, F, T));
+  TV z = dense(Q, dt, "ydlpsva", {Y, Dd, Dl, p, Dr, Du, Aa});
+  st.add(1, tc_build(z, y1, Ak));
+  TV y3 = dense(P, dt, "ydglma", {Y, Dd, Dd, Dl, Dl, Aa});
+  st.add(2, tc_build(y3, z, Ab));
+  return y3;
+}
+
+inline int64_t chain_scratch_P(int64_t X, int64_t Dl, int64_t Du, int64_t Ee, int64_t Dr, int64_t Dd) {
+  return std::max(X * Dl * Dl * Du * Du * Ee, X * Dd * Dd * Dr * Dr * Ee);
+}
+
+// Two-row column transfer (rows 1 and 2 between T and B), left to right.
+inline TV chain2_left(St& st, const TV& L, const TV& T, const TV& A1k, const TV& A1b, const TV& A2k, const TV& A2b,
+               void* P, void* Q, int dt) {
+  const int64_t X = L.dim[0], D2l = L.dim[1], D1l = L.dim[3];
+  const int64_t Du = T.dim[1], Ee = T.dim[3];
+  const int64_t p1 = A1k.dim[0], Dr1 = A1k.dim[3], Dd1 = A1k.dim[4];
+  const int64_t p2 = A2k.dim[0], Dr2 = A2k.dim[3], Dd2 = A2k.dim[4];
+  TV y1 = dense(P, dt, "xLMlmuve", {X, D2l, D2l, D1l, D1l, Du, Du, Ee});
+  st.add(0, tc_build(y1, L, T));
+  TV z1 = dense(Q, dt, "xLMdrpmve", {X, D2l, D2l, Dd1, Dr1, p1, D1l, Du, Ee});
+  st.add(1, tc_build(z1, y1, A1k));
+  TV y2 = dense(P, dt, "xLMdgrse", {X, D2l, D2l, Dd1, Dd1, Dr1, Dr1, Ee});
+  st.add(2, tc_build(y2, z1, A1b));
+  TV z2 = dense(Q, dt, "xDRqMgrse", {X, Dd2, Dr2, p2, D2l, Dd1, Dr1, Dr1, Ee});
+  st.add(3, tc_build(z2, y2, A2k));
+  TV y3 = dense(P, dt, "xDGRSrse", {X, Dd2, Dd2, Dr2, Dr2, Dr1, Dr1, Ee});
+  st.add(4, tc_build(y3, z2, A2b));
+  return y3;
+}
+
+inline TV chain2_right(St& st, const TV& R, const TV& T, const TV& A1k, const TV& A1b, const TV& A2k, const TV& A2b,
+                void* P, void* Q, int dt) {
+  const int64_t Y = R.dim[0], Dr2 = R.dim[1], Dr1 = R.dim[3];
+  const int64_t Du = T.dim[1], Aa = T.dim[0];
+  const int64_t p1 = A1k.dim[0], Dl1 = A1k.dim[1], Dd1 = A1k.dim[4];
+  const int64_t p2 = A2k.dim[0], Dl2 = A2k.dim[1], Dd2 = A2k.dim[4];
+  TV y1 = dense(P, dt, "yRSrsuva", {Y, Dr2, Dr2, Dr1, Dr1, Du, Du, Aa});
+  st.add(0, tc_build(y1, R, T));
+  TV z1 = dense(Q, dt, "yRSdlpsva", {Y, Dr2, Dr2, Dd1, Dl1, p1, Dr1, Du, Aa});
+  st.add(1, tc_build(z1, y1, A1k));
+  TV y2 = dense(P, dt, "yRSdglma", {Y, Dr2, Dr2, Dd1, Dd1, Dl1, Dl1, Aa});
+  st.add(2, tc_build(y2, z1, A1b));
+  TV z2 = dense(Q, dt, "yDLqSglma", {Y, Dd2, Dl2, p2, Dr2, Dd1, Dl1, Dl1, Aa});
+  st.add(3, tc_build(z2, y2, A2k));
+  TV y3 = dense(P, dt, "yDGLMlma", {Y, Dd2, Dd2, Dl2, Dl2, Dl1, Dl1, Aa});
+  st.add(4, tc_build(y3, z2, A2b));
+  return y3;
+}
+
+inline EwDesc ew_desc(int kind, const void* src, int sdt, void* dst, int ddt, int64_t n) {
+  EwDesc e;
+  std::memset(&e, 0, sizeof(e));
+  e.kind = kind;
+  e.src = src;
+  e.src_dt = sdt;
+  e.dst = dst;
+  e.dst_dt = ddt;
+  e.n = n;
+  return e;
+}
+
+inline RedDesc red_desc(const void* x, const void* y, int64_t n, double* out, int dt) {
+  RedDesc r;
+  std::memset(&r, 0, sizeof(r));
+  r.x = x;
+  r.y = y;
+  r.n = n;
+  r.out = out;
+  r.dt = dt;
+  return r;
+}
+
+inline QrDesc qr_desc(const double* A, int64_t sAr, int64_t sAc, double* Q, int64_t sQr, int64_t sQc, double* R,
+               int64_t sRr, int64_t sRc, double* W, int m, int n) {
+  QrDesc q;
+  q.A = A;
+  q.sAr = sAr;
+  q.sAc = sAc;
+  q.Q = Q;
+  q.sQr = sQr;
+  q.sQc = sQc;
+  q.R = R;
+  q.sRr = sRr;
+  q.sRc = sRc;
+  q.W = W;
+  q.m = m;
+  q.n = n;
+  return q;
+}
+
+
+}  // namespace pe

@@ -1,0 +1,573 @@
+// Local expectation values from the sandwich (arXiv:1311.6696, Sec. 2):
+// each row is contracted between the top boundary above it and the bottom
+// boundary below it, giving <psi|psi>, <S^z> and horizontal bond energies;
+// vertical bonds come from the two-row sandwich between T_{r-1} and B_{r+2}.
+// Operators act on the ket layer; every ratio takes numerator and
+// denominator from the same sandwich.
+//
+// All rows of all environments run together: the left and right column
+// environments of every row advance in lockstep (one grouped launch per
+// stage), then all operator insertions of all rows form two more batched
+// levels, then every scalar is one reduction.
+#include <array>
+
+#include "chains.hpp"
+
+namespace pe {
+namespace {
+
+// groups of consecutive items whose scratch fits the budget (at least one each)
+std::vector<std::pair<size_t, size_t>> budget_groups(const std::vector<size_t>& sz, size_t budget) {
+  std::vector<std::pair<size_t, size_t>> g;
+  size_t i = 0;
+  while (i < sz.size()) {
+    size_t j = i, tot = 0;
+    while (j < sz.size() && (j == i || tot + sz[j] <= budget)) tot += sz[j++];
+    g.push_back({i, j});
+    i = j;
+  }
+  return g;
+}
+
+// One-row sandwich of row r (between T_{r-1} and B_{r+1}).
+struct RJob {
+  peps_env* e;
+  int r, Lc;
+  const Mps* T;
+  const Mps* B;
+  std::vector<const Site*> s;
+  std::vector<int64_t> bT, bB, Dl;
+  std::vector<void*> L, R;
+  double* nuL;   // Lc+1 squared norms of the raw left steps
+  double* nuR;
+  double* dots;  // D[0..Lc], sz nums [Lc], bond nums [3*(Lc-1)]
+};
+
+struct R2Job {
+  peps_env* e;
+  int r, Lc;
+  const Mps* T;
+  const Mps* B;
+  std::vector<const Site*> s1, s2;
+  std::vector<int64_t> bT, bB, Dl1, Dl2;
+  std::vector<void*> L, R;
+  double* nuL;
+  double* nuR;
+  double* dots;  // D[0..Lc], nums [3*Lc]
+};
+
+int64_t env_elems(const RJob& j, int c) { return j.bB[c] * j.Dl[c] * j.Dl[c] * j.bT[c]; }
+int64_t env2_elems(const R2Job& j, int c) {
+  return j.bB[c] * j.Dl2[c] * j.Dl2[c] * j.Dl1[c] * j.Dl1[c] * j.bT[c];
+}
+
+TV envv(const RJob& j, const void* p, int c, const char* lbl, int cdt) {
+  return dense(p, cdt, lbl, {j.bB[c], j.Dl[c], j.Dl[c], j.bT[c]});
+}
+TV env2v(const R2Job& j, const void* p, int c, const char* lbl, int cdt) {
+  return dense(p, cdt, lbl, {j.bB[c], j.Dl2[c], j.Dl2[c], j.Dl1[c], j.Dl1[c], j.bT[c]});
+}
+
+// scratch (elements) of one row step at column c: P and Q
+std::pair<int64_t, int64_t> step_scratch(const RJob& j, int c) {
+  const Site& s = *j.s[c];
+  const int64_t X = std::max(j.bB[c], j.bB[c + 1]), A = std::max(j.bT[c], j.bT[c + 1]);
+  const int64_t Dh = std::max(s.Dl, s.Dr), Dv = std::max(s.Du, s.Dd);
+  return {X * Dh * Dh * Dv * Dv * A, X * Dh * Dh * Dv * Dv * A * s.d};
+}
+std::pair<int64_t, int64_t> step2_scratch(const R2Job& j, int c) {
+  const Site& a = *j.s1[c];
+  const Site& b = *j.s2[c];
+  const int64_t X = std::max(j.bB[c], j.bB[c + 1]), A = std::max(j.bT[c], j.bT[c + 1]);
+  const int64_t h1 = std::max(a.Dl, a.Dr), h2 = std::max(b.Dl, b.Dr);
+  const int64_t v = std::max(std::max(a.Du, a.Dd), std::max(b.Du, b.Dd));
+  const int64_t P = X * h2 * h2 * h1 * h1 * v * v * A;
+  return {P, P * std::max(a.d, b.d)};
+}
+
+TV step_left(St& st, std::vector<TcDesc>& fin, const RJob& j, int c, const TV& Lin, int op, void* out, void* P,
+             void* Q, int cdt) {
+  const Site& s = *j.s[c];
+  TV T = dense(j.T->tc[c], cdt, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV y3 = chain_left(st, Lin, T, site_tv(s, op, false, cdt, "plurd"), site_tv(s, 0, false, cdt, "pmvsg"), P, Q, cdt);
+  TV B = dense(j.B->tc[c], cdt, "xdgy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  TV o = envv(j, out, c + 1, "yrse", cdt);
+  fin.push_back(tc_build(o, y3, B));
+  st.flops += tc_flops(fin.back());
+  return o;
+}
+
+TV step_right(St& st, std::vector<TcDesc>& fin, const RJob& j, int c, const TV& Rin, void* out, void* P, void* Q,
+              int cdt) {
+  const Site& s = *j.s[c];
+  TV T = dense(j.T->tc[c], cdt, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV y3 = chain_right(st, Rin, T, site_tv(s, 0, false, cdt, "plurd"), site_tv(s, 0, false, cdt, "pmvsg"), P, Q, cdt);
+  TV B = dense(j.B->tc[c], cdt, "xdgy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  TV o = envv(j, out, c, "xlma", cdt);
+  fin.push_back(tc_build(o, y3, B));
+  st.flops += tc_flops(fin.back());
+  return o;
+}
+
+TV step2_left(St& st, std::vector<TcDesc>& fin, const R2Job& j, int c, const TV& Lin, int op1, int op2, void* out,
+              void* P, void* Q, int cdt) {
+  const Site& a = *j.s1[c];
+  const Site& b = *j.s2[c];
+  TV T = dense(j.T->tc[c], cdt, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV y3 = chain2_left(st, Lin, T, site_tv(a, op1, false, cdt, "plurd"), site_tv(a, 0, false, cdt, "pmvsg"),
+                      site_tv(b, op2, false, cdt, "qLdRD"), site_tv(b, 0, false, cdt, "qMgSG"), P, Q, cdt);
+  TV B = dense(j.B->tc[c], cdt, "xDGy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  TV o = env2v(j, out, c + 1, "yRSrse", cdt);
+  fin.push_back(tc_build(o, y3, B));
+  st.flops += tc_flops(fin.back());
+  return o;
+}
+
+TV step2_right(St& st, std::vector<TcDesc>& fin, const R2Job& j, int c, const TV& Rin, void* out, void* P, void* Q,
+               int cdt) {
+  const Site& a = *j.s1[c];
+  const Site& b = *j.s2[c];
+  TV T = dense(j.T->tc[c], cdt, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV y3 = chain2_right(st, Rin, T, site_tv(a, 0, false, cdt, "plurd"), site_tv(a, 0, false, cdt, "pmvsg"),
+                       site_tv(b, 0, false, cdt, "qLdRD"), site_tv(b, 0, false, cdt, "qMgSG"), P, Q, cdt);
+  TV B = dense(j.B->tc[c], cdt, "xDGy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  TV o = env2v(j, out, c, "xLMlma", cdt);
+  fin.push_back(tc_build(o, y3, B));
+  st.flops += tc_flops(fin.back());
+  return o;
+}
+
+// Normalise the raw outputs in place: nu = |X|^2 into `slot`, X /= sqrt(nu).
+void normalise(Rec& rec, const std::vector<std::pair<TV, double*>>& outs) {
+  std::vector<RedDesc> rd;
+  std::vector<EwDesc> ew;
+  for (auto& o : outs) {
+    const int64_t n = o.first.size();
+    rd.push_back(red_desc(o.first.p, nullptr, n, o.second, o.first.dt));
+    EwDesc e = ew_desc(EW_RSQRT, o.first.p, o.first.dt, const_cast<void*>(o.first.p), o.first.dt, n);
+    e.sptr = o.second;
+    ew.push_back(e);
+  }
+  rec.reduce(rd);
+  rec.ew(ew);
+}
+
+}  // namespace
+
+void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>& out) {
+  Arena call(&ctx.pool);
+  Rec rec(&ctx);
+  Scratch scr(call);
+  std::vector<RJob> rj;
+  std::vector<R2Job> r2;
+  int dtype = envs.empty() ? 0 : envs[0]->opts.dtype;
+  for (peps_env* e : envs) PE_REQUIRE(e->opts.dtype == dtype, "one precision per expect call");
+  const Opts& o = envs[0]->opts;
+  const int prec = o.prec(), cdt = o.cdt();
+  const size_t esz = dtype_size(cdt);
+  const size_t budget = ctx.scratch_budget;
+
+  // ------------------------------------------------------------ jobs ----
+  for (peps_env* e : envs) {
+    const Lattice& L = e->lat;
+    const int Lr = L.Lr, Lc = L.Lc;
+    std::vector<int> rows;
+    if (e->window) {
+      rows.push_back(e->ci);
+    } else {
+      for (int r = 0; r < Lr; ++r) rows.push_back(r);
+    }
+    for (int r : rows) {
+      RJob j;
+      j.e = e;
+      j.r = r;
+      j.Lc = Lc;
+      j.T = &e->T(r - 1);
+      j.B = &e->B(r + 1);
+      for (int c = 0; c < Lc; ++c) j.s.push_back(&L.at(r, c));
+      for (int c = 0; c <= Lc; ++c) {
+        j.bT.push_back(j.T->bond[c]);
+        j.bB.push_back(j.B->bond[c]);
+        j.Dl.push_back(c < Lc ? L.at(r, c).Dl : L.at(r, Lc - 1).Dr);
+      }
+      j.L.assign(Lc + 1, nullptr);
+      j.R.assign(Lc + 1, nullptr);
+      j.L[0] = const_cast<void*>(L.lam[r]);
+      j.R[Lc] = const_cast<void*>(L.rho[r]);
+      for (int c = 1; c < Lc; ++c) {
+        j.L[c] = call.alloc(esz * env_elems(j, c));
+        j.R[c] = call.alloc(esz * env_elems(j, c));
+      }
+      if (Lc >= 1) {
+        j.L[Lc] = call.alloc(esz * env_elems(j, Lc));
+        j.R[0] = call.alloc(esz * env_elems(j, 0));
+      }
+      j.nuL = (double*)call.alloc(sizeof(double) * (Lc + 1));
+      j.nuR = (double*)call.alloc(sizeof(double) * (Lc + 1));
+      j.dots = (double*)call.alloc(sizeof(double) * (Lc + 1 + Lc + 3 * Lc));
+      rj.push_back(std::move(j));
+    }
+    std::vector<int> prs;
+    if (e->window) {
+      if (e->ci + 1 < Lr) prs.push_back(e->ci);
+    } else {
+      for (int r = 0; r + 1 < Lr; ++r) prs.push_back(r);
+    }
+    for (int r : prs) {
+      R2Job j;
+      j.e = e;
+      j.r = r;
+      j.Lc = Lc;
+      j.T = &e->T(r - 1);
+      j.B = &e->B(r + 2);
+      for (int c = 0; c < Lc; ++c) {
+        j.s1.push_back(&L.at(r, c));
+        j.s2.push_back(&L.at(r + 1, c));
+      }
+      for (int c = 0; c <= Lc; ++c) {
+        j.bT.push_back(j.T->bond[c]);
+        j.bB.push_back(j.B->bond[c]);
+        j.Dl1.push_back(c < Lc ? L.at(r, c).Dl : L.at(r, Lc - 1).Dr);
+        j.Dl2.push_back(c < Lc ? L.at(r + 1, c).Dl : L.at(r + 1, Lc - 1).Dr);
+      }
+      j.L.assign(Lc + 1, nullptr);
+      j.R.assign(Lc + 1, nullptr);
+      for (int c = 0; c <= Lc; ++c) {
+        j.L[c] = call.alloc(esz * env2_elems(j, c));
+        j.R[c] = call.alloc(esz * env2_elems(j, c));
+      }
+      j.nuL = (double*)call.alloc(sizeof(double) * (Lc + 1));
+      j.nuR = (double*)call.alloc(sizeof(double) * (Lc + 1));
+      j.dots = (double*)call.alloc(sizeof(double) * (Lc + 1 + 3 * Lc));
+      r2.push_back(std::move(j));
+    }
+  }
+
+  // two-row closings: outer products of the row closings
+  {
+    std::vector<TcDesc> op;
+    for (R2Job& j : r2) {
+      const Lattice& L = j.e->lat;
+      const int64_t a1 = j.Dl1[0], a2 = j.Dl2[0], b1 = j.Dl1[j.Lc], b2 = j.Dl2[j.Lc];
+      op.push_back(tc_build(env2v(j, j.L[0], 0, "xLMlma", cdt), dense(L.lam[j.r + 1], cdt, "LM", {a2, a2}),
+                            dense(L.lam[j.r], cdt, "lm", {a1, a1})));
+      op.push_back(tc_build(env2v(j, j.R[j.Lc], j.Lc, "xLMlma", cdt), dense(L.rho[j.r + 1], cdt, "LM", {b2, b2}),
+                            dense(L.rho[j.r], cdt, "lm", {b1, b1})));
+    }
+    rec.tc(prec, cdt, op, false);
+  }
+
+  // ------------------------------------- phase 1: column environments ----
+  {
+    struct Slot {
+      int kind;   // 0 one-row left, 1 one-row right, 2 two-row left, 3 two-row right
+      size_t job;
+    };
+    std::vector<Slot> slots;
+    std::vector<size_t> sz;
+    for (size_t i = 0; i < rj.size(); ++i)
+      for (int k = 0; k < 2; ++k) {
+        size_t m = 0;
+        for (int c = 0; c < rj[i].Lc; ++c) {
+          auto pq = step_scratch(rj[i], c);
+          m = std::max(m, (size_t)(pq.first + pq.second));
+        }
+        slots.push_back({k, i});
+        sz.push_back(m * esz);
+      }
+    for (size_t i = 0; i < r2.size(); ++i)
+      for (int k = 2; k < 4; ++k) {
+        size_t m = 0;
+        for (int c = 0; c < r2[i].Lc; ++c) {
+          auto pq = step2_scratch(r2[i], c);
+          m = std::max(m, (size_t)(pq.first + pq.second));
+        }
+        slots.push_back({k, i});
+        sz.push_back(m * esz);
+      }
+    for (auto g : budget_groups(sz, budget)) {
+      std::vector<void*> P(g.second - g.first), Q(g.second - g.first);
+      int maxLc = 0;
+      for (size_t i = g.first; i < g.second; ++i) {
+        const Slot& sl = slots[i];
+        int64_t p = 0, q = 0;
+        const int Lc = sl.kind < 2 ? rj[sl.job].Lc : r2[sl.job].Lc;
+        maxLc = std::max(maxLc, Lc);
+        for (int c = 0; c < Lc; ++c) {
+          auto pq = sl.kind < 2 ? step_scratch(rj[sl.job], c) : step2_scratch(r2[sl.job], c);
+          p = std::max(p, pq.first);
+          q = std::max(q, pq.second);
+        }
+        P[i - g.first] = scr.get(esz * p);
+        Q[i - g.first] = scr.get(esz * q);
+      }
+      for (int s = 0; s < maxLc; ++s) {
+        St st1(3), st2(5);
+        std::vector<TcDesc> fin;
+        std::vector<std::pair<TV, double*>> outs;
+        for (size_t i = g.first; i < g.second; ++i) {
+          const Slot& sl = slots[i];
+          void* p = P[i - g.first];
+          void* q = Q[i - g.first];
+          if (sl.kind < 2) {
+            RJob& j = rj[sl.job];
+            if (s >= j.Lc) continue;
+            const double f0 = st1.flops;
+            if (sl.kind == 0) {
+              const int c = s;
+              TV o = step_left(st1, fin, j, c, envv(j, j.L[c], c, "xlma", cdt), 0, j.L[c + 1], p, q, cdt);
+              outs.push_back({o, j.nuL + c + 1});
+            } else {
+              const int c = j.Lc - 1 - s;
+              TV o = step_right(st1, fin, j, c, envv(j, j.R[c + 1], c + 1, "yrse", cdt), j.R[c], p, q, cdt);
+              outs.push_back({o, j.nuR + c});
+            }
+            j.e->flops += st1.flops - f0;
+          } else {
+            R2Job& j = r2[sl.job];
+            if (s >= j.Lc) continue;
+            const double f0 = st2.flops;
+            if (sl.kind == 2) {
+              const int c = s;
+              TV o = step2_left(st2, fin, j, c, env2v(j, j.L[c], c, "xLMlma", cdt), 0, 0, j.L[c + 1], p, q, cdt);
+              outs.push_back({o, j.nuL + c + 1});
+            } else {
+              const int c = j.Lc - 1 - s;
+              TV o = step2_right(st2, fin, j, c, env2v(j, j.R[c + 1], c + 1, "yRSrse", cdt), j.R[c], p, q, cdt);
+              outs.push_back({o, j.nuR + c});
+            }
+            j.e->flops += st2.flops - f0;
+          }
+        }
+        st1.record(rec, prec, cdt);
+        st2.record(rec, prec, cdt);
+        rec.tc(prec, cdt, fin);
+        normalise(rec, outs);
+      }
+      for (void* p : P) scr.put(p);
+      for (void* q : Q) scr.put(q);
+    }
+  }
+
+  // ------------------------------------ phase 2: operator insertions ----
+  // one-row: X1[c][op] (op Sz for every c, S+/S- for c < Lc-1), then X2[c][t]
+  std::vector<std::vector<std::array<void*, 4>>> X1(rj.size());
+  std::vector<std::vector<std::array<void*, 3>>> X2(rj.size());
+  std::vector<std::vector<std::array<void*, 3>>> Y2(r2.size());
+  {
+    struct Item {
+      int level;   // 0: X1, 1: X2, 2: two-row
+      size_t job;
+      int c, t;
+    };
+    for (int level = 0; level < 3; ++level) {
+      std::vector<Item> items;
+      std::vector<size_t> sz;
+      if (level < 2) {
+        for (size_t i = 0; i < rj.size(); ++i) {
+          RJob& j = rj[i];
+          if (level == 0) X1[i].assign(j.Lc, {nullptr, nullptr, nullptr, nullptr});
+          else X2[i].assign(j.Lc, {nullptr, nullptr, nullptr});
+          for (int c = 0; c < j.Lc; ++c) {
+            if (level == 0) {
+              for (int op = OP_SZ; op <= OP_SM; ++op) {
+                if (op != OP_SZ && c + 1 >= j.Lc) continue;
+                if (j.e->window && c != j.e->cj) continue;
+                X1[i][c][op] = call.alloc(esz * env_elems(j, c + 1));
+                items.push_back({0, i, c, op});
+                auto pq = step_scratch(j, c);
+                sz.push_back(esz * (pq.first + pq.second));
+              }
+            } else {
+              if (c + 1 >= j.Lc) continue;
+              if (j.e->window && c != j.e->cj) continue;
+              for (int t = 0; t < 3; ++t) {
+                X2[i][c][t] = call.alloc(esz * env_elems(j, c + 2));
+                items.push_back({1, i, c, t});
+                auto pq = step_scratch(j, c + 1);
+                sz.push_back(esz * (pq.first + pq.second));
+              }
+            }
+          }
+        }
+      } else {
+        for (size_t i = 0; i < r2.size(); ++i) {
+          R2Job& j = r2[i];
+          Y2[i].assign(j.Lc, {nullptr, nullptr, nullptr});
+          for (int c = 0; c < j.Lc; ++c) {
+            if (j.e->window && c != j.e->cj) continue;
+            for (int t = 0; t < 3; ++t) {
+              Y2[i][c][t] = call.alloc(esz * env2_elems(j, c + 1));
+              items.push_back({2, i, c, t});
+              auto pq = step2_scratch(j, c);
+              sz.push_back(esz * (pq.first + pq.second));
+            }
+          }
+        }
+      }
+      for (auto g : budget_groups(sz, budget)) {
+        St st1(3), st2(5);
+        std::vector<TcDesc> fin;
+        std::vector<void*> tmp;
+        for (size_t k = g.first; k < g.second; ++k) {
+          const Item& it = items[k];
+          if (it.level < 2) {
+            RJob& j = rj[it.job];
+            auto pq = step_scratch(j, it.level == 0 ? it.c : it.c + 1);
+            void* p = scr.get(esz * pq.first);
+            void* q = scr.get(esz * pq.second);
+            tmp.push_back(p);
+            tmp.push_back(q);
+            const double f0 = st1.flops;
+            if (it.level == 0) {
+              step_left(st1, fin, j, it.c, envv(j, j.L[it.c], it.c, "xlma", cdt), it.t, X1[it.job][it.c][it.t], p, q, cdt);
+            } else {
+              const int o1 = BOND_O1[it.t], o2 = BOND_O2[it.t];
+              step_left(st1, fin, j, it.c + 1, envv(j, X1[it.job][it.c][o1], it.c + 1, "xlma", cdt), o2,
+                        X2[it.job][it.c][it.t], p, q, cdt);
+            }
+            j.e->flops += st1.flops - f0;
+          } else {
+            R2Job& j = r2[it.job];
+            auto pq = step2_scratch(j, it.c);
+            void* p = scr.get(esz * pq.first);
+            void* q = scr.get(esz * pq.second);
+            tmp.push_back(p);
+            tmp.push_back(q);
+            const double f0 = st2.flops;
+            step2_left(st2, fin, j, it.c, env2v(j, j.L[it.c], it.c, "xLMlma", cdt), BOND_O1[it.t], BOND_O2[it.t],
+                       Y2[it.job][it.c][it.t], p, q, cdt);
+            j.e->flops += st2.flops - f0;
+          }
+        }
+        st1.record(rec, prec, cdt);
+        st2.record(rec, prec, cdt);
+        rec.tc(prec, cdt, fin);
+        for (void* p : tmp) scr.put(p);
+      }
+    }
+  }
+
+  // ------------------------------------------------- phase 3: scalars ----
+  {
+    std::vector<RedDesc> rd;
+    for (size_t i = 0; i < rj.size(); ++i) {
+      RJob& j = rj[i];
+      const int Lc = j.Lc;
+      for (int c = 0; c <= Lc; ++c)
+        rd.push_back(red_desc(j.L[c], j.R[c], env_elems(j, c), j.dots + c, cdt));
+      for (int c = 0; c < Lc; ++c)
+        if (X1[i][c][OP_SZ])
+          rd.push_back(red_desc(X1[i][c][OP_SZ], j.R[c + 1], env_elems(j, c + 1), j.dots + Lc + 1 + c, cdt));
+      for (int c = 0; c + 1 < Lc; ++c)
+        for (int t = 0; t < 3; ++t)
+          if (X2[i][c][t])
+            rd.push_back(red_desc(X2[i][c][t], j.R[c + 2], env_elems(j, c + 2), j.dots + 2 * Lc + 1 + 3 * c + t, cdt));
+    }
+    for (size_t i = 0; i < r2.size(); ++i) {
+      R2Job& j = r2[i];
+      const int Lc = j.Lc;
+      for (int c = 0; c <= Lc; ++c)
+        rd.push_back(red_desc(j.L[c], j.R[c], env2_elems(j, c), j.dots + c, cdt));
+      for (int c = 0; c < Lc; ++c)
+        for (int t = 0; t < 3; ++t)
+          if (Y2[i][c][t])
+            rd.push_back(red_desc(Y2[i][c][t], j.R[c + 1], env2_elems(j, c + 1), j.dots + Lc + 1 + 3 * c + t, cdt));
+    }
+    rec.reduce(rd);
+  }
+  rec.run(call);
+
+  // ------------------------------------------------- host arithmetic ----
+  out.assign(envs.size(), ExpectOut());
+  std::unordered_map<peps_env*, size_t> pos;
+  for (size_t i = 0; i < envs.size(); ++i) {
+    pos[envs[i]] = i;
+    const Lattice& L = envs[i]->lat;
+    ExpectOut& eo = out[i];
+    if (envs[i]->window) {
+      eo.sz.assign(1, NAN);
+      eo.bond.assign(2, NAN);
+    } else {
+      eo.sz.assign((size_t)L.Lr * L.Lc, NAN);
+      eo.bond.assign((size_t)L.Lr * (L.Lc - 1) + (size_t)(L.Lr - 1) * L.Lc, NAN);
+    }
+    eo.log_norm = NAN;
+  }
+  auto fetch = [&](const double* d, size_t n) {
+    std::vector<double> h(n);
+    dev::d2h(h.data(), d, n * sizeof(double), ctx.stream);
+    return h;
+  };
+  std::vector<std::vector<double>> hdots(rj.size()), hnuL(rj.size()), hnuR(rj.size());
+  std::vector<std::vector<double>> h2dots(r2.size()), h2nuL(r2.size());
+  for (size_t i = 0; i < rj.size(); ++i) {
+    const int Lc = rj[i].Lc;
+    hdots[i] = fetch(rj[i].dots, Lc + 1 + Lc + 3 * Lc);
+    hnuL[i] = fetch(rj[i].nuL, Lc + 1);
+    hnuR[i] = fetch(rj[i].nuR, Lc + 1);
+  }
+  for (size_t i = 0; i < r2.size(); ++i) {
+    const int Lc = r2[i].Lc;
+    h2dots[i] = fetch(r2[i].dots, Lc + 1 + 3 * Lc);
+    h2nuL[i] = fetch(r2[i].nuL, Lc + 1);
+  }
+  dev::sync(ctx.stream);
+  for (size_t i = 0; i < rj.size(); ++i) {
+    const RJob& j = rj[i];
+    peps_env* e = j.e;
+    ExpectOut& eo = out[pos[e]];
+    const int Lc = j.Lc, Lr = e->lat.Lr;
+    const std::vector<double>& D = hdots[i];
+    const std::vector<double>& nu = hnuL[i];
+    for (int c = 0; c < Lc; ++c) {
+      if (!X1[i][c][OP_SZ]) continue;
+      const double v = D[Lc + 1 + c] / (std::sqrt(nu[c + 1]) * D[c + 1]);
+      if (e->window) {
+        if (c == e->cj && j.r == e->ci) eo.sz[0] = v;
+      } else {
+        eo.sz[(size_t)j.r * Lc + c] = v;
+      }
+    }
+    for (int c = 0; c + 1 < Lc; ++c) {
+      if (!X2[i][c][0]) continue;
+      double num = 0.0;
+      for (int t = 0; t < 3; ++t) num += BOND_W[t] * D[2 * Lc + 1 + 3 * c + t];
+      const double v = num / (std::sqrt(nu[c + 1] * nu[c + 2]) * D[c + 2]);
+      if (e->window) {
+        if (c == e->cj && j.r == e->ci) eo.bond[0] = v;
+      } else {
+        eo.bond[(size_t)j.r * (Lc - 1) + c] = v;
+      }
+    }
+    if (j.r == Lr / 2) {
+      const int cc = Lc / 2;
+      double lg = e->Tlog(j.r - 1) + e->Blog(j.r + 1) + std::log(std::fabs(D[cc]));
+      for (int k = 1; k <= cc; ++k) lg += 0.5 * std::log(nu[k]);
+      for (int k = cc; k < Lc; ++k) lg += 0.5 * std::log(hnuR[i][k]);
+      eo.log_norm = lg;
+      eo.sign = D[cc] < 0 ? -1.0 : 1.0;
+    }
+  }
+  for (size_t i = 0; i < r2.size(); ++i) {
+    const R2Job& j = r2[i];
+    peps_env* e = j.e;
+    ExpectOut& eo = out[pos[e]];
+    const int Lc = j.Lc;
+    const std::vector<double>& D = h2dots[i];
+    const std::vector<double>& nu = h2nuL[i];
+    for (int c = 0; c < Lc; ++c) {
+      if (!Y2[i][c][0]) continue;
+      double num = 0.0;
+      for (int t = 0; t < 3; ++t) num += BOND_W[t] * D[Lc + 1 + 3 * c + t];
+      const double v = num / (std::sqrt(nu[c + 1]) * D[c + 1]);
+      if (e->window) {
+        if (c == e->cj && j.r == e->ci) eo.bond[1] = v;
+      } else {
+        eo.bond[(size_t)e->lat.Lr * (Lc - 1) + (size_t)j.r * Lc + c] = v;
+      }
+    }
+  }
+}
+
+}  // namespace pe

@@ -1,0 +1,706 @@
+// Device kernels of libpepsenv (gfx950 / CDNA4).
+#include "kernels.hpp"
+
+namespace pe {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup; every thread receives the same value.
+__device__ inline double block_sum256(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// ===========================================================================
+// Tensor contraction on MFMA.  The 16x16 MFMA tile is issued as D = B^T A^T
+// so that lane bits 0..3 index m: stores are then contiguous along m, which
+// is the unit-stride index of every large intermediate of the chains.
+// Accumulator element r of lane l holds (m = l & 15, n = row(l, r)).
+// ===========================================================================
+struct PolF64 {
+  using T = double;
+  using L = double;
+  using F = double;
+  using Acc = d4_t;
+  static constexpr int KT = 16, KS = 4;
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  template <int LD>
+  __device__ static inline F frag(const L (*X)[LD], int ks, int cb, int lane) {
+    return X[ks * 4 + (lane >> 4)][cb + (lane & 15)];
+  }
+  __device__ static inline Acc mma(F b, F a, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+  }
+};
+
+struct PolF32 {
+  using T = float;
+  using L = float;
+  using F = float;
+  using Acc = f4_t;
+  static constexpr int KT = 16, KS = 4;
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  template <int LD>
+  __device__ static inline F frag(const L (*X)[LD], int ks, int cb, int lane) {
+    return X[ks * 4 + (lane >> 4)][cb + (lane & 15)];
+  }
+  __device__ static inline Acc mma(F b, F a, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+  }
+};
+
+struct PolBF16 {
+  using T = float;   // operands are stored as float32 and rounded to bf16 (RNE) on the way to LDS
+  using L = __bf16;
+  using F = bf8_t;
+  using Acc = f4_t;
+  static constexpr int KT = 32, KS = 32;
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  template <int LD>
+  __device__ static inline F frag(const L (*X)[LD], int ks, int cb, int lane) {
+    F f;
+    const int k0 = ks * 32 + 8 * (lane >> 4), c = cb + (lane & 15);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = X[k0 + e][c];
+    return f;
+  }
+  __device__ static inline Acc mma(F b, F a, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__device__ inline T ld_zero() { return T(0); }
+
+template <class P, class TC, int MT, int NT, int WM, int WN>
+__global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, int nd) {
+  using T = typename P::T;
+  using L = typename P::L;
+  constexpr int KT = P::KT;
+  constexpr int WTM = MT / WM, WTN = NT / WN, MB = WTM / 16, NB = WTN / 16;
+  constexpr int EA = MT * KT / 256, EB = NT * KT / 256;
+  static_assert(EA >= 1 && EB >= 1 && MB >= 1 && NB >= 1, "tile");
+  __shared__ L As[KT][MT + 2];
+  __shared__ L Bs[KT][NT + 2];
+  __shared__ int64_t oAm[MT], oCm[MT], oBn[NT], oCn[NT], oAk[KT], oBk[KT];
+
+  const int tid = threadIdx.x;
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
+  }
+  const TcDesc& d = ds[lo];
+  const int M = d.M, N = d.N, K = d.K;
+  const int t = bid - d.tile_base;
+  const int m0 = (t / d.tiles_n) * MT, n0 = (t % d.tiles_n) * NT;
+  const T* __restrict__ A = (const T*)d.A;
+  const T* __restrict__ B = (const T*)d.B;
+  TC* __restrict__ C = (TC*)d.C;
+  const int a_kfast = d.a_kfast, b_kfast = d.b_kfast;
+
+  for (int i = tid; i < MT; i += 256) {
+    int m = m0 + i;
+    int64_t oa = 0, oc = 0;
+    if (m < M) {
+      for (int j = d.nm - 1; j >= 0; --j) {
+        const int dj = d.dm[j];
+        const int x = m % dj;
+        m /= dj;
+        oa += (int64_t)x * d.sAm[j];
+        oc += (int64_t)x * d.sCm[j];
+      }
+    }
+    oAm[i] = oa;
+    oCm[i] = oc;
+  }
+  for (int i = tid; i < NT; i += 256) {
+    int n = n0 + i;
+    int64_t ob = 0, oc = 0;
+    if (n < N) {
+      for (int j = d.nn - 1; j >= 0; --j) {
+        const int dj = d.dn[j];
+        const int x = n % dj;
+        n /= dj;
+        ob += (int64_t)x * d.sBn[j];
+        oc += (int64_t)x * d.sCn[j];
+      }
+    }
+    oBn[i] = ob;
+    oCn[i] = oc;
+  }
+  auto k_offsets = [&](int kc) {
+    if (tid < KT) {
+      int k = kc * KT + tid;
+      int64_t oa = 0, ob = 0;
+      if (k < K) {
+        for (int j = d.nk - 1; j >= 0; --j) {
+          const int dj = d.dk[j];
+          const int x = k % dj;
+          k /= dj;
+          oa += (int64_t)x * d.sAk[j];
+          ob += (int64_t)x * d.sBk[j];
+        }
+      }
+      oAk[tid] = oa;
+      oBk[tid] = ob;
+    }
+  };
+  k_offsets(0);
+  __syncthreads();
+
+  T ra[EA], rb[EB];
+  auto load = [&](int kc) {
+    const int k0 = kc * KT;
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      if (a_kfast) { kk = tid % KT; mm = tid / KT + e * (256 / KT); }
+      else { mm = tid % MT; kk = tid / MT + e * (256 / MT); }
+      const bool ok = (m0 + mm < M) && (k0 + kk < K);
+      ra[e] = ok ? A[oAm[mm] + oAk[kk]] : ld_zero<T>();
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      if (b_kfast) { kk = tid % KT; nn = tid / KT + e * (256 / KT); }
+      else { nn = tid % NT; kk = tid / NT + e * (256 / NT); }
+      const bool ok = (n0 + nn < N) && (k0 + kk < K);
+      rb[e] = ok ? B[oBn[nn] + oBk[kk]] : ld_zero<T>();
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      if (a_kfast) { kk = tid % KT; mm = tid / KT + e * (256 / KT); }
+      else { mm = tid % MT; kk = tid / MT + e * (256 / MT); }
+      As[kk][mm] = (L)ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      if (b_kfast) { kk = tid % KT; nn = tid / KT + e * (256 / KT); }
+      else { nn = tid % NT; kk = tid / NT + e * (256 / NT); }
+      Bs[kk][nn] = (L)rb[e];
+    }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave % WM, wn = wave / WM;
+  typename P::Acc acc[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  const int nchunks = (K + KT - 1) / KT;
+  load(0);
+  for (int kc = 0; kc < nchunks; ++kc) {
+    __syncthreads();
+    store();
+    if (kc + 1 < nchunks) k_offsets(kc + 1);
+    __syncthreads();
+    if (kc + 1 < nchunks) load(kc + 1);
+#pragma unroll
+    for (int ks = 0; ks < KT / P::KS; ++ks) {
+      typename P::F af[MB], bf[NB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) af[i] = P::template frag<MT + 2>(As, ks, wm * WTM + i * 16, lane);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bf[j] = P::template frag<NT + 2>(Bs, ks, wn * WTN + j * 16, lane);
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = P::mma(bf[j], af[i], acc[i][j]);
+    }
+  }
+
+  const double alpha = d.alpha, beta = d.beta;
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ml = wm * WTM + i * 16 + (lane & 15);
+        const int nl = wn * WTN + j * 16 + P::row(lane, r);
+        if (m0 + ml < M && n0 + nl < N) {
+          const int64_t off = oCm[ml] + oCn[nl];
+          double v = alpha * (double)acc[i][j][r];
+          if (beta != 0.0) v += beta * (double)C[off];
+          C[off] = (TC)v;
+        }
+      }
+}
+
+template <class P, class TC>
+static void launch_tc_tile(int tile, const TcDesc* d, int nd, int nt, hipStream_t s) {
+  switch (tile) {
+    case TT_64x64: tc_kernel<P, TC, 64, 64, 2, 2><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_128x32: tc_kernel<P, TC, 128, 32, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_256x16: tc_kernel<P, TC, 256, 16, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_32x128: tc_kernel<P, TC, 32, 128, 1, 4><<<nt, 256, 0, s>>>(d, nd); break;
+    default: throw Error(ST_INVALID, "bad tile");
+  }
+}
+
+void launch_tc(int prec, int out_dt, int tile, const TcDesc* d, int nd, int nt, hipStream_t s) {
+  if (nt <= 0) return;
+  if (prec == TP_F64) {
+    if (out_dt != DT_F64) throw Error(ST_INVALID, "f64 contraction writes f64");
+    launch_tc_tile<PolF64, double>(tile, d, nd, nt, s);
+  } else if (prec == TP_F32) {
+    if (out_dt == DT_F64) launch_tc_tile<PolF32, double>(tile, d, nd, nt, s);
+    else launch_tc_tile<PolF32, float>(tile, d, nd, nt, s);
+  } else {
+    if (out_dt == DT_F64) launch_tc_tile<PolBF16, double>(tile, d, nd, nt, s);
+    else launch_tc_tile<PolBF16, float>(tile, d, nd, nt, s);
+  }
+  PE_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Householder QR (one workgroup of 256 threads per matrix).
+// ===========================================================================
+constexpr int QR_MAXN = 1024;
+
+__global__ __launch_bounds__(256) void qr_kernel(const QrDesc* __restrict__ ds) {
+  const QrDesc& d = ds[blockIdx.x];
+  const int m = d.m, n = d.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* __restrict__ W = d.W;                     // m x n column-major: v's and R
+  double* __restrict__ V = d.W + (int64_t)m * n;    // m x n column-major: Q
+  __shared__ double taus[QR_MAXN], rdiag[QR_MAXN], red[4];
+  const int64_t mn = (int64_t)m * n;
+
+  for (int64_t idx = tid; idx < mn; idx += 256) {
+    const int j = (int)(idx / m), i = (int)(idx % m);
+    W[idx] = d.A[i * d.sAr + j * d.sAc];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double* wj = W + (int64_t)j * m;
+    double s = 0.0;
+    for (int i = j + tid; i < m; i += 256) s += wj[i] * wj[i];
+    s = block_sum256(s, red);
+    const double x0 = wj[j];
+    const double nrm = sqrt(s);
+    double beta = 0.0, tau = 0.0, scal = 0.0;
+    if (nrm > 0.0) {
+      beta = -copysign(nrm, x0);
+      tau = (beta - x0) / beta;
+      scal = 1.0 / (x0 - beta);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < m; i += 256) wj[i] *= scal;
+    if (tid == 0) { taus[j] = tau; rdiag[j] = beta; }
+    __syncthreads();
+    for (int k = j + 1 + wave; k < n; k += 4) {
+      double* wk = W + (int64_t)k * m;
+      double w = 0.0;
+      for (int i = j + lane; i < m; i += 64) w += (i == j ? 1.0 : wj[i]) * wk[i];
+      w = wave_sum(w) * tau;
+      for (int i = j + lane; i < m; i += 64) wk[i] -= (i == j ? 1.0 : wj[i]) * w;
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < mn; idx += 256) {
+    const int j = (int)(idx / m), i = (int)(idx % m);
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    const double* wj = W + (int64_t)j * m;
+    const double tau = taus[j];
+    for (int k = j + wave; k < n; k += 4) {
+      double* vk = V + (int64_t)k * m;
+      double w = 0.0;
+      for (int i = j + lane; i < m; i += 64) w += (i == j ? 1.0 : wj[i]) * vk[i];
+      w = wave_sum(w) * tau;
+      for (int i = j + lane; i < m; i += 64) vk[i] -= (i == j ? 1.0 : wj[i]) * w;
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < mn; idx += 256) {
+    const int j = (int)(idx / m), i = (int)(idx % m);
+    const double sg = rdiag[j] < 0.0 ? -1.0 : 1.0;
+    d.Q[i * d.sQr + j * d.sQc] = sg * V[idx];
+  }
+  if (d.R) {
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int j = idx / n, i = idx % n;
+      const double sg = rdiag[i] < 0.0 ? -1.0 : 1.0;
+      const double v = i < j ? W[(int64_t)j * m + i] : (i == j ? rdiag[i] : 0.0);
+      d.R[i * d.sRr + j * d.sRc] = sg * v;
+    }
+  }
+}
+
+void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  qr_kernel<<<nd, 256, 0, s>>>(d);
+  PE_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Two-pass deterministic reductions.
+// ===========================================================================
+template <class T>
+__device__ inline double ldv(const void* p, int64_t i) { return (double)((const T*)p)[i]; }
+
+__global__ __launch_bounds__(256) void red1_kernel(const RedDesc* __restrict__ ds, int nd, double* partials) {
+  __shared__ double red[4];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= bid) lo = mid; else hi = mid - 1;
+  }
+  const RedDesc& d = ds[lo];
+  const int b = bid - d.block_base;
+  const int64_t chunk = (d.n + d.nblocks - 1) / d.nblocks;
+  const int64_t i0 = b * chunk, i1 = min(d.n, i0 + chunk);
+  double s = 0.0;
+  if (d.dt == DT_F64) {
+    if (d.y) for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += ldv<double>(d.x, i) * ldv<double>(d.y, i);
+    else for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) { const double v = ldv<double>(d.x, i); s += v * v; }
+  } else {
+    if (d.y) for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += ldv<float>(d.x, i) * ldv<float>(d.y, i);
+    else for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) { const double v = ldv<float>(d.x, i); s += v * v; }
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) partials[d.part_base + b] = s;
+}
+
+__global__ void red2_kernel(const RedDesc* __restrict__ ds, const double* __restrict__ partials) {
+  const RedDesc& d = ds[blockIdx.x];
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < d.nblocks; ++b) s += partials[d.part_base + b];
+    *d.out = s;
+  }
+}
+
+void launch_reduce(const RedDesc* d, int nd, int nb, double* partials, hipStream_t s) {
+  if (nd <= 0) return;
+  red1_kernel<<<nb, 256, 0, s>>>(d, nd, partials);
+  red2_kernel<<<nd, 64, 0, s>>>(d, partials);
+  PE_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Elementwise kernels.
+// ===========================================================================
+__device__ inline double ew_load(const void* p, int dt, int64_t i) {
+  return dt == DT_F64 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+}
+__device__ inline void ew_store(void* p, int dt, int64_t i, double v) {
+  if (dt == DT_F64) ((double*)p)[i] = v; else ((float*)p)[i] = (float)v;
+}
+
+__global__ __launch_bounds__(256) void ew_kernel(const EwDesc* __restrict__ ds, int nd) {
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= bid) lo = mid; else hi = mid - 1;
+  }
+  const EwDesc& d = ds[lo];
+  const int64_t stride = (int64_t)d.nblocks * 256;
+  const int64_t n = d.n;
+  for (int64_t i = (int64_t)(bid - d.block_base) * 256 + threadIdx.x; i < n; i += stride) {
+    double v;
+    switch (d.kind) {
+      case EW_COPY: v = ew_load(d.src, d.src_dt, i); break;
+      case EW_PHYS: {
+        const int64_t Lh = n / 2, j = i % Lh;
+        const int p = (int)(i / Lh);
+        v = d.op[2 * p] * ew_load(d.src, d.src_dt, j) + d.op[2 * p + 1] * ew_load(d.src, d.src_dt, Lh + j);
+        break;
+      }
+      case EW_FILL: v = d.a; break;
+      case EW_SPLITMIX: {
+        const uint64_t x = splitmix_mix(d.key + (uint64_t)(i + 1) * SPLITMIX_GAMMA);
+        v = (double)(x >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+        break;
+      }
+      case EW_RSQRT: v = ew_load(d.src, d.src_dt, i) / sqrt(*d.sptr); break;
+      case EW_IDENTITY: v = (i / d.dim == i % d.dim) ? d.a : 0.0; break;
+      default: v = 0.0;
+    }
+    ew_store(d.dst, d.dst_dt, i, v);
+  }
+}
+
+void launch_ew(const EwDesc* d, int nd, int nb, hipStream_t s) {
+  if (nd <= 0) return;
+  ew_kernel<<<nb, 256, 0, s>>>(d, nd);
+  PE_HIP(hipGetLastError());
+}
+
+
+// ===========================================================================
+// CU_0 separable boundaries (one workgroup per lattice direction).
+// ===========================================================================
+namespace {
+
+constexpr int SEP_V = SEP_MAXD * SEP_MAXD;            // one D x D matrix slot
+constexpr int SEP_W = 2 * SEP_V * SEP_V;               // d * D^4 with d <= 2
+
+__device__ inline double sepA(const SepSite& s, int p, int l, int u, int r, int d) {
+  return s.A[p * s.sp + l * s.sl + u * s.su + r * s.sr + d * s.sd];
+}
+
+// Scale x[0..n) to unit Frobenius norm (every thread of the block calls this).
+__device__ void sep_unit(double* x, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += x[i] * x[i];
+  s = block_sum256(s, red);
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) x[i] *= inv;
+  __syncthreads();
+}
+
+// W1[p][m][u][r][d] = sum_l e[l][m] A[p,l,u,r,d];  W2[p][m][v][r][d] = sum_u W1 su[u][v]
+__device__ void sep_left_half(const SepSite& s, const double* e, const double* su, double* W1, double* W2) {
+  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
+  const int n = P * Dl * Du * Dr * Dd;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int r = t % Dr; t /= Dr;
+    const int u = t % Du; t /= Du;
+    const int m = t % Dl; t /= Dl;
+    const int p = t;
+    double acc = 0.0;
+    for (int l = 0; l < Dl; ++l) acc += e[l * Dl + m] * sepA(s, p, l, u, r, d);
+    W1[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int r = t % Dr; t /= Dr;
+    const int v = t % Du; t /= Du;
+    const int pm = t;   // p*Dl + m
+    double acc = 0.0;
+    for (int u = 0; u < Du; ++u) acc += W1[((pm * Du + u) * Dr + r) * Dd + d] * su[u * Du + v];
+    W2[i] = acc;
+  }
+  __syncthreads();
+}
+
+// b[d][g] = sum e[l][m] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] f[r][s]
+__device__ void sep_b(const SepSite& s, const double* e, const double* su, const double* f, double* W1, double* W2,
+                      double* out) {
+  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
+  sep_left_half(s, e, su, W1, W2);
+  const int n = P * Dl * Du * Dr * Dd;
+  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][m][v][s][d] = sum_r W2[p][m][v][r][d] f[r][s]
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int ss = t % Dr; t /= Dr;
+    const int pmv = t;
+    double acc = 0.0;
+    for (int r = 0; r < Dr; ++r) acc += W2[(pmv * Dr + r) * Dd + d] * f[r * Dr + ss];
+    W1[i] = acc;
+  }
+  __syncthreads();
+  const int K = P * Dl * Du * Dr;
+  for (int o = threadIdx.x; o < Dd * Dd; o += 256) {
+    const int d = o / Dd, g = o % Dd;
+    double acc = 0.0;
+    for (int q = 0; q < K; ++q) {
+      int t = q;
+      const int ss = t % Dr; t /= Dr;
+      const int v = t % Du; t /= Du;
+      const int m = t % Dl; t /= Dl;
+      const int p = t;
+      acc += W1[q * Dd + d] * sepA(s, p, m, v, ss, g);
+    }
+    out[o] = acc;
+  }
+  __syncthreads();
+}
+
+// e'[r][s] = sum e[l][m] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] sig[d][g]
+__device__ void sep_eupd(const SepSite& s, const double* e, const double* su, const double* sg, double* W1,
+                         double* W2, double* out) {
+  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
+  sep_left_half(s, e, su, W1, W2);
+  const int n = P * Dl * Du * Dr * Dd;
+  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][m][v][r][g] = sum_d W2[p][m][v][r][d] sg[d][g]
+    const int g = i % Dd, base = i - g;
+    double acc = 0.0;
+    for (int d = 0; d < Dd; ++d) acc += W2[base + d] * sg[d * Dd + g];
+    W1[i] = acc;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < Dr * Dr; o += 256) {
+    const int r = o / Dr, ss = o % Dr;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p)
+      for (int m = 0; m < Dl; ++m)
+        for (int v = 0; v < Du; ++v)
+          for (int g = 0; g < Dd; ++g)
+            acc += W1[(((p * Dl + m) * Du + v) * Dr + r) * Dd + g] * sepA(s, p, m, v, ss, g);
+    out[o] = acc;
+  }
+  __syncthreads();
+}
+
+// f'[l][m] = sum f[r][s] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] sig[d][g]
+__device__ void sep_fupd(const SepSite& s, const double* f, const double* su, const double* sg, double* W1,
+                         double* W2, double* out) {
+  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
+  const int n = P * Dl * Du * Dr * Dd;
+  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][l][u][s][d] = sum_r A[p,l,u,r,d] f[r][s]
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int ss = t % Dr; t /= Dr;
+    const int u = t % Du; t /= Du;
+    const int l = t % Dl; t /= Dl;
+    const int p = t;
+    double acc = 0.0;
+    for (int r = 0; r < Dr; ++r) acc += sepA(s, p, l, u, r, d) * f[r * Dr + ss];
+    W1[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {   // W2[p][l][v][s][d] = sum_u W1[p][l][u][s][d] su[u][v]
+    int t = i;
+    const int d = t % Dd; t /= Dd;
+    const int ss = t % Dr; t /= Dr;
+    const int v = t % Du; t /= Du;
+    const int pl = t;
+    double acc = 0.0;
+    for (int u = 0; u < Du; ++u) acc += W1[((pl * Du + u) * Dr + ss) * Dd + d] * su[u * Du + v];
+    W2[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][l][v][s][g] = sum_d W2[p][l][v][s][d] sg[d][g]
+    const int g = i % Dd, base = i - g;
+    double acc = 0.0;
+    for (int d = 0; d < Dd; ++d) acc += W2[base + d] * sg[d * Dd + g];
+    W1[i] = acc;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < Dl * Dl; o += 256) {
+    const int l = o / Dl, m = o % Dl;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p)
+      for (int v = 0; v < Du; ++v)
+        for (int ss = 0; ss < Dr; ++ss)
+          for (int g = 0; g < Dd; ++g)
+            acc += W1[(((p * Dl + l) * Du + v) * Dr + ss) * Dd + g] * sepA(s, p, m, v, ss, g);
+    out[o] = acc;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void sep_kernel(const SepDesc* __restrict__ ds) {
+  const SepDesc& D = ds[blockIdx.x];
+  __shared__ double red[4];
+  __shared__ double one[1];
+  const int Lr = D.Lr, Lc = D.Lc;
+  double* E = D.work;                       // (Lc+1) slots
+  double* F = E + (size_t)(Lc + 1) * SEP_V;  // (Lc+1) slots
+  double* OLD = F + (size_t)(Lc + 1) * SEP_V;
+  double* W1 = OLD + (size_t)Lc * SEP_V;
+  double* W2 = W1 + SEP_W;
+  double* B = W2 + SEP_W;
+  if (threadIdx.x == 0) one[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k + 1 < Lr; ++k) {
+    const SepSite* row = D.sites + (size_t)k * Lc;
+    auto sup = [&](int c) -> const double* { return k == 0 ? one : D.sig + D.off[(size_t)(k - 1) * Lc + c]; };
+    auto sig = [&](int c) -> double* { return D.sig + D.off[(size_t)k * Lc + c]; };
+    for (int c = 0; c < Lc; ++c) {
+      const int Dd = row[c].Dd;
+      for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = (i / Dd == i % Dd) ? 1.0 / sqrt((double)Dd) : 0.0;
+    }
+    if (threadIdx.x == 0) {
+      E[0] = 1.0;
+      F[(size_t)Lc * SEP_V] = 1.0;
+    }
+    __syncthreads();
+    for (int c = Lc - 1; c >= 1; --c) {
+      sep_fupd(row[c], F + (size_t)(c + 1) * SEP_V, sup(c), sig(c), W1, W2, F + (size_t)c * SEP_V);
+      sep_unit(F + (size_t)c * SEP_V, row[c].Dl * row[c].Dl, red);
+    }
+    int sweeps = 0;
+    double delta = 0.0;
+    while (true) {
+      for (int c = 0; c < Lc; ++c)
+        for (int i = threadIdx.x; i < row[c].Dd * row[c].Dd; i += 256) OLD[(size_t)c * SEP_V + i] = sig(c)[i];
+      __syncthreads();
+      for (int c = 0; c < Lc; ++c) {
+        const int Dd = row[c].Dd;
+        sep_b(row[c], E + (size_t)c * SEP_V, sup(c), F + (size_t)(c + 1) * SEP_V, W1, W2, B);
+        sep_unit(B, Dd * Dd, red);
+        for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = B[i];
+        __syncthreads();
+        if (c + 1 < Lc) {
+          sep_eupd(row[c], E + (size_t)c * SEP_V, sup(c), sig(c), W1, W2, E + (size_t)(c + 1) * SEP_V);
+          sep_unit(E + (size_t)(c + 1) * SEP_V, row[c].Dr * row[c].Dr, red);
+        }
+      }
+      for (int c = Lc - 1; c >= 0; --c) {
+        const int Dd = row[c].Dd;
+        sep_b(row[c], E + (size_t)c * SEP_V, sup(c), F + (size_t)(c + 1) * SEP_V, W1, W2, B);
+        sep_unit(B, Dd * Dd, red);
+        for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = B[i];
+        __syncthreads();
+        if (c > 0) {
+          sep_fupd(row[c], F + (size_t)(c + 1) * SEP_V, sup(c), sig(c), W1, W2, F + (size_t)c * SEP_V);
+          sep_unit(F + (size_t)c * SEP_V, row[c].Dl * row[c].Dl, red);
+        }
+      }
+      ++sweeps;
+      double dmax = 0.0;
+      for (int c = 0; c < Lc; ++c) {
+        const int Dd = row[c].Dd;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < Dd * Dd; i += 256) {
+          const double x = sig(c)[i] - OLD[(size_t)c * SEP_V + i];
+          s += x * x;
+        }
+        s = block_sum256(s, red);
+        dmax = fmax(dmax, sqrt(s));
+      }
+      delta = dmax;
+      if (delta <= D.tol || sweeps >= D.max_sweeps) break;
+    }
+    if (threadIdx.x == 0) {
+      D.sweeps[k] = sweeps;
+      D.delta[k] = delta;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_sep(const SepDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  sep_kernel<<<nd, 256, 0, s>>>(d);
+  PE_HIP(hipGetLastError());
+}
+
+}  // namespace pe

@@ -1,0 +1,137 @@
+// Device kernels of libpepsenv and their descriptor records.
+//
+// Every kernel is "grouped": one launch processes an array of independent
+// descriptors (problems of any shapes), so that independent boundary rows,
+// sandwiches, cluster windows and PEPS instances share launches.
+#pragma once
+#include "common.hpp"
+
+namespace pe {
+
+// ---------------------------------------------------------------------------
+// Tensor contraction C[m,n] = alpha * sum_k A[m,k] B[k,n] + beta * C[m,n]
+// where m, n and k are each a multi-index of up to 4 sub-dimensions with
+// arbitrary strides in every operand (a GEMM over strided tensor views, so
+// no permutation kernels are needed between the stages of a chain).
+// ---------------------------------------------------------------------------
+constexpr int TC_MAXD = 4;
+struct TcDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t sAm[TC_MAXD], sAk[TC_MAXD], sBk[TC_MAXD], sBn[TC_MAXD], sCm[TC_MAXD], sCn[TC_MAXD];
+  int32_t dm[TC_MAXD], dn[TC_MAXD], dk[TC_MAXD];   // sub-dimension sizes, outermost first
+  int32_t nm, nn, nk;                              // number of sub-dimensions (>= 1)
+  int32_t M, N, K;
+  int32_t tiles_n, tile_base;                      // filled when the op is recorded
+  int32_t a_kfast, b_kfast;                        // global->LDS load order
+  double alpha, beta;
+};
+
+// Arithmetic of a contraction.
+enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
+// Tile shapes (MT x NT per 256-thread workgroup).
+enum TcTile : int { TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_COUNT = 4 };
+inline int tile_mt(int t) { return t == TT_64x64 ? 64 : t == TT_128x32 ? 128 : t == TT_256x16 ? 256 : 32; }
+inline int tile_nt(int t) { return t == TT_64x64 ? 64 : t == TT_128x32 ? 32 : t == TT_256x16 ? 16 : 128; }
+
+// out_dt: DT_F64 or DT_F32 (element type of C).  A and B are float64 for
+// TP_F64 and float32 for TP_F32/TP_BF16.
+void launch_tc(int prec, int out_dt, int tile, const TcDesc* d_desc, int n_desc, int n_tiles,
+               hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Householder QR of an m x n float64 matrix (m >= n), one workgroup each.
+// Q (m x n, orthonormal columns) and optionally R (n x n) are written with
+// arbitrary strides; the signs are fixed so that diag(R) >= 0.
+// ---------------------------------------------------------------------------
+struct QrDesc {
+  const double* A;
+  int64_t sAr, sAc;
+  double* Q;
+  int64_t sQr, sQc;
+  double* R;        // may be null
+  int64_t sRr, sRc;
+  double* W;        // workspace of 2*m*n doubles
+  int32_t m, n;
+};
+void launch_qr(const QrDesc* d_desc, int n_desc, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Deterministic sums: out = sum_i x_i * y_i (y null -> sum x_i^2), in two
+// passes over fixed partitions (bitwise reproducible).
+// ---------------------------------------------------------------------------
+struct RedDesc {
+  const void* x;
+  const void* y;
+  int64_t n;
+  double* out;
+  int32_t dt;          // element type of x and y
+  int32_t block_base;  // first block of this descriptor (filled on record)
+  int32_t nblocks;
+  int32_t part_base;   // offset into the partial-sum buffer
+};
+void launch_reduce(const RedDesc* d_desc, int n_desc, int n_blocks, double* partials, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Elementwise operations on contiguous buffers.
+// ---------------------------------------------------------------------------
+enum EwKind : int {
+  EW_COPY = 0,        // dst = src (with type conversion)
+  EW_PHYS = 1,        // dst[p*L+i] = sum_q op[p][q] src[q*L+i]   (2x2 operator, L = n/2)
+  EW_FILL = 2,        // dst = a
+  EW_SPLITMIX = 3,    // dst[i] = SplitMix64 value i of stream state `key`, in [-1, 1)
+  EW_RSQRT = 4,       // dst = src / sqrt(*sptr)
+  EW_IDENTITY = 5,    // dst = a * identity (n = D*D)
+};
+struct EwDesc {
+  const void* src;
+  void* dst;
+  int64_t n;
+  int32_t src_dt, dst_dt;
+  int32_t kind;
+  int32_t block_base;
+  int32_t nblocks;
+  int32_t dim;          // matrix dimension for EW_IDENTITY
+  double a;
+  double op[4];
+  uint64_t key;
+  const double* sptr;
+};
+void launch_ew(const EwDesc* d_desc, int n_desc, int n_blocks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// CU_0 separable boundaries (D' = 1): for one lattice direction, the rows of
+// the frame are absorbed one after another; each absorption is an ALS over
+// the row's sites whose local solution is sigma_c = b_c / |b_c| (the norm
+// matrix is a multiple of the identity), sweeping left-right-left until no
+// sigma changes by more than `tol` or `max_sweeps` sweeps have run.  One
+// workgroup per descriptor; virtual bond dimensions up to SEP_MAXD.
+// ---------------------------------------------------------------------------
+constexpr int SEP_MAXD = 8;
+struct SepSite {
+  const double* A;
+  int32_t d, Dl, Du, Dr, Dd, pad;
+  int64_t sp, sl, su, sr, sd;   // strides of the frame's (p, l, u, r, d) legs
+};
+struct SepDesc {
+  int32_t Lr, Lc, max_sweeps, pad;
+  double tol;
+  const SepSite* sites;   // Lr*Lc, frame row-major
+  double* sig;            // sigma of frame row k, column c at sig + off[k*Lc + c] (Dd x Dd)
+  const int64_t* off;
+  double* work;           // (3*Lc + 2) * SEP_MAXD^2 doubles
+  int32_t* sweeps;        // Lr-1 entries
+  double* delta;          // Lr-1 entries
+};
+void launch_sep(const SepDesc* d_desc, int n_desc, hipStream_t s);
+
+// SplitMix64 (Steele, Lea, Flood 2014): output function and stream state.
+__host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t SPLITMIX_GAMMA = 0x9E3779B97F4A7C15ull;
+
+}  // namespace pe

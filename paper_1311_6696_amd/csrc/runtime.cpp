@@ -1,0 +1,336 @@
+// Host runtime: pool, views, recorder.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <climits>
+
+namespace pe {
+
+// ------------------------------------------------------------------ Pool ----
+static size_t size_class(size_t b) {
+  if (b < 256) return 256;
+  size_t p = 1;
+  while (p < b) p <<= 1;
+  if (p <= (size_t(1) << 20)) return p;
+  const size_t step = p >> 3;   // 1/8 steps above 1 MiB
+  return (b + step - 1) / step * step;
+}
+
+Pool::~Pool() {
+  for (auto& kv : free_) dev::free(kv.second);
+  for (auto& kv : size_of_) (void)kv;   // blocks still in use are leaked deliberately
+}
+
+void* Pool::alloc(size_t bytes) {
+  const size_t sc = size_class(bytes);
+  auto it = free_.find(sc);
+  void* p;
+  if (it != free_.end()) {
+    p = it->second;
+    free_.erase(it);
+  } else {
+    try {
+      p = dev::malloc(sc);
+    } catch (const Error&) {
+      trim();
+      p = dev::malloc(sc);
+    }
+    size_of_[p] = sc;
+  }
+  in_use_ += sc;
+  return p;
+}
+
+void Pool::release(void* p) {
+  if (!p) return;
+  auto it = size_of_.find(p);
+  if (it == size_of_.end()) return;
+  in_use_ -= it->second;
+  free_.emplace(it->second, p);
+}
+
+void Pool::trim() {
+  for (auto& kv : free_) {
+    size_of_.erase(kv.second);
+    dev::free(kv.second);
+  }
+  free_.clear();
+}
+
+Ctx::~Ctx() {
+  if (pinned) dev::host_free(pinned);
+}
+
+void* Ctx::staging(size_t bytes) {
+  if (bytes > pinned_cap) {
+    if (pinned) {
+      dev::sync(stream);
+      dev::host_free(pinned);
+    }
+    pinned_cap = std::max(bytes, pinned_cap * 2);
+    pinned = dev::host_alloc(pinned_cap);
+  }
+  return pinned;
+}
+
+// ----------------------------------------------------------------- views ----
+TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_t>& dims) {
+  PE_REQUIRE(idx.size() == dims.size(), "view rank mismatch for '" + idx + "'");
+  TV v;
+  v.p = p;
+  v.dt = dt;
+  v.idx = idx;
+  v.dim = dims;
+  v.str.assign(dims.size(), 0);
+  int64_t s = 1;
+  for (int i = (int)dims.size() - 1; i >= 0; --i) {
+    v.str[i] = s;
+    s *= dims[i];
+  }
+  return v;
+}
+
+TV relabel(TV v, const std::string& idx) {
+  PE_REQUIRE(idx.size() == v.idx.size(), "relabel rank mismatch");
+  v.idx = idx;
+  return v;
+}
+
+namespace {
+struct Sub {
+  int64_t dim, s1, s2;
+};
+void merge_subs(std::vector<Sub>& v) {
+  std::vector<Sub> out;
+  for (const Sub& s : v) {
+    if (!out.empty() && out.back().s1 == s.s1 * s.dim && out.back().s2 == s.s2 * s.dim) {
+      out.back().dim *= s.dim;
+      out.back().s1 = s.s1;
+      out.back().s2 = s.s2;
+    } else {
+      out.push_back(s);
+    }
+  }
+  if (out.empty()) out.push_back({1, 0, 0});
+  v.swap(out);
+}
+int find_idx(const TV& t, char c) {
+  const size_t p = t.idx.find(c);
+  return p == std::string::npos ? -1 : (int)p;
+}
+}  // namespace
+
+TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha, double beta) {
+  // Operand "A" is the one holding C's unit-stride index, so that the MFMA
+  // tile's contiguous lane group writes contiguous memory.
+  char cin = 0;
+  int64_t best = INT64_MAX;
+  for (size_t i = 0; i < C.idx.size(); ++i)
+    if (C.dim[i] > 1 && C.str[i] < best) {
+      best = C.str[i];
+      cin = C.idx[i];
+    }
+  const bool x_is_a = (cin == 0) || find_idx(X, cin) >= 0;
+  const TV& A = x_is_a ? X : Y;
+  const TV& B = x_is_a ? Y : X;
+  std::vector<Sub> Ms, Ns, Ks;
+  for (size_t i = 0; i < C.idx.size(); ++i) {
+    const char c = C.idx[i];
+    const int ia = find_idx(A, c), ib = find_idx(B, c);
+    if (ia < 0 && ib < 0 && C.dim[i] == 1) continue;   // trivial index of the output only
+    PE_REQUIRE((ia >= 0) != (ib >= 0), std::string("index '") + c + "' must be in exactly one operand");
+    if (ia >= 0) {
+      PE_REQUIRE(A.dim[ia] == C.dim[i], std::string("dimension mismatch of '") + c + "'");
+      if (C.dim[i] > 1) Ms.push_back({C.dim[i], A.str[ia], C.str[i]});
+    } else {
+      PE_REQUIRE(B.dim[ib] == C.dim[i], std::string("dimension mismatch of '") + c + "'");
+      if (C.dim[i] > 1) Ns.push_back({C.dim[i], B.str[ib], C.str[i]});
+    }
+  }
+  for (size_t i = 0; i < A.idx.size(); ++i) {
+    const char c = A.idx[i];
+    if (find_idx(C, c) >= 0) continue;
+    const int ib = find_idx(B, c);
+    if (ib < 0 && A.dim[i] == 1) continue;
+    PE_REQUIRE(ib >= 0, std::string("index '") + c + "' appears once");
+    PE_REQUIRE(B.dim[ib] == A.dim[i], std::string("dimension mismatch of '") + c + "'");
+    if (A.dim[i] > 1) Ks.push_back({A.dim[i], A.str[i], B.str[ib]});
+  }
+  for (size_t i = 0; i < B.idx.size(); ++i)
+    PE_REQUIRE(find_idx(C, B.idx[i]) >= 0 || find_idx(A, B.idx[i]) >= 0 || B.dim[i] == 1,
+               std::string("index '") + B.idx[i] + "' appears once");
+  merge_subs(Ms);
+  merge_subs(Ns);
+  merge_subs(Ks);
+  PE_REQUIRE(Ms.size() <= TC_MAXD && Ns.size() <= TC_MAXD && Ks.size() <= TC_MAXD,
+             "contraction " + C.idx + " = " + X.idx + " * " + Y.idx + " needs more than 4 sub-dimensions");
+  TcDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.A = A.p;
+  d.B = B.p;
+  d.C = const_cast<void*>(C.p);
+  int64_t M = 1, N = 1, K = 1;
+  d.nm = (int)Ms.size();
+  d.nn = (int)Ns.size();
+  d.nk = (int)Ks.size();
+  for (int i = 0; i < d.nm; ++i) {
+    d.dm[i] = (int32_t)Ms[i].dim;
+    d.sAm[i] = Ms[i].s1;
+    d.sCm[i] = Ms[i].s2;
+    M *= Ms[i].dim;
+  }
+  for (int i = 0; i < d.nn; ++i) {
+    d.dn[i] = (int32_t)Ns[i].dim;
+    d.sBn[i] = Ns[i].s1;
+    d.sCn[i] = Ns[i].s2;
+    N *= Ns[i].dim;
+  }
+  for (int i = 0; i < d.nk; ++i) {
+    d.dk[i] = (int32_t)Ks[i].dim;
+    d.sAk[i] = Ks[i].s1;
+    d.sBk[i] = Ks[i].s2;
+    K *= Ks[i].dim;
+  }
+  PE_REQUIRE(M < INT_MAX && N < INT_MAX && K < INT_MAX, "contraction too large");
+  d.M = (int)M;
+  d.N = (int)N;
+  d.K = (int)K;
+  d.a_kfast = (Ks.back().s1 == 1 && Ms.back().s1 != 1) ? 1 : 0;
+  d.b_kfast = (Ks.back().s2 == 1 && Ns.back().s1 != 1) ? 1 : 0;
+  d.alpha = alpha;
+  d.beta = beta;
+  return d;
+}
+
+// -------------------------------------------------------------- recorder ----
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4 };
+
+size_t Rec::push_bytes(const void* p, size_t n) {
+  const size_t off = (blob_.size() + 15) / 16 * 16;
+  blob_.resize(off + n);
+  std::memcpy(blob_.data() + off, p, n);
+  return off;
+}
+
+static int pick_tile(const TcDesc& d) {
+  if (d.N <= 16) return TT_256x16;
+  if (d.N <= 32) return TT_128x32;
+  if (d.M <= 32 && d.N >= 128) return TT_32x128;
+  return TT_64x64;
+}
+
+void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
+  if (ds.empty()) return;
+  // one tile shape per launch: the shape of the largest problem decides
+  size_t big = 0;
+  for (size_t i = 1; i < ds.size(); ++i)
+    if ((double)ds[i].M * ds[i].N > (double)ds[big].M * ds[big].N) big = i;
+  const int tile = pick_tile(ds[big]);
+  const int mt = tile_mt(tile), nt = tile_nt(tile);
+  int64_t tiles = 0;
+  double fl = 0.0;
+  for (auto& d : ds) {
+    d.tiles_n = (d.N + nt - 1) / nt;
+    d.tile_base = (int32_t)tiles;
+    tiles += (int64_t)((d.M + mt - 1) / mt) * d.tiles_n;
+    fl += 2.0 * d.M * (double)d.N * d.K;
+  }
+  PE_REQUIRE(tiles < INT_MAX, "too many tiles in one launch");
+  Op op{OK_TC, prec, out_dt, tile, (int)ds.size(), (int)tiles, push_bytes(ds.data(), ds.size() * sizeof(TcDesc)),
+        algorithmic ? fl : 0.0};
+  if (algorithmic) flops_ += fl;
+  ops_.push_back(op);
+}
+
+void Rec::qr(const std::vector<QrDesc>& ds) {
+  if (ds.empty()) return;
+  for (const auto& d : ds) PE_REQUIRE(d.m >= d.n && d.n >= 1 && d.n <= 1024, "QR shape");
+  ops_.push_back(Op{OK_QR, 0, 0, 0, (int)ds.size(), (int)ds.size(), push_bytes(ds.data(), ds.size() * sizeof(QrDesc)), 0.0});
+}
+
+void Rec::reduce(std::vector<RedDesc> ds) {
+  if (ds.empty()) return;
+  int blocks = 0;
+  for (auto& d : ds) {
+    d.nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (d.n + 8191) / 8192));
+    d.block_base = blocks;
+    d.part_base = partials_ + blocks;
+    blocks += d.nblocks;
+  }
+  partials_ += blocks;
+  ops_.push_back(Op{OK_RED, 0, 0, 0, (int)ds.size(), blocks, push_bytes(ds.data(), ds.size() * sizeof(RedDesc)), 0.0});
+}
+
+void Rec::ew(std::vector<EwDesc> ds) {
+  if (ds.empty()) return;
+  int blocks = 0;
+  for (auto& d : ds) {
+    d.nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (d.n + 1023) / 1024));
+    d.block_base = blocks;
+    blocks += d.nblocks;
+  }
+  ops_.push_back(Op{OK_EW, 0, 0, 0, (int)ds.size(), blocks, push_bytes(ds.data(), ds.size() * sizeof(EwDesc)), 0.0});
+}
+
+void Rec::sep(const std::vector<SepDesc>& ds) {
+  if (ds.empty()) return;
+  ops_.push_back(Op{OK_SEP, 0, 0, 0, (int)ds.size(), (int)ds.size(), push_bytes(ds.data(), ds.size() * sizeof(SepDesc)), 0.0});
+}
+
+void* Rec::aux(Arena& arena, const void* data, size_t bytes) {
+  void* d = arena.alloc(bytes);
+  aux_.push_back({d, {push_bytes(data, bytes), bytes}});
+  return d;
+}
+
+void Rec::run(Arena& arena) {
+  if (ops_.empty()) return;
+  hipStream_t s = ctx_->stream;
+  uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
+  double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+  void* host = ctx_->staging(blob_.size());
+  std::memcpy(host, blob_.data(), blob_.size());
+  dev::h2d(dblob, host, blob_.size(), s);
+  for (auto& a : aux_) dev::d2d(a.first, dblob + a.second.first, a.second.second, s);
+  std::vector<std::pair<void*, void*>> evs;
+  std::vector<int> ev_op;
+  for (size_t i = 0; i < ops_.size(); ++i) {
+    const Op& op = ops_[i];
+    const void* d = dblob + op.off;
+    void* e0 = nullptr;
+    if (ctx_->profile && op.kind == OK_TC) {
+      e0 = dev::event_create();
+      dev::event_record(e0, s);
+    }
+    switch (op.kind) {
+      case OK_TC: launch_tc(op.prec, op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
+      case OK_QR: launch_qr((const QrDesc*)d, op.nd, s); break;
+      case OK_RED: launch_reduce((const RedDesc*)d, op.nd, op.grid, partials, s); break;
+      case OK_EW: launch_ew((const EwDesc*)d, op.nd, op.grid, s); break;
+      case OK_SEP: launch_sep((const SepDesc*)d, op.nd, s); break;
+    }
+    if (e0) {
+      void* e1 = dev::event_create();
+      dev::event_record(e1, s);
+      evs.push_back({e0, e1});
+      ev_op.push_back((int)i);
+    }
+  }
+  // the staging buffer and descriptors must stay valid until the stream drains
+  dev::sync(s);
+  for (size_t j = 0; j < evs.size(); ++j) {
+    const Op& op = ops_[ev_op[j]];
+    const int key = op.prec * 8 + op.out_dt * 4 + op.tile;
+    ctx_->st_ms[key] += dev::event_ms(evs[j].first, evs[j].second);
+    ctx_->st_flops[key] += op.flops;
+    ctx_->st_launch[key] += 1;
+    dev::event_destroy(evs[j].first);
+    dev::event_destroy(evs[j].second);
+  }
+  ops_.clear();
+  blob_.clear();
+  aux_.clear();
+  partials_ = 0;
+}
+
+}  // namespace pe

@@ -1,0 +1,184 @@
+// Host runtime of libpepsenv: memory pool, op recorder, tensor views and the
+// environment data structures.
+#pragma once
+#include <map>
+#include <memory>
+#include <unordered_map>
+
+#include "devapi.hpp"
+#include "kernels.hpp"
+
+namespace pe {
+
+// ---------------------------------------------------------------- memory ----
+// Caching device allocator: freed blocks are kept per size class and handed
+// out again, so repeated calls with the same shapes allocate nothing.
+class Pool {
+ public:
+  ~Pool();
+  void* alloc(size_t bytes);
+  void release(void* p);
+  void trim();
+  size_t bytes_in_use() const { return in_use_; }
+
+ private:
+  std::multimap<size_t, void*> free_;
+  std::unordered_map<void*, size_t> size_of_;
+  size_t in_use_ = 0;
+};
+
+// Allocations of one object (environment or call), returned to the pool on
+// destruction.
+class Arena {
+ public:
+  explicit Arena(Pool* p) : pool_(p) {}
+  ~Arena() { clear(); }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  void* alloc(size_t bytes) {
+    void* p = pool_->alloc(bytes);
+    blocks_.push_back(p);
+    return p;
+  }
+  void clear() {
+    for (void* p : blocks_) pool_->release(p);
+    blocks_.clear();
+  }
+
+ private:
+  Pool* pool_;
+  std::vector<void*> blocks_;
+};
+
+// ------------------------------------------------------------------ views ---
+// A strided tensor view with one character label per index.
+struct TV {
+  const void* p = nullptr;
+  int dt = DT_F64;
+  std::string idx;
+  std::vector<int64_t> dim, str;
+  int64_t size() const {
+    int64_t n = 1;
+    for (auto d : dim) n *= d;
+    return n;
+  }
+};
+TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_t>& dims);
+TV relabel(TV v, const std::string& idx);
+// C = alpha * contraction(X, Y) + beta * C, every index in exactly two views.
+TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha = 1.0, double beta = 0.0);
+
+// --------------------------------------------------------------- recorder ---
+// Records grouped launches and their descriptors, then uploads every
+// descriptor in one copy and issues the launches in order on one stream.
+struct Ctx;
+class Rec {
+ public:
+  explicit Rec(Ctx* c) : ctx_(c) {}
+  void tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic = true);
+  void qr(const std::vector<QrDesc>& ds);
+  void reduce(std::vector<RedDesc> ds);
+  void ew(std::vector<EwDesc> ds);
+  void sep(const std::vector<SepDesc>& ds);
+  // Device copy of host data, available to every op recorded after this call.
+  void* aux(Arena& arena, const void* data, size_t bytes);
+  // Upload, launch everything, and clear.  Scratch of `arena` must outlive the launch.
+  void run(Arena& arena);
+  double flops() const { return flops_; }
+
+ private:
+  struct Op {
+    int kind, prec, out_dt, tile, nd, grid;
+    size_t off;
+    double flops;
+  };
+  size_t push_bytes(const void* p, size_t n);
+  Ctx* ctx_;
+  std::vector<Op> ops_;
+  std::vector<uint8_t> blob_;
+  std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
+  int partials_ = 0;
+  double flops_ = 0.0;
+};
+
+// ---------------------------------------------------------------- context ---
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Pool pool;
+  size_t scratch_budget = size_t(48) << 30;
+  bool profile = false;
+  static constexpr int NSTAT = 24;
+  double st_flops[NSTAT] = {0};
+  double st_ms[NSTAT] = {0};
+  int64_t st_launch[NSTAT] = {0};
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+  ~Ctx();
+  void* staging(size_t bytes);
+};
+
+// ----------------------------------------------------------- environment ---
+// Packed site tensor: copies in the contraction dtype with the identity,
+// S^z, S^+ and S^- applied to the ket physical leg.
+struct Site {
+  void* op[4] = {nullptr, nullptr, nullptr, nullptr};
+  int d = 2, Dl = 1, Du = 1, Dr = 1, Dd = 1;
+};
+
+struct Lattice {
+  int Lr = 0, Lc = 0;
+  std::vector<const Site*> s;                 // row-major
+  std::vector<const void*> lam, rho, tau, beta;   // closings in the compute dtype
+  const Site& at(int r, int c) const { return *s[(size_t)r * Lc + c]; }
+};
+
+// Boundary MPS: Lc tensors [a][k][b][a'] in float64 and in the compute dtype.
+struct Mps {
+  std::vector<double*> t64;
+  std::vector<const void*> tc;
+  std::vector<int> bond;   // Lc+1 entries, bond[0] = bond[Lc] = 1
+  std::vector<int> leg;    // Lc entries
+  const double* omega = nullptr;   // device slots of the squared centre norms (null: closing)
+  int n_omega = 0;                 // 1 for an exact row, halfsweeps for a truncated one
+  bool truncated = false;
+};
+
+struct Opts {
+  int chi = 1, dtype = 0, halfsweeps = 4;
+  uint64_t seed = 0;
+  int prec() const { return dtype; }
+  int cdt() const { return dtype == 0 ? DT_F64 : DT_F32; }
+};
+
+}  // namespace pe
+
+// The context's state is shared with every environment made from it, so an
+// environment stays valid (and frees into a live pool) even if the context
+// handle is destroyed first.
+struct peps_ctx {
+  std::shared_ptr<pe::Ctx> c;
+};
+
+struct peps_env {
+  explicit peps_env(const std::shared_ptr<pe::Ctx>& c) : ctxref(c), ctx(c.get()), arena(&c->pool) {}
+  std::shared_ptr<pe::Ctx> ctxref;   // declared first: released last
+  pe::Ctx* ctx;
+  pe::Arena arena;
+  pe::Opts opts;
+  pe::Lattice lat;
+  std::vector<std::unique_ptr<pe::Site>> sites;   // owned packed sites (may be shared by windows)
+  std::shared_ptr<void> shared_owner;             // keeps a parent's packed data alive
+  std::vector<pe::Mps> top;   // top[k] = T_{k-1}: rows 0..k-1 absorbed, k = 0..Lr-1
+  std::vector<pe::Mps> bot;   // bot[k]: rows Lr-k..Lr-1 absorbed (flipped frame)
+  std::vector<double> top_log, bot_log;   // cumulative log-scales
+  std::vector<double> omegas;             // per truncated row, halfsweeps values
+  int n_trunc = 0;
+  bool window = false;
+  int ci = 0, cj = 0;                     // centre (window coordinates)
+  double flops = 0.0;
+  pe::Mps& T(int r) { return top[r + 1]; }
+  pe::Mps& B(int r) { return bot[lat.Lr - r]; }
+  double Tlog(int r) const { return top_log[r + 1]; }
+  double Blog(int r) const { return bot_log[lat.Lr - r]; }
+};

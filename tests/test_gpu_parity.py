@@ -1,0 +1,128 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Float64 results must agree with the oracle to 1e-10 (absolute on <S^z> and
+bond energies, which are O(1) bounded quantities, and on log <psi|psi>);
+the oracle runs the same algorithm (same caps, same SplitMix64 start, same
+half-sweeps), so the two differ only by rounding order.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import api, exact
+from paper_1311_6696_amd import binding
+from paper_1311_6696_amd.inputs import make_peps, product_state, config_peps, CONFIGS
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sess():
+    return binding.Session(0)
+
+
+def run_gpu(sess, A_list, chi, dtype="f64", H=4):
+    dev = [binding.to_device(A) for A in A_list]
+    envs = sess.env_boundary(dev, chi, dtype, H)
+    res = sess.expect(envs)
+    info = [e.info() for e in envs]
+    for e in envs:
+        e.free()
+    return res, info
+
+
+def max_obs_diff(r, ref):
+    out = 0.0
+    for k in ("sz", "bond_h", "bond_v"):
+        if np.asarray(ref[k]).size:
+            out = max(out, float(np.max(np.abs(np.asarray(r[k]) - np.asarray(ref[k])))))
+    return out
+
+
+@pytest.mark.parametrize("seed", [1001, 1002, 1003])
+def test_cfg1_exact_vs_statevector(sess, seed):
+    say(f"cfg1 4x4 D=2 chi=16 seed={seed}")
+    A = make_peps(4, 4, 2, "uniform", seed)
+    (r,), _ = run_gpu(sess, [A], 16)
+    sv = exact.sv_observables(A)
+    ref = api.expect(api.env_boundary(A, 16))
+    assert max_obs_diff(r, ref) < TOL64
+    assert max_obs_diff(r, sv) < TOL64
+    assert abs(r["log_norm"] - np.log(sv["norm"])) < TOL64
+    assert r["sign"] == 1.0
+
+
+@pytest.mark.parametrize("case", [
+    (3, 4, 2, "normal_unit", 4, 4),
+    (4, 3, 3, "normal_unit", 5, 3),
+    (5, 5, 2, "near_product", 6, 4),
+    (1, 5, 2, "uniform", 4, 2),
+    (5, 1, 2, "uniform", 4, 2),
+    (4, 4, 3, "uniform", 9, 1),
+])
+def test_truncated_parity(sess, case):
+    Lr, Lc, D, dist, chi, H = case
+    say(f"truncated {case}")
+    A = make_peps(Lr, Lc, D, dist, 100 + Lr * 10 + Lc)
+    (r,), (info,) = run_gpu(sess, [A], chi, H=H)
+    env = api.env_boundary(A, chi, H)
+    ref = api.expect(env)
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+    # ALS diagnostics: squared centre norms per half-sweep agree with the oracle's
+    om = [i.omegas for row in (env.top, env.bottom) for (_, _, i) in row[1:] if i is not None and not i.exact]
+    if om:
+        got = np.sort(info.reshape(-1))
+        want = np.sort(np.array(om).reshape(-1))
+        np.testing.assert_allclose(got, want, rtol=1e-10)
+
+
+def test_product_state(sess):
+    say("product state 3x5")
+    A = product_state(3, 5, seed=2)
+    (r,), _ = run_gpu(sess, [A], 3)
+    ref = api.expect(api.env_boundary(A, 3))
+    assert max_obs_diff(r, ref) < 1e-13
+
+
+def test_batched_heterogeneous(sess):
+    """Lattices of different shapes in one call give the single-call results."""
+    say("batched heterogeneous")
+    As = [make_peps(3, 4, 2, "normal_unit", 21), make_peps(4, 3, 3, "uniform", 22),
+          make_peps(5, 5, 2, "near_product", 23)]
+    res, _ = run_gpu(sess, As, 5, H=3)
+    for A, r in zip(As, res):
+        ref = api.expect(api.env_boundary(A, 5, 3))
+        assert max_obs_diff(r, ref) < TOL64
+
+
+def test_cfg2_full_parity(sess):
+    """8x8, D=4, near-product, chi=32: all 112 bonds and the norm."""
+    say("cfg2 8x8 D=4 chi=32 f64")
+    c = CONFIGS[2]
+    A = config_peps(2)
+    (r,), _ = run_gpu(sess, [A], c["chi"])
+    ref = api.expect(api.env_boundary(A, c["chi"]))
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 5e-2)])
+def test_precision_forms_error(sess, dtype, tol):
+    """FP32 / BF16 bulk contractions (FP64 QR and norms): error vs the FP64 oracle."""
+    say(f"precision form {dtype}")
+    A = make_peps(6, 6, 3, "normal_unit", 31)
+    (r,), _ = run_gpu(sess, [A], 9, dtype=dtype)
+    ref = api.expect(api.env_boundary(A, 9))
+    e_ref = api.energy(ref)
+    e = float(np.sum(r["bond_h"]) + np.sum(r["bond_v"]))
+    err = abs(e - e_ref) / abs(e_ref)
+    say(f"  {dtype}: relative energy error {err:.3e}, max bond error {max_obs_diff(r, ref):.3e}")
+    assert err < tol
