@@ -1,0 +1,56 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, it
+exports every function declared in include/peps_env.h, and its error paths
+that need no device behave."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1311_6696_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "peps_env.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:peps_status|void|const char\*)\s+(peps_\w+)\s*\(", text, re.M)))
+
+
+def test_header_lists_the_abi():
+    names = declared_functions()
+    for n in ("peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_ctx_create", "peps_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libpepsenv.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(binding.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(binding.SYMBOLS)
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = binding.load()
+    lib.peps_env_free(None)
+    lib.peps_ctx_destroy(None)
+    assert lib.peps_env_info(None, None, None, None) == -1
+    assert b"must not be NULL" in lib.peps_last_error()
+    assert lib.peps_expect(None, None, 0, None) == -1
+    assert lib.peps_env_boundary(None, None, 0, None, None) == -1
+    assert lib.peps_cluster_env(None, None, 0, None, 0, None, None) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(OSError):
+        binding.load(str(tmp_path / "nope.so"))
+
+
+def test_struct_layouts_match_header():
+    # sizes of the records shared with C (x86-64 ABI)
+    assert C.sizeof(binding.State) == 4 * 3 + 4 + 8 + 8
+    assert C.sizeof(binding.Opts) == 4 * 4 + 8
+    assert C.sizeof(binding.Window) == 7 * 4
+    assert C.sizeof(binding.Result) == 5 * 8

@@ -1,0 +1,113 @@
+"""Cluster windows on the GPU (through the C ABI) against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import api, cluster, exact
+from oracle.boundary import whole_lattice
+from paper_1311_6696_amd import binding
+from paper_1311_6696_amd.inputs import make_peps
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sess():
+    return binding.Session(0)
+
+
+def windows_for(L, n, sites=None):
+    out = []
+    for (i, j) in (sites or [(i, j) for i in range(L) for j in range(L)]):
+        r0, r1 = cluster.window_bounds(i, n, L)
+        c0, c1 = cluster.window_bounds(j, n, L)
+        out.append((0, r0, r1, c0, c1, i, j))
+    return out
+
+
+def gpu_clusters(sess, A, wins, chi, H=4, dtype="f64"):
+    envs = sess.cluster_env([binding.to_device(A)], wins, chi, dtype, H)
+    res = sess.expect(envs)
+    for e in envs:
+        e.free()
+    return res
+
+
+def compare(res, wins, ref, tol):
+    worst = 0.0
+    for w, r in zip(wins, res):
+        rs = ref[(w[5], w[6])]
+        for a, b in ((r["sz"], rs[0]), (r["right"], rs[1]), (r["down"], rs[2])):
+            if np.isnan(b):
+                assert np.isnan(a)
+            else:
+                worst = max(worst, abs(a - b))
+    assert worst < tol, worst
+    return worst
+
+
+@pytest.mark.parametrize("L,D,n,chi,H", [(4, 2, 2, 4, 4), (5, 2, 3, 4, 3), (6, 3, 4, 6, 2), (5, 2, 6, 4, 2)])
+def test_cluster_windows_parity(sess, L, D, n, chi, H):
+    say(f"clusters L={L} D={D} n={n} chi={chi}")
+    A = make_peps(L, L, D, "near_product", 40 + L + n)
+    wins = windows_for(L, n)
+    res = gpu_clusters(sess, A, wins, chi, H)
+    ref, _ = cluster.cluster_env(whole_lattice(A), n, chi, H)
+    compare(res, wins, ref, TOL64)
+
+
+def test_window_equal_to_lattice_is_full_environment(sess):
+    say("window == lattice")
+    A = make_peps(4, 5, 2, "normal_unit", 77)
+    wins = [(0, 0, 3, 0, 4, i, j) for i in range(4) for j in range(5)]
+    res = gpu_clusters(sess, A, wins, 8)
+    full = api.expect(api.env_boundary(A, 8))
+    for w, r in zip(wins, res):
+        i, j = w[5], w[6]
+        assert abs(r["sz"] - full["sz"][i, j]) < TOL64
+        if j < 4:
+            assert abs(r["right"] - full["bond_h"][i, j]) < TOL64
+        if i < 3:
+            assert abs(r["down"] - full["bond_v"][i, j]) < TOL64
+
+
+def test_n2_windows_exact(sess):
+    """n = 2 at chi = D^2: no truncation, equal to the direct contraction of
+    the closed window network (closings from the oracle's CU_0)."""
+    say("n=2 exact windows")
+    A = make_peps(4, 4, 3, "near_product", 9)
+    wins = windows_for(4, 2)
+    res = gpu_clusters(sess, A, wins, 9)
+    _, sep = cluster.cluster_env(whole_lattice(A), 2, 9, sites=[(0, 0)])
+    for w, r in zip(wins, res):
+        _, r0, r1, c0, c1, i, j = w
+        ex = exact.closed_network_observables(cluster.window_lattice(sep, r0, r1, c0, c1))
+        assert abs(r["sz"] - ex["sz"][i - r0, j - c0]) < TOL64
+        if j < c1:
+            assert abs(r["right"] - ex["bond_h"][i - r0, j - c0]) < TOL64
+        if i < r1:
+            assert abs(r["down"] - ex["bond_v"][i - r0, j - c0]) < TOL64
+
+
+def test_cluster_config4_sample(sess):
+    """16x16, D=6, near-product, chi=36: a sample of n=2/4/6 windows (edge,
+    corner and bulk) against the oracle, in the launch configuration of a
+    batched run (all windows of one n in one call)."""
+    from paper_1311_6696_amd.inputs import config_peps
+    A = config_peps(4)
+    lat = whole_lattice(A)
+    sample = [(0, 0), (0, 7), (5, 5), (15, 15), (9, 14)]
+    for n in (2, 4, 6):
+        say(f"config 4 sample n={n}")
+        wins = windows_for(16, n)
+        res = gpu_clusters(sess, A, wins, 36)
+        ref, _ = cluster.cluster_env(lat, n, 36, sites=sample)
+        picked = [(w, r) for w, r in zip(wins, res) if (w[5], w[6]) in ref]
+        compare([r for _, r in picked], [w for w, _ in picked], ref, TOL64)
