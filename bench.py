@@ -19,19 +19,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense MFMA TFLOP/s, MI355X
-TILES = ["64x64", "128x32", "256x16", "32x128"]
-PRECS = ["f64", "f32", "bf16"]
-
-
-def variant_name(i):
-    return f"tc_kernel<{PRECS[i // 8]}, out={'f64' if (i // 4) % 2 == 0 else 'f32'}, {TILES[i % 4]}>"
-
-
-def run_steps(sess, dev_state, chi, dtype, halfsweeps, n):
+def run_steps(sess, dev_state, chi, dtype, halfsweeps, n, split=None):
+    """n full environments; `split` (a list) receives (boundary_s, expect_s) per step."""
     res = None
     for _ in range(n):
+        t0 = time.perf_counter()
         envs = sess.env_boundary([dev_state], chi, dtype, halfsweeps)
+        t1 = time.perf_counter()
         res = sess.expect(envs)[0]
+        t2 = time.perf_counter()
+        if split is not None:
+            split.append((t1 - t0, t2 - t1))
         for e in envs:
             e.free()
     return res
@@ -53,6 +51,8 @@ def main():
     ap.add_argument("--halfsweeps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32/BF16 measurements")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="lattices per call of the batched side measurement (1 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path has no multi-GPU component); got --gpus {args.gpus}",
@@ -75,7 +75,8 @@ def main():
     ref = run_steps(sess, dev_state, chi, "f64", H, args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = run_steps(sess, dev_state, chi, "f64", H, args.steps)
+    split = []
+    res = run_steps(sess, dev_state, chi, "f64", H, args.steps, split)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
@@ -113,9 +114,11 @@ def main():
         "gflops_per_s": flops / (ms * 1e-3) / 1e9,
         "pct_fp64_mfma_peak": 100.0 * flops / (ms * 1e-3) / (PEAK["f64"] * 1e12),
         "gflop_per_env": flops / 1e9,
+        "boundary_ms": 1000.0 * float(np.median([s[0] for s in split])),
+        "expect_ms": 1000.0 * float(np.median([s[1] for s in split])),
         "roofline": {
             "bound": "mfma",
-            "kernel": variant_name(dom),
+            "kernel": binding.variant_name(dom),
             "achieved": achieved,
             "peak": PEAK["f64"],
             "unit": "TFLOP/s",
@@ -126,6 +129,26 @@ def main():
             "contraction_ms_per_env": tc_total_ms,
         },
     }
+
+    if args.batch > 1:
+        # the same workload, several independent lattices per call (one grouped launch per stage)
+        note(f"batched: {args.batch} lattices per call")
+        states = [binding.to_device(config_peps(2, seed=2000 + i)) for i in range(args.batch)]
+        for _ in range(2):
+            envs = sess.env_boundary(states, chi, "f64", H)
+            sess.expect(envs)
+        torch.cuda.synchronize()
+        nb = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            envs = sess.env_boundary(states, chi, "f64", H)
+            sess.expect(envs)
+            for e in envs:
+                e.free()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        out["batched"] = {"lattices_per_call": args.batch, "value": nb * args.batch / tb, "unit": "env/s",
+                          "ms_per_call": 1000.0 * tb / nb}
 
     if not args.no_forms:
         forms = {}

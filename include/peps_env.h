@@ -133,12 +133,13 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, d
 
 /* Profiling of the contraction kernel: when enabled, every contraction
  * launch is bracketed by HIP events on the context's stream; statistics are
- * kept per kernel variant, index = prec*8 + out_dtype*4 + tile
+ * kept per kernel variant, index = (prec*2 + out_dtype)*6 + tile
  * (prec: 0 f64, 1 f32, 2 bf16; out_dtype: 0 f64, 1 f32; tile: 0 64x64,
- * 1 128x32, 2 256x16, 3 32x128).  Enabling clears the statistics. */
+ * 1 128x32, 2 256x16, 3 32x128, 4 64x32, 5 64x16).  Enabling clears the
+ * statistics. */
 peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
-/* Copies the 24 per-variant statistics: algorithmic flops, milliseconds and
- * launch counts (host arrays of 24 entries each). */
+/* Copies the 36 per-variant statistics: algorithmic flops, milliseconds and
+ * launch counts (host arrays of 36 entries each). */
 peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches);
 /* Upper bound (bytes) of the transient workspace one call may hold for the
  * chain intermediates of a batch; larger batches run in several groups. */

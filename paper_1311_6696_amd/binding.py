@@ -16,7 +16,15 @@ PEPS_F64, PEPS_F32, PEPS_BF16 = 0, 1, 2
 DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
 STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
 DEFAULT_SEED = 0x13116696
-N_STATS = 24
+TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16")
+N_STATS = 3 * 2 * len(TILES)
+
+
+def variant_name(i):
+    """Kernel variant of statistics slot i (see peps_ctx_profile)."""
+    prec = ("f64", "f32", "bf16")[i // (2 * len(TILES))]
+    out = ("f64", "f32")[(i // len(TILES)) % 2]
+    return f"tc_kernel<{prec}, out={out}, {TILES[i % len(TILES)]}>"
 
 
 class PepsError(RuntimeError):

@@ -156,7 +156,7 @@ void normalise(Rec& rec, const std::vector<std::pair<TV, double*>>& outs) {
 
 void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>& out) {
   Arena call(&ctx.pool);
-  Rec rec(&ctx);
+  Rec rec(&ctx, &call);
   Scratch scr(call);
   std::vector<RJob> rj;
   std::vector<R2Job> r2;
@@ -343,6 +343,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         st2.record(rec, prec, cdt);
         rec.tc(prec, cdt, fin);
         normalise(rec, outs);
+        rec.flush(call);
       }
       for (void* p : P) scr.put(p);
       for (void* q : Q) scr.put(q);
@@ -444,6 +445,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         st2.record(rec, prec, cdt);
         rec.tc(prec, cdt, fin);
         for (void* p : tmp) scr.put(p);
+        rec.flush(call);
       }
     }
   }

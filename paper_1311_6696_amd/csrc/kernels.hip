@@ -7,10 +7,30 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
+// DPP move of a double (both 32-bit halves); lanes without a source read 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Inclusive scan
+// inside each 16-lane row by row_shr 1,2,4,8, then row_bcast:15 and
+// row_bcast:31 carry the row totals so that lane 63 holds the sum.  The
+// summation order is fixed, so every lane gets the same bits.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_d<0x111>(v);        // row_shr:1
+  v += dpp_d<0x112>(v);        // row_shr:2
+  v += dpp_d<0x114>(v);        // row_shr:4
+  v += dpp_d<0x118>(v);        // row_shr:8
+  v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Sum over the 256 threads of a workgroup; every thread receives the same value.
@@ -105,9 +125,13 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
     if (ds[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
   }
   const TcDesc& d = ds[lo];
-  const int M = d.M, N = d.N, K = d.K;
-  const int t = bid - d.tile_base;
+  const int M = d.M, N = d.N;
+  const int ksplit = d.ksplit;
+  const int wg = bid - d.tile_base;
+  const int t = wg / ksplit, slice = wg - t * ksplit;
   const int m0 = (t / d.tiles_n) * MT, n0 = (t % d.tiles_n) * NT;
+  const int kbeg = slice * d.kslice;
+  const int K = min(d.K, kbeg + d.kslice);   // this slice covers [kbeg, K)
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
   TC* __restrict__ C = (TC*)d.C;
@@ -145,7 +169,7 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
   }
   auto k_offsets = [&](int kc) {
     if (tid < KT) {
-      int k = kc * KT + tid;
+      int k = kbeg + kc * KT + tid;
       int64_t oa = 0, ob = 0;
       if (k < K) {
         for (int j = d.nk - 1; j >= 0; --j) {
@@ -165,7 +189,7 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
 
   T ra[EA], rb[EB];
   auto load = [&](int kc) {
-    const int k0 = kc * KT;
+    const int k0 = kbeg + kc * KT;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int mm, kk;
@@ -210,7 +234,7 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  const int nchunks = (K + KT - 1) / KT;
+  const int nchunks = (K - kbeg + KT - 1) / KT;
   load(0);
   for (int kc = 0; kc < nchunks; ++kc) {
     __syncthreads();
@@ -233,6 +257,45 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
   }
 
   const double alpha = d.alpha, beta = d.beta;
+  if (ksplit == 1) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm * WTM + i * 16 + (lane & 15);
+          const int nl = wn * WTN + j * 16 + P::row(lane, r);
+          if (m0 + ml < M && n0 + nl < N) {
+            const int64_t off = oCm[ml] + oCn[nl];
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * (double)C[off];
+            C[off] = (TC)v;
+          }
+        }
+    return;
+  }
+  // split-K: publish this slice's partial tile; the last slice to arrive
+  // sums all partials of the tile in slice order (deterministic) and stores.
+  __shared__ int s_last;
+  double* __restrict__ part = d.part + ((int64_t)t * ksplit + slice) * (MT * NT);
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ml = wm * WTM + i * 16 + (lane & 15);
+        const int nl = wn * WTN + j * 16 + P::row(lane, r);
+        part[ml * NT + nl] = (double)acc[i][j][r];
+      }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(d.cnt + t, 1) == ksplit - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const double* __restrict__ tp = d.part + (int64_t)t * ksplit * (MT * NT);
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -242,12 +305,15 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
         const int ml = wm * WTM + i * 16 + (lane & 15);
         const int nl = wn * WTN + j * 16 + P::row(lane, r);
         if (m0 + ml < M && n0 + nl < N) {
+          double sum = 0.0;
+          for (int q = 0; q < ksplit; ++q) sum += tp[(int64_t)q * (MT * NT) + ml * NT + nl];
           const int64_t off = oCm[ml] + oCn[nl];
-          double v = alpha * (double)acc[i][j][r];
+          double v = alpha * sum;
           if (beta != 0.0) v += beta * (double)C[off];
           C[off] = (TC)v;
         }
       }
+  if (tid == 0) d.cnt[t] = 0;
 }
 
 template <class P, class TC>
@@ -257,6 +323,8 @@ static void launch_tc_tile(int tile, const TcDesc* d, int nd, int nt, hipStream_
     case TT_128x32: tc_kernel<P, TC, 128, 32, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
     case TT_256x16: tc_kernel<P, TC, 256, 16, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
     case TT_32x128: tc_kernel<P, TC, 32, 128, 1, 4><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_64x32: tc_kernel<P, TC, 64, 32, 2, 2><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_64x16: tc_kernel<P, TC, 64, 16, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
     default: throw Error(ST_INVALID, "bad tile");
   }
 }
@@ -356,6 +424,181 @@ __global__ __launch_bounds__(256) void qr_kernel(const QrDesc* __restrict__ ds) 
 void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
   qr_kernel<<<nd, 256, 0, s>>>(d);
+  PE_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Register-resident Householder QR for blocks with m <= 64*RPW, n <= 4*NCW:
+// column k lives in wave k%4 (slot k/4), row i in lane i%64 (slot i/64).
+// Each reflection needs one wave reduction per trailing column and one
+// barrier; the reflectors go to the workspace for the accumulation of Q.
+// ===========================================================================
+template <int RPW, int NCW>
+__global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ ds) {
+  const QrDesc& d = ds[blockIdx.x];
+  const int m = d.m, n = d.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NMAX = 4 * NCW, MMAX = 64 * RPW;
+  __shared__ double vbuf[2][MMAX];
+  __shared__ double scl[2];
+  __shared__ double taus[NMAX], rdiag[NMAX];
+  double* __restrict__ V = d.W;   // reflector j at V[j*m .. j*m+m)
+  double a[RPW][NCW];
+#pragma unroll
+  for (int s = 0; s < RPW; ++s)
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+      const int i = lane + 64 * s, k = wave + 4 * c;
+      a[s][c] = (i < m && k < n) ? d.A[i * d.sAr + k * d.sAc] : 0.0;
+    }
+  // Reflection loop at run time; register slots are only ever addressed by
+  // compile-time indices under uniform predicates (no dynamic indexing).
+  for (int j = 0; j < n; ++j) {
+    {
+    const int oc = j >> 2, buf = j & 1;
+    if (wave == (j & 3)) {
+      double p = 0.0, x0loc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCW; ++c)
+        if (c == oc) {
+#pragma unroll
+          for (int s = 0; s < RPW; ++s) {
+            const int i = lane + 64 * s;
+            if (i >= j && i < m) p += a[s][c] * a[s][c];
+            if (i == j) x0loc = a[s][c];
+          }
+        }
+      p = wave_sum(p);
+      const double x0 = __shfl(x0loc, j & 63, 64);
+      const double nrm = sqrt(p);
+      double beta = 0.0, tau = 0.0, scal = 0.0;
+      if (nrm > 0.0) {
+        beta = -copysign(nrm, x0);
+        tau = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int c = 0; c < NCW; ++c)
+        if (c == oc) {
+#pragma unroll
+          for (int s = 0; s < RPW; ++s) {
+            const int i = lane + 64 * s;
+            const double v = i > j ? a[s][c] * scal : (i == j ? 1.0 : 0.0);
+            if (i > j) a[s][c] = v;
+            vbuf[buf][i] = i < m ? v : 0.0;
+            if (i < m) V[(int64_t)j * m + i] = v;
+          }
+        }
+      if (lane == 0) {
+        scl[buf] = tau;
+        taus[j] = tau;
+        rdiag[j] = beta;
+      }
+    }
+    __syncthreads();
+    const double tau = scl[buf];
+    double vi[RPW];
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) vi[s] = vbuf[buf][lane + 64 * s];
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+      const int k = wave + 4 * c;
+      if (k > j && k < n) {
+        double p = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPW; ++s) p += vi[s] * a[s][c];
+        const double w = wave_sum(p) * tau;
+#pragma unroll
+        for (int s = 0; s < RPW; ++s) a[s][c] -= vi[s] * w;
+      }
+    }
+    }
+  }
+  __syncthreads();
+  if (d.R) {
+#pragma unroll
+    for (int s = 0; s < RPW; ++s)
+#pragma unroll
+      for (int c = 0; c < NCW; ++c) {
+        const int i = lane + 64 * s, k = wave + 4 * c;
+        if (i < n && k < n) {
+          const double sg = rdiag[i] < 0.0 ? -1.0 : 1.0;
+          const double v = i < k ? a[s][c] : (i == k ? rdiag[i] : 0.0);
+          d.R[i * d.sRr + k * d.sRc] = sg * v;
+        }
+      }
+  }
+  // Q = H_0 ... H_{n-1} [I; 0], accumulated from the last reflector
+#pragma unroll
+  for (int s = 0; s < RPW; ++s)
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) a[s][c] = (lane + 64 * s == wave + 4 * c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int jj = 0; jj < NMAX; ++jj) {
+    const int j = NMAX - 1 - jj;
+    const double tau = j < n ? taus[j] : 0.0;
+    double vi[RPW];
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int i = lane + 64 * s;
+      vi[s] = (i >= j && i < m) ? V[(int64_t)j * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+      const int k = wave + 4 * c;
+      if (k >= j && k < n) {
+        double p = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPW; ++s) p += vi[s] * a[s][c];
+        const double w = wave_sum(p) * tau;
+#pragma unroll
+        for (int s = 0; s < RPW; ++s) a[s][c] -= vi[s] * w;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RPW; ++s)
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+      const int i = lane + 64 * s, k = wave + 4 * c;
+      if (i < m && k < n) d.Q[i * d.sQr + k * d.sQc] = (rdiag[k] < 0.0 ? -1.0 : 1.0) * a[s][c];
+    }
+}
+
+// Register-resident variants: (rows per lane, columns per wave).
+struct QrVariant {
+  int rpw, ncw;
+};
+constexpr QrVariant QR_VARIANTS[] = {{1, 2}, {1, 4}, {2, 4}, {4, 4}, {4, 8}, {8, 4}, {8, 8}, {16, 4}, {12, 8}, {2, 16}, {4, 16}};
+constexpr int QR_NVAR = sizeof(QR_VARIANTS) / sizeof(QR_VARIANTS[0]);
+
+int qr_variant_for(int m, int n) {
+  int best = -1, cost = 1 << 30;
+  for (int v = 0; v < QR_NVAR; ++v) {
+    const QrVariant& q = QR_VARIANTS[v];
+    if (64 * q.rpw >= m && 4 * q.ncw >= n && q.rpw * q.ncw < cost) {
+      best = v;
+      cost = q.rpw * q.ncw;
+    }
+  }
+  return best;   // -1: use the streaming kernel
+}
+
+void launch_qr_reg(int variant, const QrDesc* d, int nd, hipStream_t s) {
+  switch (variant) {
+    case 0: qr_reg_kernel<1, 2><<<nd, 256, 0, s>>>(d); break;
+    case 1: qr_reg_kernel<1, 4><<<nd, 256, 0, s>>>(d); break;
+    case 2: qr_reg_kernel<2, 4><<<nd, 256, 0, s>>>(d); break;
+    case 3: qr_reg_kernel<4, 4><<<nd, 256, 0, s>>>(d); break;
+    case 4: qr_reg_kernel<4, 8><<<nd, 256, 0, s>>>(d); break;
+    case 5: qr_reg_kernel<8, 4><<<nd, 256, 0, s>>>(d); break;
+    case 6: qr_reg_kernel<8, 8><<<nd, 256, 0, s>>>(d); break;
+    case 7: qr_reg_kernel<16, 4><<<nd, 256, 0, s>>>(d); break;
+    case 8: qr_reg_kernel<12, 8><<<nd, 256, 0, s>>>(d); break;
+    case 9: qr_reg_kernel<2, 16><<<nd, 256, 0, s>>>(d); break;
+    case 10: qr_reg_kernel<4, 16><<<nd, 256, 0, s>>>(d); break;
+    default: throw Error(ST_INVALID, "bad QR variant");
+  }
   PE_HIP(hipGetLastError());
 }
 

@@ -26,14 +26,29 @@ struct TcDesc {
   int32_t tiles_n, tile_base;                      // filled when the op is recorded
   int32_t a_kfast, b_kfast;                        // global->LDS load order
   double alpha, beta;
+  // Split-K (filled when the op is recorded): ksplit slices of kslice
+  // elements each; slice s of tile t writes its partial tile to
+  // part[(t*ksplit + s)*MT*NT], and the workgroup that finishes a tile last
+  // (cnt[t], reset to 0 by it) sums the partials in slice order.
+  int32_t ksplit, kslice;
+  double* part;
+  int32_t* cnt;
 };
 
 // Arithmetic of a contraction.
 enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 // Tile shapes (MT x NT per 256-thread workgroup).
-enum TcTile : int { TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_COUNT = 4 };
-inline int tile_mt(int t) { return t == TT_64x64 ? 64 : t == TT_128x32 ? 128 : t == TT_256x16 ? 256 : 32; }
-inline int tile_nt(int t) { return t == TT_64x64 ? 64 : t == TT_128x32 ? 32 : t == TT_256x16 ? 16 : 128; }
+enum TcTile : int { TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_64x32 = 4, TT_64x16 = 5, TT_COUNT = 6 };
+inline int tile_mt(int t) {
+  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64};
+  return v[t];
+}
+inline int tile_nt(int t) {
+  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16};
+  return v[t];
+}
+// Statistics slot of a contraction variant.
+inline int tc_stat_index(int prec, int out_dt, int tile) { return (prec * 2 + out_dt) * TT_COUNT + tile; }
 
 // out_dt: DT_F64 or DT_F32 (element type of C).  A and B are float64 for
 // TP_F64 and float32 for TP_F32/TP_BF16.
@@ -56,6 +71,9 @@ struct QrDesc {
   int32_t m, n;
 };
 void launch_qr(const QrDesc* d_desc, int n_desc, hipStream_t s);
+// Register-resident variant for blocks up to m x n (-1 when none fits) and its launch.
+int qr_variant_for(int m, int n);
+void launch_qr_reg(int variant, const QrDesc* d_desc, int n_desc, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Deterministic sums: out = sum_i x_i * y_i (y null -> sum x_i^2), in two

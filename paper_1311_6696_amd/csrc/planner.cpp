@@ -349,7 +349,7 @@ static Mps closing_mps(const Lattice& L, int side) {
 
 void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
   Arena call(&ctx.pool);
-  Rec rec(&ctx);
+  Rec rec(&ctx, &call);
   Scratch scr(call);
   int maxLr = 0;
   for (peps_env* e : envs) {
@@ -468,6 +468,7 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
       j.Tout->truncated = !j.exact;
       for (void* p : j.scratch) scr.put(p);
     }
+    rec.flush(call);   // the GPU starts on this row while the next one is planned
   }
   rec.run(call);
   // log-scales (FP64 on the host) and diagnostics

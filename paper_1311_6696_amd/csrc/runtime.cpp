@@ -58,20 +58,25 @@ void Pool::trim() {
 }
 
 Ctx::~Ctx() {
-  if (pinned) dev::host_free(pinned);
+  if (split_cnt) pool.release(split_cnt);
+  for (auto& p : pinned_free) dev::host_free(p.second);
 }
 
-void* Ctx::staging(size_t bytes) {
-  if (bytes > pinned_cap) {
-    if (pinned) {
-      dev::sync(stream);
-      dev::host_free(pinned);
-    }
-    pinned_cap = std::max(bytes, pinned_cap * 2);
-    pinned = dev::host_alloc(pinned_cap);
+void* Ctx::pinned_get(size_t bytes) {
+  auto it = pinned_free.lower_bound(bytes);
+  if (it != pinned_free.end()) {
+    void* p = it->second;
+    pinned_free.erase(it);
+    return p;
   }
-  return pinned;
+  size_t cap = 1 << 16;
+  while (cap < bytes) cap <<= 1;
+  void* p = dev::host_alloc(cap);
+  pinned_size[p] = cap;
+  return p;
 }
+
+void Ctx::pinned_put(void* p, size_t) { pinned_free.emplace(pinned_size[p], p); }
 
 // ----------------------------------------------------------------- views ----
 TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_t>& dims) {
@@ -212,27 +217,74 @@ size_t Rec::push_bytes(const void* p, size_t n) {
   return off;
 }
 
-static int pick_tile(const TcDesc& d) {
-  if (d.N <= 16) return TT_256x16;
-  if (d.N <= 32) return TT_128x32;
-  if (d.M <= 32 && d.N >= 128) return TT_32x128;
-  return TT_64x64;
+// Tile shape of one grouped launch: the candidates fitting the largest N in
+// the batch, largest first; the first one that still gives every CU two
+// workgroups wins (else the smallest), so small-K stages fill the chip.
+static int pick_tile(const std::vector<TcDesc>& ds) {
+  int maxN = 0, maxM = 0;
+  for (const auto& d : ds) {
+    maxN = std::max(maxN, d.N);
+    maxM = std::max(maxM, d.M);
+  }
+  std::vector<int> cand;
+  if (maxN <= 16) cand = {TT_256x16, TT_64x16};
+  else if (maxN <= 32) cand = {TT_128x32, TT_64x32};
+  else if (maxM <= 32) cand = {TT_32x128};
+  else cand = {TT_64x64, TT_64x32};
+  constexpr int64_t WANT = 2 * 256;
+  for (int t : cand) {
+    int64_t tiles = 0;
+    for (const auto& d : ds)
+      tiles += (int64_t)((d.M + tile_mt(t) - 1) / tile_mt(t)) * ((d.N + tile_nt(t) - 1) / tile_nt(t));
+    if (tiles >= WANT) return t;
+  }
+  return cand.back();
 }
 
 void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
-  // one tile shape per launch: the shape of the largest problem decides
-  size_t big = 0;
-  for (size_t i = 1; i < ds.size(); ++i)
-    if ((double)ds[i].M * ds[i].N > (double)ds[big].M * ds[big].N) big = i;
-  const int tile = pick_tile(ds[big]);
+  const int tile = pick_tile(ds);
   const int mt = tile_mt(tile), nt = tile_nt(tile);
-  int64_t tiles = 0;
+  const int kt = prec == TP_BF16 ? 32 : 16;
+  // Split K when the launch would leave most CUs idle and K is long: each
+  // slice keeps at least 4 chunks of K.
+  int64_t plain = 0, maxK = 0;
+  for (const auto& d : ds) {
+    plain += (int64_t)((d.M + mt - 1) / mt) * ((d.N + nt - 1) / nt);
+    maxK = std::max<int64_t>(maxK, d.K);
+  }
+  int ksplit = 1;
+  if (scratch_ && plain < 256 && maxK >= 8 * kt && plain <= Ctx::SPLIT_CNT) {
+    ksplit = (int)std::min<int64_t>({32, (512 + plain - 1) / plain, maxK / (4 * kt)});
+    if (ksplit < 2) ksplit = 1;
+  }
+  double* part = nullptr;
+  if (ksplit > 1) {
+    part = (double*)scratch_->alloc(sizeof(double) * (size_t)plain * ksplit * mt * nt);
+    if (!ctx_->split_cnt) {
+      ctx_->split_cnt = (int32_t*)ctx_->pool.alloc(sizeof(int32_t) * Ctx::SPLIT_CNT);
+      EwDesc z;
+      std::memset(&z, 0, sizeof(z));
+      z.kind = EW_FILL;
+      z.dst = ctx_->split_cnt;
+      z.dst_dt = DT_F32;   // 0.0f has the bit pattern of int 0
+      z.src_dt = DT_F32;
+      z.n = Ctx::SPLIT_CNT;
+      ew({z});
+    }
+  }
+  int64_t tiles = 0, tbase = 0;
   double fl = 0.0;
   for (auto& d : ds) {
     d.tiles_n = (d.N + nt - 1) / nt;
+    const int64_t dt = (int64_t)((d.M + mt - 1) / mt) * d.tiles_n;
+    d.ksplit = ksplit;
+    d.kslice = ksplit > 1 ? (int)(((d.K + ksplit - 1) / ksplit + kt - 1) / kt * kt) : d.K;
+    d.part = part ? part + tbase * ksplit * mt * nt : nullptr;
+    d.cnt = ksplit > 1 ? ctx_->split_cnt + tbase : nullptr;
     d.tile_base = (int32_t)tiles;
-    tiles += (int64_t)((d.M + mt - 1) / mt) * d.tiles_n;
+    tiles += dt * ksplit;
+    tbase += dt;
     fl += 2.0 * d.M * (double)d.N * d.K;
   }
   PE_REQUIRE(tiles < INT_MAX, "too many tiles in one launch");
@@ -244,8 +296,15 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
 
 void Rec::qr(const std::vector<QrDesc>& ds) {
   if (ds.empty()) return;
-  for (const auto& d : ds) PE_REQUIRE(d.m >= d.n && d.n >= 1 && d.n <= 1024, "QR shape");
-  ops_.push_back(Op{OK_QR, 0, 0, 0, (int)ds.size(), (int)ds.size(), push_bytes(ds.data(), ds.size() * sizeof(QrDesc)), 0.0});
+  int mm = 0, nn = 0;
+  for (const auto& d : ds) {
+    PE_REQUIRE(d.m >= d.n && d.n >= 1 && d.n <= 1024, "QR shape");
+    mm = std::max(mm, d.m);
+    nn = std::max(nn, d.n);
+  }
+  const int variant = qr_variant_for(mm, nn);
+  ops_.push_back(Op{OK_QR, 0, 0, variant, (int)ds.size(), (int)ds.size(),
+                    push_bytes(ds.data(), ds.size() * sizeof(QrDesc)), 0.0});
 }
 
 void Rec::reduce(std::vector<RedDesc> ds) {
@@ -283,17 +342,16 @@ void* Rec::aux(Arena& arena, const void* data, size_t bytes) {
   return d;
 }
 
-void Rec::run(Arena& arena) {
+void Rec::flush(Arena& arena) {
   if (ops_.empty()) return;
   hipStream_t s = ctx_->stream;
   uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
   double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
-  void* host = ctx_->staging(blob_.size());
+  void* host = ctx_->pinned_get(blob_.size());
+  pinned_.push_back({host, blob_.size()});
   std::memcpy(host, blob_.data(), blob_.size());
   dev::h2d(dblob, host, blob_.size(), s);
   for (auto& a : aux_) dev::d2d(a.first, dblob + a.second.first, a.second.second, s);
-  std::vector<std::pair<void*, void*>> evs;
-  std::vector<int> ev_op;
   for (size_t i = 0; i < ops_.size(); ++i) {
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
@@ -304,7 +362,10 @@ void Rec::run(Arena& arena) {
     }
     switch (op.kind) {
       case OK_TC: launch_tc(op.prec, op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
-      case OK_QR: launch_qr((const QrDesc*)d, op.nd, s); break;
+      case OK_QR:
+        if (op.tile >= 0) launch_qr_reg(op.tile, (const QrDesc*)d, op.nd, s);
+        else launch_qr((const QrDesc*)d, op.nd, s);
+        break;
       case OK_RED: launch_reduce((const RedDesc*)d, op.nd, op.grid, partials, s); break;
       case OK_EW: launch_ew((const EwDesc*)d, op.nd, op.grid, s); break;
       case OK_SEP: launch_sep((const SepDesc*)d, op.nd, s); break;
@@ -312,25 +373,44 @@ void Rec::run(Arena& arena) {
     if (e0) {
       void* e1 = dev::event_create();
       dev::event_record(e1, s);
-      evs.push_back({e0, e1});
-      ev_op.push_back((int)i);
+      events_.push_back({{e0, e1}, {tc_stat_index(op.prec, op.out_dt, op.tile), op.flops}});
     }
-  }
-  // the staging buffer and descriptors must stay valid until the stream drains
-  dev::sync(s);
-  for (size_t j = 0; j < evs.size(); ++j) {
-    const Op& op = ops_[ev_op[j]];
-    const int key = op.prec * 8 + op.out_dt * 4 + op.tile;
-    ctx_->st_ms[key] += dev::event_ms(evs[j].first, evs[j].second);
-    ctx_->st_flops[key] += op.flops;
-    ctx_->st_launch[key] += 1;
-    dev::event_destroy(evs[j].first);
-    dev::event_destroy(evs[j].second);
   }
   ops_.clear();
   blob_.clear();
   aux_.clear();
   partials_ = 0;
+}
+
+void Rec::run(Arena& arena) {
+  flush(arena);
+  // staging buffers and descriptors stay valid until the stream drains
+  dev::sync(ctx_->stream);
+  for (auto& e : events_) {
+    const int key = e.second.first;
+    ctx_->st_ms[key] += dev::event_ms(e.first.first, e.first.second);
+    ctx_->st_flops[key] += e.second.second;
+    ctx_->st_launch[key] += 1;
+    dev::event_destroy(e.first.first);
+    dev::event_destroy(e.first.second);
+  }
+  events_.clear();
+  for (auto& p : pinned_) ctx_->pinned_put(p.first, p.second);
+  pinned_.clear();
+}
+
+Rec::~Rec() {
+  if (!pinned_.empty() || !events_.empty()) {
+    try {
+      dev::sync(ctx_->stream);
+    } catch (...) {
+    }
+    for (auto& e : events_) {
+      dev::event_destroy(e.first.first);
+      dev::event_destroy(e.first.second);
+    }
+    for (auto& p : pinned_) ctx_->pinned_put(p.first, p.second);
+  }
 }
 
 }  // namespace pe

@@ -74,7 +74,8 @@ TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha = 1.0, doubl
 struct Ctx;
 class Rec {
  public:
-  explicit Rec(Ctx* c) : ctx_(c) {}
+  // `scratch` (optional) provides record-time workspace, e.g. split-K partials.
+  explicit Rec(Ctx* c, Arena* scratch = nullptr) : ctx_(c), scratch_(scratch) {}
   void tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic = true);
   void qr(const std::vector<QrDesc>& ds);
   void reduce(std::vector<RedDesc> ds);
@@ -82,8 +83,12 @@ class Rec {
   void sep(const std::vector<SepDesc>& ds);
   // Device copy of host data, available to every op recorded after this call.
   void* aux(Arena& arena, const void* data, size_t bytes);
-  // Upload, launch everything, and clear.  Scratch of `arena` must outlive the launch.
+  // Upload and launch everything recorded so far (no wait).  Device memory
+  // for descriptors comes from `arena`, which must outlive the stream work.
+  void flush(Arena& arena);
+  // flush(), wait for the stream, collect profiling statistics.
   void run(Arena& arena);
+  ~Rec();
   double flops() const { return flops_; }
 
  private:
@@ -94,11 +99,14 @@ class Rec {
   };
   size_t push_bytes(const void* p, size_t n);
   Ctx* ctx_;
+  Arena* scratch_;
   std::vector<Op> ops_;
   std::vector<uint8_t> blob_;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
   int partials_ = 0;
   double flops_ = 0.0;
+  std::vector<std::pair<void*, size_t>> pinned_;   // staging buffers in flight
+  std::vector<std::pair<std::pair<void*, void*>, std::pair<int, double>>> events_;
 };
 
 // ---------------------------------------------------------------- context ---
@@ -108,14 +116,19 @@ struct Ctx {
   Pool pool;
   size_t scratch_budget = size_t(48) << 30;
   bool profile = false;
-  static constexpr int NSTAT = 24;
+  static constexpr int NSTAT = 3 * 2 * TT_COUNT;
   double st_flops[NSTAT] = {0};
   double st_ms[NSTAT] = {0};
   int64_t st_launch[NSTAT] = {0};
-  void* pinned = nullptr;
-  size_t pinned_cap = 0;
+  // split-K tile counters: zero between launches (the last workgroup of a
+  // tile resets its counter), shared by every split contraction in order
+  static constexpr int SPLIT_CNT = 1 << 16;
+  int32_t* split_cnt = nullptr;
+  std::multimap<size_t, void*> pinned_free;     // pinned staging buffers by capacity
+  std::unordered_map<void*, size_t> pinned_size;
   ~Ctx();
-  void* staging(size_t bytes);
+  void* pinned_get(size_t bytes);
+  void pinned_put(void* p, size_t bytes);
 };
 
 // ----------------------------------------------------------- environment ---
