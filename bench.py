@@ -6,6 +6,7 @@ PEPS (top and bottom boundaries by ALS row absorption, then the norm, 64
 sandwiches), inputs resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+                    [--workloads precision,clusters,instances]
 """
 import argparse
 import json
@@ -43,6 +44,113 @@ def energy(r):
     return float(np.sum(r["bond_h"]) + np.sum(r["bond_v"]))
 
 
+def timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) / reps
+
+
+def side_precision(sess, binding, torch):
+    """10x10, D=6, unit-norm Gaussian sites, chi=72: one full environment per
+    dtype; errors are against the FP64 GPU path (the FP64 path itself is
+    checked against the oracle on the smaller lattices)."""
+    from paper_1311_6696_amd.inputs import CONFIGS, config_peps
+    cfg = CONFIGS[3]
+    st = binding.to_device(config_peps(3))
+    out, ref = {}, None
+    for dt in ("f64", "f32", "bf16"):
+        note(f"precision workload {dt}")
+        run = lambda: run_steps(sess, st, cfg["chi"], dt, 4, 1)
+        run()   # warm-up (allocations)
+        r, t = timed(torch, run, 1)
+        if ref is None:
+            ref = r
+        e, e0 = energy(r), energy(ref)
+        out[dt] = {"env_per_s": 1.0 / t, "s_per_env": t, "tflops": r["flops"] / t / 1e12,
+                   "pct_peak": 100.0 * r["flops"] / t / 1e12 / PEAK[dt], "tflop_per_env": r["flops"] / 1e12,
+                   "rel_energy_err_vs_f64": abs(e - e0) / abs(e0),
+                   "max_bond_err_vs_f64": float(max(np.max(np.abs(r["bond_h"] - ref["bond_h"])),
+                                                    np.max(np.abs(r["bond_v"] - ref["bond_v"]))))}
+        out[dt]["speedup_vs_f64"] = out["f64"]["s_per_env"] / t
+    out["workload"] = "10x10 OBC PEPS, d=2, D=6, N(0,1) unit-norm sites, chi=72, 4 half-sweeps"
+    return out
+
+
+def side_clusters(sess, binding, torch):
+    """16x16, D=6, near-product, chi=36: all 256 n x n windows per call, FP32
+    contractions (FP64 QR and norms)."""
+    from paper_1311_6696_amd.inputs import CONFIGS, config_peps
+    cfg = CONFIGS[4]
+    L = cfg["L"]
+    st = binding.to_device(config_peps(4))
+    out = {}
+    for n in cfg["ns"]:
+        wins = []
+        for i in range(L):
+            for j in range(L):
+                r0, r1 = max(0, i - (n + 1) // 2 + 1), min(L - 1, i + n // 2)
+                c0, c1 = max(0, j - (n + 1) // 2 + 1), min(L - 1, j + n // 2)
+                wins.append((0, r0, r1, c0, c1, i, j))
+        note(f"cluster workload n={n}")
+
+        def run():
+            envs = sess.cluster_env([st], wins, cfg["chi"], "f32", 4)
+            res = sess.expect(envs)
+            for e in envs:
+                e.free()
+            return res
+        run()
+        res, t = timed(torch, run, 1)
+        fl = sum(r["flops"] for r in res)
+        out[f"n{n}"] = {"windows": len(wins), "windows_per_s": len(wins) / t, "s_per_call": t,
+                        "tflops": fl / t / 1e12, "pct_f32_peak": 100.0 * fl / t / 1e12 / PEAK["f32"],
+                        "tflop_per_call": fl / 1e12}
+    out["workload"] = "16x16 OBC PEPS, d=2, D=6, near-product, chi=36, all 256 windows per n, FP32 contractions"
+    return out
+
+
+def side_instances(sess, binding, torch):
+    """Independent lattices of mixed L and D in one call, chi = D^2.  The
+    draw's D=8 instances (87 to 645 TFLOP each in FP64) exceed this
+    measurement's time budget; the D <= 5 instances of the draw are run."""
+    from paper_1311_6696_amd.inputs import batched_instances
+    pairs, insts = batched_instances()
+    keep = [k for k, (L, D) in enumerate(pairs) if D <= 5]
+    out = {}
+    states = [binding.to_device(insts[k]) for k in keep]
+    chis = [pairs[k][1] ** 2 for k in keep]
+    for dt in ("f64", "bf16"):
+        note(f"instances workload {dt}")
+
+        def run():
+            # one call, one options record (chi = D^2) per lattice
+            envs = sess.env_boundary(states, chis, dt, 4)
+            res = sess.expect(envs)
+            for e in envs:
+                e.free()
+            return res
+        run()
+        res, t = timed(torch, run, 1)
+        fl = sum(r["flops"] for r in res)
+        out[dt] = {"instances": len(keep), "instances_per_s": len(keep) / t, "s_per_batch": t,
+                   "tflops": fl / t / 1e12, "tflop_per_batch": fl / 1e12}
+        if dt == "f64":
+            ref = res
+        else:
+            out[dt]["max_rel_energy_err_vs_f64"] = float(max(abs(energy(a) - energy(b)) / abs(energy(b))
+                                                             for a, b in zip(res, ref)))
+            out[dt]["speedup_vs_f64"] = out["f64"]["s_per_batch"] / t
+    out["workload"] = ("the D<=5 instances of 32 seeded lattices (L in 6..12, D in {3,4,5,8}, chi=D^2, "
+                       f"U[0,1) entries): {len(keep)} lattices in one call")
+    return out
+
+
+SIDE = {"precision": side_precision, "clusters": side_clusters, "instances": side_instances}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +161,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32/BF16 measurements")
     ap.add_argument("--batch", type=int, default=8,
                     help="lattices per call of the batched side measurement (1 = skip)")
+    ap.add_argument("--workloads", default="",
+                    help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
+                         "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path has no multi-GPU component); got --gpus {args.gpus}",
@@ -167,6 +278,12 @@ def main():
                               "max_bond_err_vs_f64": float(max(np.max(np.abs(r["bond_h"] - res["bond_h"])),
                                                                np.max(np.abs(r["bond_v"] - res["bond_v"]))))}
         out["precision_forms"] = forms
+
+    side = [w for w in args.workloads.split(",") if w]
+    if side:
+        out["workloads"] = {}
+    for w in side:
+        out["workloads"][w] = SIDE[w](sess, binding, torch)
 
     if not args.no_cpu:
         note("oracle cpu baseline")

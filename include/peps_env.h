@@ -75,9 +75,14 @@ typedef struct {
   int32_t chi;          /* boundary bond dimension D' >= 1 */
   int32_t dtype;        /* peps_dtype */
   int32_t halfsweeps;   /* ALS half-sweeps per truncated row, >= 1 (default 4 if 0) */
-  int32_t flags;        /* reserved, 0 */
+  int32_t flags;        /* 0, or PEPS_OPTS_PER_STATE (peps_env_boundary only) */
   uint64_t seed;        /* SplitMix64 key of the ALS start tensors */
 } peps_env_opts;
+
+/* opts.flags: the options argument of peps_env_boundary points to one
+ * record per state (every record carries the flag); chi, dtype, halfsweeps
+ * and seed may then differ between the lattices of one batched run. */
+#define PEPS_OPTS_PER_STATE 1
 
 /* Cluster window around the centre site (ci, cj) of state `state`,
  * rows r0..r1 and columns c0..c1 inclusive, centre inside the window. */
@@ -109,8 +114,9 @@ peps_status peps_ctx_create(int32_t device, void* hip_stream, peps_ctx** out);
 void peps_ctx_destroy(peps_ctx* ctx);
 
 /* Top and bottom boundaries of n_states lattices (one batched run).
- * opts points to one options record used for all states.  On success
- * out[i] receives a new environment handle per state. */
+ * opts points to one options record used for all states, or to n_states
+ * records when its flags hold PEPS_OPTS_PER_STATE.  On success out[i]
+ * receives a new environment handle per state. */
 peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_states,
                               const peps_env_opts* opts, peps_env** out);
 

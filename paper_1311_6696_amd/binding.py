@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpepsenv.
 PEPS_F64, PEPS_F32, PEPS_BF16 = 0, 1, 2
 DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
 STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
+OPTS_PER_STATE = 1   # peps_env_opts.flags: one options record per state
 DEFAULT_SEED = 0x13116696
 TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16")
 N_STATS = 3 * 2 * len(TILES)
@@ -164,11 +165,22 @@ class Context:
                     int(seed) & ((1 << 64) - 1))
 
     def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+        """chi: one value for all states, or a sequence with one per state
+        (passed as per-state options records)."""
         n = len(states)
         arr = (State * n)(*[s.struct() for s in states])
         out = (C.c_void_p * n)()
-        o = self.opts(chi, dtype, halfsweeps, seed)
-        _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, C.byref(o), out))
+        if np.ndim(chi) == 0:
+            o = self.opts(chi, dtype, halfsweeps, seed)
+            _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, C.byref(o), out))
+        else:
+            if len(chi) != n:
+                raise ValueError("one chi per state")
+            recs = [self.opts(c, dtype, halfsweeps, seed) for c in chi]
+            for r in recs:
+                r.flags = OPTS_PER_STATE
+            o = (Opts * n)(*recs)
+            _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, o, out))
         return [Env(self, out[i], s.rows, s.cols) for i, s in enumerate(states)]
 
     def cluster_env_raw(self, states, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):

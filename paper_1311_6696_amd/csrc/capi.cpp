@@ -61,12 +61,12 @@ void validate_state(const peps_state& s, int idx) {
     }
 }
 
-Opts make_opts(const peps_env_opts* o) {
+Opts make_opts(const peps_env_opts* o, int32_t allowed_flags = 0) {
   PE_REQUIRE(o != nullptr, "opts must not be NULL");
   PE_REQUIRE(o->chi >= 1, "chi must be >= 1");
   PE_REQUIRE(o->dtype >= PEPS_F64 && o->dtype <= PEPS_BF16, "unknown dtype");
   PE_REQUIRE(o->halfsweeps >= 0 && o->halfsweeps <= 64, "halfsweeps must be in [0, 64]");
-  PE_REQUIRE(o->flags == 0, "flags must be 0");
+  PE_REQUIRE((o->flags & ~allowed_flags) == 0, "unsupported flags");
   Opts r;
   r.chi = o->chi;
   r.dtype = o->dtype;
@@ -160,12 +160,20 @@ peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_sta
   peps_status s = guarded([&] {
     PE_REQUIRE(ctx && st && out, "ctx, st and out must not be NULL");
     PE_REQUIRE(n_states >= 1, "n_states must be >= 1");
-    const Opts o = make_opts(opts);
+    PE_REQUIRE(opts != nullptr, "opts must not be NULL");
+    const bool per_state = (opts->flags & PEPS_OPTS_PER_STATE) != 0;
+    std::vector<Opts> os;
+    for (int i = 0; i < n_states; ++i) {
+      const peps_env_opts* oi = per_state ? opts + i : opts;
+      PE_REQUIRE(!per_state || (oi->flags & PEPS_OPTS_PER_STATE), "every per-state options record carries the flag");
+      os.push_back(make_opts(oi, PEPS_OPTS_PER_STATE));
+    }
     for (int i = 0; i < n_states; ++i) validate_state(st[i], i);
     dev::set_device(ctx->c->device);
     Arena tmp(&ctx->c->pool);
     Rec rec(ctx->c.get());
     for (int i = 0; i < n_states; ++i) {
+      const Opts& o = os[i];
       auto* e = new peps_env(ctx->c);
       made.push_back(e);
       e->opts = o;

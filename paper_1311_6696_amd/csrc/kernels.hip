@@ -1,4 +1,6 @@
 // Device kernels of libpepsenv (gfx950 / CDNA4).
+#include <climits>
+
 #include "kernels.hpp"
 
 namespace pe {
@@ -102,32 +104,40 @@ struct PolBF16 {
   }
 };
 
-template <class T>
-__device__ inline T ld_zero() { return T(0); }
+// Shared-memory staging of one workgroup of tc_kernel.
+template <class L, int MT, int NT, int KT>
+struct TcSmem {
+  L As[KT][MT + 2];
+  L Bs[KT][NT + 2];
+  int64_t oAm[MT], oCm[MT], oBn[NT], oCn[NT], oAk[KT], oBk[KT];
+};
 
+// One output tile (or one K-slice of it) of descriptor d; `wg` numbers the
+// tile's workgroup slot inside the descriptor.
 template <class P, class TC, int MT, int NT, int WM, int WN>
-__global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, int nd) {
+__device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT, NT, P::KT>& sm) {
   using T = typename P::T;
   using L = typename P::L;
   constexpr int KT = P::KT;
   constexpr int WTM = MT / WM, WTN = NT / WN, MB = WTM / 16, NB = WTN / 16;
   constexpr int EA = MT * KT / 256, EB = NT * KT / 256;
   static_assert(EA >= 1 && EB >= 1 && MB >= 1 && NB >= 1, "tile");
-  __shared__ L As[KT][MT + 2];
-  __shared__ L Bs[KT][NT + 2];
-  __shared__ int64_t oAm[MT], oCm[MT], oBn[NT], oCn[NT], oAk[KT], oBk[KT];
+  auto& As = sm.As;
+  auto& Bs = sm.Bs;
+  int64_t* oAm = sm.oAm;
+  int64_t* oCm = sm.oCm;
+  int64_t* oBn = sm.oBn;
+  int64_t* oCn = sm.oCn;
+  int64_t* oAk = sm.oAk;
+  int64_t* oBk = sm.oBk;
 
-  const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
-  int lo = 0, hi = nd - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ds[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
-  }
-  const TcDesc& d = ds[lo];
+  // The empty asm hides the thread index from loop-invariant hoisting across
+  // the tile loop: hoisted per-thread addresses would stay live in VGPRs
+  // for the whole walk and cost a wave of occupancy.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int M = d.M, N = d.N;
   const int ksplit = d.ksplit;
-  const int wg = bid - d.tile_base;
   const int t = wg / ksplit, slice = wg - t * ksplit;
   const int m0 = (t / d.tiles_n) * MT, n0 = (t % d.tiles_n) * NT;
   const int kbeg = slice * d.kslice;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
       if (a_kfast) { kk = tid % KT; mm = tid / KT + e * (256 / KT); }
       else { mm = tid % MT; kk = tid / MT + e * (256 / MT); }
       const bool ok = (m0 + mm < M) && (k0 + kk < K);
-      ra[e] = ok ? A[oAm[mm] + oAk[kk]] : ld_zero<T>();
+      ra[e] = ok ? A[oAm[mm] + oAk[kk]] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
       if (b_kfast) { kk = tid % KT; nn = tid / KT + e * (256 / KT); }
       else { nn = tid % NT; kk = tid / NT + e * (256 / NT); }
       const bool ok = (n0 + nn < N) && (k0 + kk < K);
-      rb[e] = ok ? B[oBn[nn] + oBk[kk]] : ld_zero<T>();
+      rb[e] = ok ? B[oBn[nn] + oBk[kk]] : T(0);
     }
   };
   auto store = [&]() {
@@ -275,9 +285,8 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
         }
     return;
   }
-  // split-K: publish this slice's partial tile; the last slice to arrive
-  // sums all partials of the tile in slice order (deterministic) and stores.
-  __shared__ int s_last;
+  // split-K: this slice's partial tile, m fastest (coalesced for the
+  // reduction, whose stores run along m)
   double* __restrict__ part = d.part + ((int64_t)t * ksplit + slice) * (MT * NT);
 #pragma unroll
   for (int i = 0; i < MB; ++i)
@@ -287,44 +296,46 @@ __global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, 
       for (int r = 0; r < 4; ++r) {
         const int ml = wm * WTM + i * 16 + (lane & 15);
         const int nl = wn * WTN + j * 16 + P::row(lane, r);
-        part[ml * NT + nl] = (double)acc[i][j][r];
+        part[nl * MT + ml] = (double)acc[i][j][r];
       }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(d.cnt + t, 1) == ksplit - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const double* __restrict__ tp = d.part + (int64_t)t * ksplit * (MT * NT);
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ml = wm * WTM + i * 16 + (lane & 15);
-        const int nl = wn * WTN + j * 16 + P::row(lane, r);
-        if (m0 + ml < M && n0 + nl < N) {
-          double sum = 0.0;
-          for (int q = 0; q < ksplit; ++q) sum += tp[(int64_t)q * (MT * NT) + ml * NT + nl];
-          const int64_t off = oCm[ml] + oCn[nl];
-          double v = alpha * sum;
-          if (beta != 0.0) v += beta * (double)C[off];
-          C[off] = (TC)v;
-        }
-      }
-  if (tid == 0) d.cnt[t] = 0;
 }
+
+// Grouped contraction: workgroup slots are numbered consecutively across
+// the descriptors (tile_base); each workgroup walks the slots bid,
+// bid + gridDim.x, ... so that large launches run a resident grid.  The
+// owning descriptor only moves forward along that walk.
+template <class P, class TC, int MT, int NT, int WM, int WN>
+__global__ __launch_bounds__(256) void tc_kernel(const TcDesc* __restrict__ ds, int nd, int nslots) {
+  __shared__ TcSmem<typename P::L, MT, NT, P::KT> sm;
+  int lo = 0;
+  for (int bid = blockIdx.x; bid < nslots; bid += gridDim.x) {
+    if (lo + 1 < nd && ds[lo + 1].tile_base <= bid) {
+      int a = lo + 1, b = nd - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ds[mid].tile_base <= bid) a = mid; else b = mid - 1;
+      }
+      lo = a;
+    }
+    tc_tile<P, TC, MT, NT, WM, WN>(ds[lo], bid - ds[lo].tile_base, sm);
+    __syncthreads();   // shared offsets and staging are rewritten by the next slot
+  }
+}
+
+// Resident workgroups per launch for large groups: 256 CUs, several
+// workgroups of 256 threads each.
+constexpr int TC_GRID_CAP = 256 * 8;
 
 template <class P, class TC>
 static void launch_tc_tile(int tile, const TcDesc* d, int nd, int nt, hipStream_t s) {
+  const int g = nt < TC_GRID_CAP ? nt : TC_GRID_CAP;
   switch (tile) {
-    case TT_64x64: tc_kernel<P, TC, 64, 64, 2, 2><<<nt, 256, 0, s>>>(d, nd); break;
-    case TT_128x32: tc_kernel<P, TC, 128, 32, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
-    case TT_256x16: tc_kernel<P, TC, 256, 16, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
-    case TT_32x128: tc_kernel<P, TC, 32, 128, 1, 4><<<nt, 256, 0, s>>>(d, nd); break;
-    case TT_64x32: tc_kernel<P, TC, 64, 32, 2, 2><<<nt, 256, 0, s>>>(d, nd); break;
-    case TT_64x16: tc_kernel<P, TC, 64, 16, 4, 1><<<nt, 256, 0, s>>>(d, nd); break;
+    case TT_64x64: tc_kernel<P, TC, 64, 64, 2, 2><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_128x32: tc_kernel<P, TC, 128, 32, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_256x16: tc_kernel<P, TC, 256, 16, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_32x128: tc_kernel<P, TC, 32, 128, 1, 4><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_64x32: tc_kernel<P, TC, 64, 32, 2, 2><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_64x16: tc_kernel<P, TC, 64, 16, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
     default: throw Error(ST_INVALID, "bad tile");
   }
 }
@@ -341,6 +352,65 @@ void launch_tc(int prec, int out_dt, int tile, const TcDesc* d, int nd, int nt, 
     if (out_dt == DT_F64) launch_tc_tile<PolBF16, double>(tile, d, nd, nt, s);
     else launch_tc_tile<PolBF16, float>(tile, d, nd, nt, s);
   }
+  PE_HIP(hipGetLastError());
+}
+
+// Split-K reduction: one thread per output element (256 per workgroup,
+// MT*NT/256 workgroups per tile); the partial slices are summed in slice
+// order, so the result does not depend on scheduling.
+template <class TC>
+__global__ __launch_bounds__(256) void tc_reduce_kernel(const TcDesc* __restrict__ ds, int nd, int mt, int nt) {
+  const int per_tile = mt * nt / 256;
+  const int tile = blockIdx.x / per_tile;
+  const int e = (blockIdx.x - tile * per_tile) * 256 + threadIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].tile_base / ds[mid].ksplit <= tile) lo = mid; else hi = mid - 1;
+  }
+  const TcDesc& d = ds[lo];
+  const int t = tile - d.tile_base / d.ksplit;
+  const int ml = e % mt, nl = e / mt;
+  int m = (t / d.tiles_n) * mt + ml, n = (t % d.tiles_n) * nt + nl;
+  if (m >= d.M || n >= d.N) return;
+  int64_t off = 0;
+  for (int j = d.nm - 1; j >= 0; --j) {
+    const int dj = d.dm[j];
+    off += (int64_t)(m % dj) * d.sCm[j];
+    m /= dj;
+  }
+  for (int j = d.nn - 1; j >= 0; --j) {
+    const int dj = d.dn[j];
+    off += (int64_t)(n % dj) * d.sCn[j];
+    n /= dj;
+  }
+  const int64_t sz = (int64_t)mt * nt;
+  const double* __restrict__ tp = d.part + (int64_t)t * d.ksplit * sz + e;
+  const int ks = d.ksplit;
+  double sum = 0.0;
+  int q = 0;
+  for (; q + 4 <= ks; q += 4) {   // four independent loads in flight, summed in order
+    const double v0 = tp[(q + 0) * sz], v1 = tp[(q + 1) * sz], v2 = tp[(q + 2) * sz], v3 = tp[(q + 3) * sz];
+    sum += v0;
+    sum += v1;
+    sum += v2;
+    sum += v3;
+  }
+  for (; q < ks; ++q) sum += tp[q * sz];
+  TC* __restrict__ C = (TC*)d.C;
+  double v = d.alpha * sum;
+  if (d.beta != 0.0) v += d.beta * (double)C[off];
+  C[off] = (TC)v;
+}
+
+void launch_tc_reduce(int out_dt, int tile, const TcDesc* d, int nd, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return;
+  const int mt = tile_mt(tile), nt = tile_nt(tile);
+  if ((mt * nt) % 256 != 0) throw Error(ST_INVALID, "bad tile");
+  const int64_t grid = (int64_t)n_tiles * (mt * nt / 256);
+  if (grid > INT_MAX) throw Error(ST_INVALID, "split-K reduction too large");
+  if (out_dt == DT_F64) tc_reduce_kernel<double><<<(int)grid, 256, 0, s>>>(d, nd, mt, nt);
+  else tc_reduce_kernel<float><<<(int)grid, 256, 0, s>>>(d, nd, mt, nt);
   PE_HIP(hipGetLastError());
 }
 
@@ -428,35 +498,35 @@ void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
 }
 
 // ===========================================================================
-// Register-resident Householder QR for blocks with m <= 64*RPW, n <= 4*NCW:
-// column k lives in wave k%4 (slot k/4), row i in lane i%64 (slot i/64).
+// Register-resident Householder QR for blocks with m <= 64*RPW, n <= NW*NCW:
+// column k lives in wave k%NW (slot k/NW), row i in lane i%64 (slot i/64).
 // Each reflection needs one wave reduction per trailing column and one
-// barrier; the reflectors go to the workspace for the accumulation of Q.
+// barrier.  The reflectors stay in the registers of their owning wave (in
+// place below the diagonal) and are broadcast through shared memory, so no
+// global memory is touched between the first load and the final stores.
 // ===========================================================================
-template <int RPW, int NCW>
-__global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ ds) {
+template <int RPW, int NCW, int NW>
+__global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restrict__ ds) {
   const QrDesc& d = ds[blockIdx.x];
   const int m = d.m, n = d.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NMAX = 4 * NCW, MMAX = 64 * RPW;
+  constexpr int NMAX = NW * NCW, MMAX = 64 * RPW;
   __shared__ double vbuf[2][MMAX];
   __shared__ double scl[2];
   __shared__ double taus[NMAX], rdiag[NMAX];
-  double* __restrict__ V = d.W;   // reflector j at V[j*m .. j*m+m)
   double a[RPW][NCW];
 #pragma unroll
   for (int s = 0; s < RPW; ++s)
 #pragma unroll
     for (int c = 0; c < NCW; ++c) {
-      const int i = lane + 64 * s, k = wave + 4 * c;
+      const int i = lane + 64 * s, k = wave + NW * c;
       a[s][c] = (i < m && k < n) ? d.A[i * d.sAr + k * d.sAc] : 0.0;
     }
   // Reflection loop at run time; register slots are only ever addressed by
   // compile-time indices under uniform predicates (no dynamic indexing).
   for (int j = 0; j < n; ++j) {
-    {
-    const int oc = j >> 2, buf = j & 1;
-    if (wave == (j & 3)) {
+    const int oc = j / NW, buf = j & 1;
+    if (wave == j % NW) {
       double p = 0.0, x0loc = 0.0;
 #pragma unroll
       for (int c = 0; c < NCW; ++c)
@@ -486,7 +556,6 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
             const double v = i > j ? a[s][c] * scal : (i == j ? 1.0 : 0.0);
             if (i > j) a[s][c] = v;
             vbuf[buf][i] = i < m ? v : 0.0;
-            if (i < m) V[(int64_t)j * m + i] = v;
           }
         }
       if (lane == 0) {
@@ -502,7 +571,7 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
     for (int s = 0; s < RPW; ++s) vi[s] = vbuf[buf][lane + 64 * s];
 #pragma unroll
     for (int c = 0; c < NCW; ++c) {
-      const int k = wave + 4 * c;
+      const int k = wave + NW * c;
       if (k > j && k < n) {
         double p = 0.0;
 #pragma unroll
@@ -512,7 +581,6 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
         for (int s = 0; s < RPW; ++s) a[s][c] -= vi[s] * w;
       }
     }
-    }
   }
   __syncthreads();
   if (d.R) {
@@ -520,7 +588,7 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
     for (int s = 0; s < RPW; ++s)
 #pragma unroll
       for (int c = 0; c < NCW; ++c) {
-        const int i = lane + 64 * s, k = wave + 4 * c;
+        const int i = lane + 64 * s, k = wave + NW * c;
         if (i < n && k < n) {
           const double sg = rdiag[i] < 0.0 ? -1.0 : 1.0;
           const double v = i < k ? a[s][c] : (i == k ? rdiag[i] : 0.0);
@@ -528,31 +596,41 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
         }
       }
   }
-  // Q = H_0 ... H_{n-1} [I; 0], accumulated from the last reflector
+  // Q = H_0 ... H_{n-1} [I; 0], accumulated from the last reflector; the
+  // owner of reflector j publishes it (unit diagonal, zeros above) each step.
+  double q[RPW][NCW];
 #pragma unroll
   for (int s = 0; s < RPW; ++s)
 #pragma unroll
-    for (int c = 0; c < NCW; ++c) a[s][c] = (lane + 64 * s == wave + 4 * c) ? 1.0 : 0.0;
+    for (int c = 0; c < NCW; ++c) q[s][c] = (lane + 64 * s == wave + NW * c) ? 1.0 : 0.0;
+  for (int j = n - 1; j >= 0; --j) {
+    const int oc = j / NW, buf = j & 1;
+    if (wave == j % NW) {
 #pragma unroll
-  for (int jj = 0; jj < NMAX; ++jj) {
-    const int j = NMAX - 1 - jj;
-    const double tau = j < n ? taus[j] : 0.0;
+      for (int c = 0; c < NCW; ++c)
+        if (c == oc) {
+#pragma unroll
+          for (int s = 0; s < RPW; ++s) {
+            const int i = lane + 64 * s;
+            vbuf[buf][i] = (i > j && i < m) ? a[s][c] : (i == j ? 1.0 : 0.0);
+          }
+        }
+    }
+    __syncthreads();
+    const double tau = taus[j];
     double vi[RPW];
 #pragma unroll
-    for (int s = 0; s < RPW; ++s) {
-      const int i = lane + 64 * s;
-      vi[s] = (i >= j && i < m) ? V[(int64_t)j * m + i] : 0.0;
-    }
+    for (int s = 0; s < RPW; ++s) vi[s] = vbuf[buf][lane + 64 * s];
 #pragma unroll
     for (int c = 0; c < NCW; ++c) {
-      const int k = wave + 4 * c;
+      const int k = wave + NW * c;
       if (k >= j && k < n) {
         double p = 0.0;
 #pragma unroll
-        for (int s = 0; s < RPW; ++s) p += vi[s] * a[s][c];
+        for (int s = 0; s < RPW; ++s) p += vi[s] * q[s][c];
         const double w = wave_sum(p) * tau;
 #pragma unroll
-        for (int s = 0; s < RPW; ++s) a[s][c] -= vi[s] * w;
+        for (int s = 0; s < RPW; ++s) q[s][c] -= vi[s] * w;
       }
     }
   }
@@ -560,25 +638,32 @@ __global__ __launch_bounds__(256) void qr_reg_kernel(const QrDesc* __restrict__ 
   for (int s = 0; s < RPW; ++s)
 #pragma unroll
     for (int c = 0; c < NCW; ++c) {
-      const int i = lane + 64 * s, k = wave + 4 * c;
-      if (i < m && k < n) d.Q[i * d.sQr + k * d.sQc] = (rdiag[k] < 0.0 ? -1.0 : 1.0) * a[s][c];
+      const int i = lane + 64 * s, k = wave + NW * c;
+      if (i < m && k < n) d.Q[i * d.sQr + k * d.sQc] = (rdiag[k] < 0.0 ? -1.0 : 1.0) * q[s][c];
     }
 }
 
-// Register-resident variants: (rows per lane, columns per wave).
+// Register-resident variants: (rows per lane, columns per wave, waves).
+// Sixteen waves keep two or fewer columns per wave for n <= 32, which
+// shortens the per-reflection critical path.  A lane holds its block
+// entries and the same number of Q entries: at 16 waves per workgroup
+// (128 VGPRs per lane) that allows 16 entries each, at 8 waves 32.
 struct QrVariant {
-  int rpw, ncw;
+  int rpw, ncw, nw;
 };
-constexpr QrVariant QR_VARIANTS[] = {{1, 2}, {1, 4}, {2, 4}, {4, 4}, {4, 8}, {8, 4}, {8, 8}, {16, 4}, {12, 8}, {2, 16}, {4, 16}};
+constexpr QrVariant QR_VARIANTS[] = {{1, 2, 4},  {1, 4, 4},  {1, 1, 16}, {2, 1, 16}, {4, 1, 16},
+                                     {8, 1, 16}, {16, 2, 8}, {2, 2, 16}, {4, 2, 16},
+                                     {8, 2, 16}, {4, 4, 16}};
 constexpr int QR_NVAR = sizeof(QR_VARIANTS) / sizeof(QR_VARIANTS[0]);
 
 int qr_variant_for(int m, int n) {
   int best = -1, cost = 1 << 30;
   for (int v = 0; v < QR_NVAR; ++v) {
     const QrVariant& q = QR_VARIANTS[v];
-    if (64 * q.rpw >= m && 4 * q.ncw >= n && q.rpw * q.ncw < cost) {
+    const int c = q.rpw * q.ncw * 4 + (q.nw == 16 ? 1 : 0);   // registers, then fewer waves
+    if (64 * q.rpw >= m && q.nw * q.ncw >= n && c < cost) {
       best = v;
-      cost = q.rpw * q.ncw;
+      cost = c;
     }
   }
   return best;   // -1: use the streaming kernel
@@ -586,17 +671,17 @@ int qr_variant_for(int m, int n) {
 
 void launch_qr_reg(int variant, const QrDesc* d, int nd, hipStream_t s) {
   switch (variant) {
-    case 0: qr_reg_kernel<1, 2><<<nd, 256, 0, s>>>(d); break;
-    case 1: qr_reg_kernel<1, 4><<<nd, 256, 0, s>>>(d); break;
-    case 2: qr_reg_kernel<2, 4><<<nd, 256, 0, s>>>(d); break;
-    case 3: qr_reg_kernel<4, 4><<<nd, 256, 0, s>>>(d); break;
-    case 4: qr_reg_kernel<4, 8><<<nd, 256, 0, s>>>(d); break;
-    case 5: qr_reg_kernel<8, 4><<<nd, 256, 0, s>>>(d); break;
-    case 6: qr_reg_kernel<8, 8><<<nd, 256, 0, s>>>(d); break;
-    case 7: qr_reg_kernel<16, 4><<<nd, 256, 0, s>>>(d); break;
-    case 8: qr_reg_kernel<12, 8><<<nd, 256, 0, s>>>(d); break;
-    case 9: qr_reg_kernel<2, 16><<<nd, 256, 0, s>>>(d); break;
-    case 10: qr_reg_kernel<4, 16><<<nd, 256, 0, s>>>(d); break;
+    case 0: qr_reg_kernel<1, 2, 4><<<nd, 256, 0, s>>>(d); break;
+    case 1: qr_reg_kernel<1, 4, 4><<<nd, 256, 0, s>>>(d); break;
+    case 2: qr_reg_kernel<1, 1, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 3: qr_reg_kernel<2, 1, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 4: qr_reg_kernel<4, 1, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 5: qr_reg_kernel<8, 1, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 6: qr_reg_kernel<16, 2, 8><<<nd, 512, 0, s>>>(d); break;
+    case 7: qr_reg_kernel<2, 2, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 8: qr_reg_kernel<4, 2, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 9: qr_reg_kernel<8, 2, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 10: qr_reg_kernel<4, 4, 16><<<nd, 1024, 0, s>>>(d); break;
     default: throw Error(ST_INVALID, "bad QR variant");
   }
   PE_HIP(hipGetLastError());

@@ -27,12 +27,10 @@ struct TcDesc {
   int32_t a_kfast, b_kfast;                        // global->LDS load order
   double alpha, beta;
   // Split-K (filled when the op is recorded): ksplit slices of kslice
-  // elements each; slice s of tile t writes its partial tile to
-  // part[(t*ksplit + s)*MT*NT], and the workgroup that finishes a tile last
-  // (cnt[t], reset to 0 by it) sums the partials in slice order.
+  // elements each; slice s of tile t writes its partial tile, m fastest, to
+  // part[(t*ksplit + s)*MT*NT]; a separate launch sums the slices in order.
   int32_t ksplit, kslice;
   double* part;
-  int32_t* cnt;
 };
 
 // Arithmetic of a contraction.
@@ -54,6 +52,9 @@ inline int tc_stat_index(int prec, int out_dt, int tile) { return (prec * 2 + ou
 // TP_F64 and float32 for TP_F32/TP_BF16.
 void launch_tc(int prec, int out_dt, int tile, const TcDesc* d_desc, int n_desc, int n_tiles,
                hipStream_t s);
+// Second half of a split-K contraction: C = alpha * (sum of the slices in
+// slice order) + beta * C, one workgroup per output tile (n_tiles in all).
+void launch_tc_reduce(int out_dt, int tile, const TcDesc* d_desc, int n_desc, int n_tiles, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Householder QR of an m x n float64 matrix (m >= n), one workgroup each.

@@ -58,7 +58,6 @@ void Pool::trim() {
 }
 
 Ctx::~Ctx() {
-  if (split_cnt) pool.release(split_cnt);
   for (auto& p : pinned_free) dev::host_free(p.second);
 }
 
@@ -200,15 +199,17 @@ TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha, double beta
   d.M = (int)M;
   d.N = (int)N;
   d.K = (int)K;
-  d.a_kfast = (Ks.back().s1 == 1 && Ms.back().s1 != 1) ? 1 : 0;
-  d.b_kfast = (Ks.back().s2 == 1 && Ns.back().s1 != 1) ? 1 : 0;
+  // load along k when k, not the output index, is unit-stride in the operand
+  const bool k_unit_a = !Ks.empty() && Ks.back().s1 == 1, k_unit_b = !Ks.empty() && Ks.back().s2 == 1;
+  d.a_kfast = (k_unit_a && (Ms.empty() || Ms.back().s1 != 1)) ? 1 : 0;
+  d.b_kfast = (k_unit_b && (Ns.empty() || Ns.back().s1 != 1)) ? 1 : 0;
   d.alpha = alpha;
   d.beta = beta;
   return d;
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -220,17 +221,21 @@ size_t Rec::push_bytes(const void* p, size_t n) {
 // Tile shape of one grouped launch: the candidates fitting the largest N in
 // the batch, largest first; the first one that still gives every CU two
 // workgroups wins (else the smallest), so small-K stages fill the chip.
-static int pick_tile(const std::vector<TcDesc>& ds) {
-  int maxN = 0, maxM = 0;
-  for (const auto& d : ds) {
-    maxN = std::max(maxN, d.N);
-    maxM = std::max(maxM, d.M);
-  }
-  std::vector<int> cand;
-  if (maxN <= 16) cand = {TT_256x16, TT_64x16};
-  else if (maxN <= 32) cand = {TT_128x32, TT_64x32};
-  else if (maxM <= 32) cand = {TT_32x128};
-  else cand = {TT_64x64, TT_64x32};
+// Tile family of one contraction: skinny outputs (N <= 16, N <= 32), short
+// M, or general.  A grouped launch runs one tile shape, so a group is split
+// by family before the shape is chosen.
+static int tile_family(const TcDesc& d) {
+  if (d.N <= 16) return 0;
+  if (d.N <= 32) return 1;
+  if (d.M <= 32) return 2;
+  return 3;
+}
+
+// Largest tile of the family that still gives two workgroups per CU.
+static int pick_tile(int family, const std::vector<TcDesc>& ds) {
+  static const std::vector<int> CAND[4] = {
+      {TT_256x16, TT_64x16}, {TT_128x32, TT_64x32}, {TT_32x128}, {TT_64x64, TT_64x32}};
+  const std::vector<int>& cand = CAND[family];
   constexpr int64_t WANT = 2 * 256;
   for (int t : cand) {
     int64_t tiles = 0;
@@ -243,35 +248,41 @@ static int pick_tile(const std::vector<TcDesc>& ds) {
 
 void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
-  const int tile = pick_tile(ds);
+  // the descriptors of one group are independent, so families may run as
+  // separate launches in any order
+  std::vector<TcDesc> fam[4];
+  for (const auto& d : ds) fam[tile_family(d)].push_back(d);
+  for (int f = 0; f < 4; ++f)
+    if (!fam[f].empty()) tc_launch(prec, out_dt, pick_tile(f, fam[f]), std::move(fam[f]), algorithmic);
+}
+
+void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic) {
   const int mt = tile_mt(tile), nt = tile_nt(tile);
   const int kt = prec == TP_BF16 ? 32 : 16;
-  // Split K when the launch would leave most CUs idle and K is long: each
-  // slice keeps at least 4 chunks of K.
+  // Split K when the output tiles leave most CUs idle and K is long: each
+  // slice keeps at least two chunks of K, and a second launch sums the
+  // slices in order (no cross-workgroup synchronisation inside the kernel).
   int64_t plain = 0, maxK = 0;
   for (const auto& d : ds) {
     plain += (int64_t)((d.M + mt - 1) / mt) * ((d.N + nt - 1) / nt);
     maxK = std::max<int64_t>(maxK, d.K);
   }
   int ksplit = 1;
-  if (scratch_ && plain < 256 && maxK >= 8 * kt && plain <= Ctx::SPLIT_CNT) {
-    ksplit = (int)std::min<int64_t>({32, (512 + plain - 1) / plain, maxK / (4 * kt)});
+  if (scratch_ && plain < 128 && maxK >= 8 * kt) {
+    ksplit = (int)std::min<int64_t>({32, (512 + plain - 1) / plain, maxK / (2 * kt)});
     if (ksplit < 2) ksplit = 1;
   }
+  // the partial buffer is reused by every split launch of this recorder:
+  // launches run in stream order and each reduction finishes its slices
+  // before the next contraction starts
   double* part = nullptr;
   if (ksplit > 1) {
-    part = (double*)scratch_->alloc(sizeof(double) * (size_t)plain * ksplit * mt * nt);
-    if (!ctx_->split_cnt) {
-      ctx_->split_cnt = (int32_t*)ctx_->pool.alloc(sizeof(int32_t) * Ctx::SPLIT_CNT);
-      EwDesc z;
-      std::memset(&z, 0, sizeof(z));
-      z.kind = EW_FILL;
-      z.dst = ctx_->split_cnt;
-      z.dst_dt = DT_F32;   // 0.0f has the bit pattern of int 0
-      z.src_dt = DT_F32;
-      z.n = Ctx::SPLIT_CNT;
-      ew({z});
+    const size_t need = (size_t)plain * ksplit * mt * nt;
+    if (need > part_cap_) {
+      part_cap_ = std::max(need, part_cap_ * 2);
+      part_buf_ = (double*)scratch_->alloc(sizeof(double) * part_cap_);
     }
+    part = part_buf_;
   }
   int64_t tiles = 0, tbase = 0;
   double fl = 0.0;
@@ -281,7 +292,6 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
     d.ksplit = ksplit;
     d.kslice = ksplit > 1 ? (int)(((d.K + ksplit - 1) / ksplit + kt - 1) / kt * kt) : d.K;
     d.part = part ? part + tbase * ksplit * mt * nt : nullptr;
-    d.cnt = ksplit > 1 ? ctx_->split_cnt + tbase : nullptr;
     d.tile_base = (int32_t)tiles;
     tiles += dt * ksplit;
     tbase += dt;
@@ -292,6 +302,7 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
         algorithmic ? fl : 0.0};
   if (algorithmic) flops_ += fl;
   ops_.push_back(op);
+  if (ksplit > 1) ops_.push_back(Op{OK_TCR, prec, out_dt, tile, (int)ds.size(), (int)tbase, op.off, 0.0});
 }
 
 void Rec::qr(const std::vector<QrDesc>& ds) {
@@ -362,6 +373,7 @@ void Rec::flush(Arena& arena) {
     }
     switch (op.kind) {
       case OK_TC: launch_tc(op.prec, op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
+      case OK_TCR: launch_tc_reduce(op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
       case OK_QR:
         if (op.tile >= 0) launch_qr_reg(op.tile, (const QrDesc*)d, op.nd, s);
         else launch_qr((const QrDesc*)d, op.nd, s);

@@ -98,12 +98,15 @@ class Rec {
     double flops;
   };
   size_t push_bytes(const void* p, size_t n);
+  void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic);
   Ctx* ctx_;
   Arena* scratch_;
   std::vector<Op> ops_;
   std::vector<uint8_t> blob_;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
   int partials_ = 0;
+  double* part_buf_ = nullptr;   // split-K partial tiles (scratch)
+  size_t part_cap_ = 0;
   double flops_ = 0.0;
   std::vector<std::pair<void*, size_t>> pinned_;   // staging buffers in flight
   std::vector<std::pair<std::pair<void*, void*>, std::pair<int, double>>> events_;
@@ -120,10 +123,6 @@ struct Ctx {
   double st_flops[NSTAT] = {0};
   double st_ms[NSTAT] = {0};
   int64_t st_launch[NSTAT] = {0};
-  // split-K tile counters: zero between launches (the last workgroup of a
-  // tile resets its counter), shared by every split contraction in order
-  static constexpr int SPLIT_CNT = 1 << 16;
-  int32_t* split_cnt = nullptr;
   std::multimap<size_t, void*> pinned_free;     // pinned staging buffers by capacity
   std::unordered_map<void*, size_t> pinned_size;
   ~Ctx();

@@ -103,6 +103,23 @@ def test_batched_heterogeneous(sess):
         assert max_obs_diff(r, ref) < TOL64
 
 
+def test_batched_per_state_chi(sess):
+    """Instances of different L, D and chi = D^2 (the batched-instances
+    recipe at small sizes) in one call, one options record per state."""
+    say("batched per-state chi")
+    pairs = [(4, 2), (5, 3), (3, 3), (6, 2)]
+    As = [make_peps(L, L, D, "uniform", 40 + k) for k, (L, D) in enumerate(pairs)]
+    chis = [D * D for (_, D) in pairs]
+    envs = sess.env_boundary([binding.to_device(A) for A in As], chis, "f64", 3)
+    res = sess.expect(envs)
+    for e in envs:
+        e.free()
+    for A, chi, r in zip(As, chis, res):
+        ref = api.expect(api.env_boundary(A, chi, 3))
+        assert max_obs_diff(r, ref) < TOL64
+        assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
 def test_cfg2_full_parity(sess):
     """8x8, D=4, near-product, chi=32: all 112 bonds and the norm."""
     say("cfg2 8x8 D=4 chi=32 f64")
