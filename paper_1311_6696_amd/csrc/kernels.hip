@@ -653,7 +653,7 @@ struct QrVariant {
 };
 constexpr QrVariant QR_VARIANTS[] = {{1, 2, 4},  {1, 4, 4},  {1, 1, 16}, {2, 1, 16}, {4, 1, 16},
                                      {8, 1, 16}, {16, 2, 8}, {2, 2, 16}, {4, 2, 16},
-                                     {8, 2, 16}, {4, 4, 16}};
+                                     {8, 2, 16}, {4, 4, 16}, {4, 5, 16}};
 constexpr int QR_NVAR = sizeof(QR_VARIANTS) / sizeof(QR_VARIANTS[0]);
 
 int qr_variant_for(int m, int n) {
@@ -682,6 +682,7 @@ void launch_qr_reg(int variant, const QrDesc* d, int nd, hipStream_t s) {
     case 8: qr_reg_kernel<4, 2, 16><<<nd, 1024, 0, s>>>(d); break;
     case 9: qr_reg_kernel<8, 2, 16><<<nd, 1024, 0, s>>>(d); break;
     case 10: qr_reg_kernel<4, 4, 16><<<nd, 1024, 0, s>>>(d); break;
+    case 11: qr_reg_kernel<4, 5, 16><<<nd, 1024, 0, s>>>(d); break;
     default: throw Error(ST_INVALID, "bad QR variant");
   }
   PE_HIP(hipGetLastError());

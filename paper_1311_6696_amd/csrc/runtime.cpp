@@ -218,9 +218,6 @@ size_t Rec::push_bytes(const void* p, size_t n) {
   return off;
 }
 
-// Tile shape of one grouped launch: the candidates fitting the largest N in
-// the batch, largest first; the first one that still gives every CU two
-// workgroups wins (else the smallest), so small-K stages fill the chip.
 // Tile family of one contraction: skinny outputs (N <= 16, N <= 32), short
 // M, or general.  A grouped launch runs one tile shape, so a group is split
 // by family before the shape is chosen.
@@ -253,7 +250,10 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   std::vector<TcDesc> fam[4];
   for (const auto& d : ds) fam[tile_family(d)].push_back(d);
   for (int f = 0; f < 4; ++f)
-    if (!fam[f].empty()) tc_launch(prec, out_dt, pick_tile(f, fam[f]), std::move(fam[f]), algorithmic);
+    if (!fam[f].empty()) {
+      const int tile = pick_tile(f, fam[f]);   // before the group is moved into the call
+      tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic);
+    }
 }
 
 void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic) {
@@ -305,6 +305,14 @@ void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool
   if (ksplit > 1) ops_.push_back(Op{OK_TCR, prec, out_dt, tile, (int)ds.size(), (int)tbase, op.off, 0.0});
 }
 
+// Householder QR of every block of the group.  Blocks that fit a
+// register-resident variant run as one grouped launch; taller blocks with at
+// most TSQR_NMAX columns are factored as a tree (TSQR): row blocks of at most
+// TSQR_LEAF rows in parallel, then the stack of their R factors recursively,
+// and Q rebuilt by one grouped contraction per level.  Every node keeps
+// R_ii >= 0, so Q and R are the unique factors with that sign convention,
+// the ones a single Householder QR gives.  Wider blocks use the streaming
+// kernel.
 void Rec::qr(const std::vector<QrDesc>& ds) {
   if (ds.empty()) return;
   int mm = 0, nn = 0;
@@ -314,8 +322,63 @@ void Rec::qr(const std::vector<QrDesc>& ds) {
     nn = std::max(nn, d.n);
   }
   const int variant = qr_variant_for(mm, nn);
+  if (variant < 0 && nn <= TSQR_NMAX) {
+    if (qr_depth_ == 0) qr_used_ = 0;   // earlier QR ops are ordered before this one on the stream
+    ++qr_depth_;
+    qr_tall(ds);
+    --qr_depth_;
+    return;
+  }
   ops_.push_back(Op{OK_QR, 0, 0, variant, (int)ds.size(), (int)ds.size(),
                     push_bytes(ds.data(), ds.size() * sizeof(QrDesc)), 0.0});
+}
+
+double* Rec::qr_scratch(size_t n) {
+  PE_REQUIRE(scratch_ != nullptr, "tall QR needs a scratch arena");
+  n = (n + 31) & ~(size_t)31;   // 256-byte granules
+  if (qr_used_ + n > qr_cap_) {
+    // regions carved earlier in this QR stay valid: the old buffer lives in the arena
+    qr_cap_ = std::max(2 * qr_cap_, n + (size_t(1) << 20));
+    qr_buf_ = (double*)scratch_->alloc(sizeof(double) * qr_cap_);
+    qr_used_ = 0;
+  }
+  double* p = qr_buf_ + qr_used_;
+  qr_used_ += n;
+  return p;
+}
+
+void Rec::qr_tall(const std::vector<QrDesc>& ds) {
+  std::vector<QrDesc> leaves, stacks;
+  std::vector<TcDesc> rebuild;
+  for (const QrDesc& d : ds) {
+    const int m = d.m, n = d.n;
+    const int b = (m + TSQR_LEAF - 1) / TSQR_LEAF;   // row blocks, each of >= TSQR_LEAF/2 >= n rows
+    double* Qb = qr_scratch((size_t)m * n);          // Q of every row block, row-major
+    double* S = qr_scratch((size_t)b * n * n);       // stacked R factors
+    double* QS = qr_scratch((size_t)b * n * n);      // Q of the stack
+    int row0 = 0;
+    for (int i = 0; i < b; ++i) {
+      const int r = m / b + (i < m % b ? 1 : 0);
+      PE_REQUIRE(r >= n, "TSQR block shorter than its width");
+      leaves.push_back(QrDesc{d.A + row0 * d.sAr, d.sAr, d.sAc, Qb + (int64_t)row0 * n, n, 1,
+                              S + (int64_t)i * n * n, n, 1, nullptr, r, n});
+      // final rows of block i: Q[row0 .. row0+r) = Qb_i . QS[i*n .. (i+1)*n)
+      TV C;
+      C.p = d.Q + row0 * d.sQr;
+      C.dt = DT_F64;
+      C.idx = "ik";
+      C.dim = {r, n};
+      C.str = {d.sQr, d.sQc};
+      rebuild.push_back(tc_build(C, dense(Qb + (int64_t)row0 * n, DT_F64, "ij", {r, n}),
+                                 dense(QS + (int64_t)i * n * n, DT_F64, "jk", {n, n})));
+      row0 += r;
+    }
+    stacks.push_back(QrDesc{S, n, 1, QS, n, 1, d.R, d.sRr, d.sRc, nullptr, b * n, n});
+  }
+  for (const QrDesc& l : leaves) PE_REQUIRE(qr_variant_for(l.m, l.n) >= 0, "TSQR leaf without a register variant");
+  qr(leaves);
+  qr(stacks);   // recursion while the stack is still taller than a register block
+  tc(TP_F64, DT_F64, rebuild, false);
 }
 
 void Rec::reduce(std::vector<RedDesc> ds) {

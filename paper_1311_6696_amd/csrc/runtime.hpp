@@ -99,6 +99,12 @@ class Rec {
   };
   size_t push_bytes(const void* p, size_t n);
   void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic);
+  void qr_tall(const std::vector<QrDesc>& ds);
+  double* qr_scratch(size_t n);
+  static constexpr int TSQR_LEAF = 256, TSQR_NMAX = 80;   // leaf rows, widest tree-factored block
+  double* qr_buf_ = nullptr;   // TSQR workspace (scratch), reused by every QR op of this recorder
+  size_t qr_cap_ = 0, qr_used_ = 0;
+  int qr_depth_ = 0;
   Ctx* ctx_;
   Arena* scratch_;
   std::vector<Op> ops_;

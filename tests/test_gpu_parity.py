@@ -120,6 +120,21 @@ def test_batched_per_state_chi(sess):
         assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
 
+@pytest.mark.parametrize("L,D,chi,dist,seed", [
+    (4, 3, 72, "normal_unit", 61),   # 81 x 72 QR blocks: five columns per wave
+    (4, 5, 30, "uniform", 52),       # 625 x 30 and 625 x 25 blocks: tree QR over row blocks
+])
+def test_wide_and_tall_qr_blocks(sess, L, D, chi, dist, seed):
+    """Truncated rows whose QR blocks need the widest register variant or the
+    row-block tree (TSQR) give the oracle's results."""
+    say(f"qr blocks L={L} D={D} chi={chi}")
+    A = make_peps(L, L, D, dist, seed)
+    (r,), _ = run_gpu(sess, [A], chi, H=2)
+    ref = api.expect(api.env_boundary(A, chi, 2))
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
 def test_cfg2_full_parity(sess):
     """8x8, D=4, near-product, chi=32: all 112 bonds and the norm."""
     say("cfg2 8x8 D=4 chi=32 f64")
