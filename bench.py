@@ -164,6 +164,9 @@ def main():
     ap.add_argument("--workloads", default="",
                     help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
                          "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="one device-to-device copy of this many MiB before the run: a plain copy kernel of "
+                         "known size against which hardware byte counters are scaled")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path has no multi-GPU component); got --gpus {args.gpus}",
@@ -180,6 +183,12 @@ def main():
     sess = binding.Session(0)
     dev_state = binding.to_device(A)
     torch.cuda.synchronize()
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     note("warm-up")
     # warm-up, then the timed region (bracketed by synchronisations)

@@ -139,13 +139,14 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, d
 
 /* Profiling of the contraction kernel: when enabled, every contraction
  * launch is bracketed by HIP events on the context's stream; statistics are
- * kept per kernel variant, index = (prec*2 + out_dtype)*6 + tile
+ * kept per kernel variant, index = (prec*2 + out_dtype)*13 + tile
  * (prec: 0 f64, 1 f32, 2 bf16; out_dtype: 0 f64, 1 f32; tile: 0 64x64,
- * 1 128x32, 2 256x16, 3 32x128, 4 64x32, 5 64x16).  Enabling clears the
- * statistics. */
+ * 1 128x32, 2 256x16, 3 32x128, 4 64x32, 5 64x16, 6 128x48, 7 64x80, and
+ * 8..12 the skinny kernel for outputs up to 16, 32, 48, 64, 80 wide).
+ * Enabling clears the statistics. */
 peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
-/* Copies the 36 per-variant statistics: algorithmic flops, milliseconds and
- * launch counts (host arrays of 36 entries each). */
+/* Copies the 78 per-variant statistics: algorithmic flops, milliseconds and
+ * launch counts (host arrays of 78 entries each). */
 peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches);
 /* Upper bound (bytes) of the transient workspace one call may hold for the
  * chain intermediates of a batch; larger batches run in several groups. */

@@ -17,7 +17,8 @@ DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
 STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
 OPTS_PER_STATE = 1   # peps_env_opts.flags: one options record per state
 DEFAULT_SEED = 0x13116696
-TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16")
+TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16", "128x48", "64x80",
+         "skinny16", "skinny32", "skinny48", "skinny64", "skinny80")
 N_STATS = 3 * 2 * len(TILES)
 
 
@@ -25,7 +26,10 @@ def variant_name(i):
     """Kernel variant of statistics slot i (see peps_ctx_profile)."""
     prec = ("f64", "f32", "bf16")[i // (2 * len(TILES))]
     out = ("f64", "f32")[(i // len(TILES)) % 2]
-    return f"tc_kernel<{prec}, out={out}, {TILES[i % len(TILES)]}>"
+    tile = TILES[i % len(TILES)]
+    if tile.startswith("skinny"):
+        return f"tcs_kernel<{prec}, out={out}, N<={tile[6:]}>"
+    return f"tc_kernel<{prec}, out={out}, {tile}>"
 
 
 class PepsError(RuntimeError):

@@ -1,5 +1,6 @@
 // Device kernels of libpepsenv (gfx950 / CDNA4).
 #include <climits>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -122,6 +123,7 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
   constexpr int WTM = MT / WM, WTN = NT / WN, MB = WTM / 16, NB = WTN / 16;
   constexpr int EA = MT * KT / 256, EB = NT * KT / 256;
   static_assert(EA >= 1 && EB >= 1 && MB >= 1 && NB >= 1, "tile");
+  static_assert(EA * 256 == MT * KT && EB * 256 == NT * KT, "a chunk is a whole number of loads per thread");
   auto& As = sm.As;
   auto& Bs = sm.Bs;
   int64_t* oAm = sm.oAm;
@@ -198,21 +200,31 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
   __syncthreads();
 
   T ra[EA], rb[EB];
+  // Element e of a thread covers linear index tid + 256*e of the KT x MT (or
+  // KT x NT) chunk, fastest along k when that is the operand's unit stride.
+  auto a_at = [&](int e, int& mm, int& kk) {
+    const int idx = tid + 256 * e;
+    if (a_kfast) { kk = idx % KT; mm = idx / KT; }
+    else { mm = idx % MT; kk = idx / MT; }
+  };
+  auto b_at = [&](int e, int& nn, int& kk) {
+    const int idx = tid + 256 * e;
+    if (b_kfast) { kk = idx % KT; nn = idx / KT; }
+    else { nn = idx % NT; kk = idx / NT; }
+  };
   auto load = [&](int kc) {
     const int k0 = kbeg + kc * KT;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int mm, kk;
-      if (a_kfast) { kk = tid % KT; mm = tid / KT + e * (256 / KT); }
-      else { mm = tid % MT; kk = tid / MT + e * (256 / MT); }
+      a_at(e, mm, kk);
       const bool ok = (m0 + mm < M) && (k0 + kk < K);
       ra[e] = ok ? A[oAm[mm] + oAk[kk]] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       int nn, kk;
-      if (b_kfast) { kk = tid % KT; nn = tid / KT + e * (256 / KT); }
-      else { nn = tid % NT; kk = tid / NT + e * (256 / NT); }
+      b_at(e, nn, kk);
       const bool ok = (n0 + nn < N) && (k0 + kk < K);
       rb[e] = ok ? B[oBn[nn] + oBk[kk]] : T(0);
     }
@@ -221,15 +233,13 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int mm, kk;
-      if (a_kfast) { kk = tid % KT; mm = tid / KT + e * (256 / KT); }
-      else { mm = tid % MT; kk = tid / MT + e * (256 / MT); }
+      a_at(e, mm, kk);
       As[kk][mm] = (L)ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       int nn, kk;
-      if (b_kfast) { kk = tid % KT; nn = tid / KT + e * (256 / KT); }
-      else { nn = tid % NT; kk = tid / NT + e * (256 / NT); }
+      b_at(e, nn, kk);
       Bs[kk][nn] = (L)rb[e];
     }
   };
@@ -252,8 +262,10 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
     if (kc + 1 < nchunks) k_offsets(kc + 1);
     __syncthreads();
     if (kc + 1 < nchunks) load(kc + 1);
+    const int kleft = K - (kbeg + kc * KT);   // k steps past the end are zero in LDS: skip them
 #pragma unroll
     for (int ks = 0; ks < KT / P::KS; ++ks) {
+      if (ks * P::KS >= kleft) break;
       typename P::F af[MB], bf[NB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) af[i] = P::template frag<MT + 2>(As, ks, wm * WTM + i * 16, lane);
@@ -336,6 +348,8 @@ static void launch_tc_tile(int tile, const TcDesc* d, int nd, int nt, hipStream_
     case TT_32x128: tc_kernel<P, TC, 32, 128, 1, 4><<<g, 256, 0, s>>>(d, nd, nt); break;
     case TT_64x32: tc_kernel<P, TC, 64, 32, 2, 2><<<g, 256, 0, s>>>(d, nd, nt); break;
     case TT_64x16: tc_kernel<P, TC, 64, 16, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_128x48: tc_kernel<P, TC, 128, 48, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
+    case TT_64x80: tc_kernel<P, TC, 64, 80, 4, 1><<<g, 256, 0, s>>>(d, nd, nt); break;
     default: throw Error(ST_INVALID, "bad tile");
   }
 }
@@ -351,6 +365,185 @@ void launch_tc(int prec, int out_dt, int tile, const TcDesc* d, int nd, int nt, 
   } else {
     if (out_dt == DT_F64) launch_tc_tile<PolBF16, double>(tile, d, nd, nt, s);
     else launch_tc_tile<PolBF16, float>(tile, d, nd, nt, s);
+  }
+  PE_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Skinny contraction: small K and N (<= 16*NB), long M with unit stride in
+// A and C.  Each wave owns a 16-row strip and reads its A fragments straight
+// from global memory into registers, KSM k-steps at a time (no
+// shared-memory staging, no barriers inside a descriptor), so a wave keeps
+// up to KSM loads in flight.  B and the k/n offset tables are
+// staged in shared memory once per descriptor.  Slots are groups of four
+// strips (64 rows), numbered across descriptors by tile_base.
+// ===========================================================================
+__host__ __device__ constexpr int tcs_bpad(int nb) { return 16 * nb + 2; }
+
+template <class P, class TC, int NB, int KSM>
+__global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds, int nd, int ngroups, int kp) {
+  using T = typename P::T;
+  using L = typename P::L;
+  static_assert(P::KS == 4, "fragments of four k per lane group");
+  constexpr int NP = 16 * NB, NPAD = tcs_bpad(NB);
+  extern __shared__ __align__(16) unsigned char tcs_smem[];
+  L* Bs = (L*)tcs_smem;                                                      // [kp][NPAD]
+  int64_t* oAk = (int64_t*)(tcs_smem + ((size_t)kp * NPAD * sizeof(L) + 15) / 16 * 16);   // [kp]
+  int64_t* oCn = oAk + kp;                                                   // [NP]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int cur = -1;
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    int lo = cur;
+    if (cur < 0 || (cur + 1 < nd && ds[cur + 1].tile_base <= g)) {
+      int a = cur < 0 ? 0 : cur + 1, b = nd - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ds[mid].tile_base <= g) a = mid; else b = mid - 1;
+      }
+      lo = a;
+    }
+    const TcDesc& d = ds[lo];
+    const int M = d.M, N = d.N, K = d.K;
+    if (lo != cur) {
+      __syncthreads();   // the previous descriptor's tables are no longer read
+      const T* __restrict__ B = (const T*)d.B;
+      for (int i = tid; i < kp * NP; i += 256) {
+        const int k = i / NP, n = i - k * NP;
+        T v = T(0);
+        if (k < K && n < N) {
+          int kk = k, nn = n;
+          int64_t o = 0;
+          for (int j = d.nk - 1; j >= 0; --j) {
+            o += (int64_t)(kk % d.dk[j]) * d.sBk[j];
+            kk /= d.dk[j];
+          }
+          for (int j = d.nn - 1; j >= 0; --j) {
+            o += (int64_t)(nn % d.dn[j]) * d.sBn[j];
+            nn /= d.dn[j];
+          }
+          v = B[o];
+        }
+        Bs[k * NPAD + n] = (L)v;
+      }
+      for (int k = tid; k < kp; k += 256) {
+        int64_t o = 0;
+        if (k < K) {
+          int kk = k;
+          for (int j = d.nk - 1; j >= 0; --j) {
+            o += (int64_t)(kk % d.dk[j]) * d.sAk[j];
+            kk /= d.dk[j];
+          }
+        }
+        oAk[k] = o;
+      }
+      for (int n = tid; n < NP; n += 256) {
+        int64_t o = 0;
+        if (n < N) {
+          int nn = n;
+          for (int j = d.nn - 1; j >= 0; --j) {
+            o += (int64_t)(nn % d.dn[j]) * d.sCn[j];
+            nn /= d.dn[j];
+          }
+        }
+        oCn[n] = o;
+      }
+      __syncthreads();
+      cur = lo;
+    }
+    const int m = ((g - d.tile_base) * 4 + wave) * 16 + (lane & 15);
+    const bool mok = m < M;
+    int64_t oa = 0, oc = 0;
+    if (mok) {
+      int mm = m;
+      for (int j = d.nm - 1; j >= 0; --j) {
+        const int x = mm % d.dm[j];
+        mm /= d.dm[j];
+        oa += (int64_t)x * d.sAm[j];
+        oc += (int64_t)x * d.sCm[j];
+      }
+    }
+    const T* __restrict__ A = (const T*)d.A;
+    const int nks = (K + 3) >> 2;
+    typename P::Acc acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[j][r] = 0;
+    // K in blocks of KSM k-steps: all fragment loads of a block are issued
+    // before its first MFMA
+    for (int kb = 0; kb < nks; kb += KSM) {
+      T af[KSM];
+#pragma unroll
+      for (int q = 0; q < KSM; ++q) {
+        const int k = 4 * (kb + q) + (lane >> 4);
+        af[q] = (kb + q < nks && mok && k < K) ? A[oa + oAk[k]] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < KSM; ++q) {
+        if (kb + q >= nks) break;
+        const L* brow = Bs + (4 * (kb + q) + (lane >> 4)) * NPAD + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j] = P::mma(brow[16 * j], (typename P::F)af[q], acc[j]);
+      }
+    }
+    TC* __restrict__ C = (TC*)d.C;
+    const double alpha = d.alpha, beta = d.beta;
+    if (mok) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = 16 * j + P::row(lane, r);
+          if (n < N) {
+            const int64_t off = oc + oCn[n];
+            double v = alpha * (double)acc[j][r];
+            if (beta != 0.0) v += beta * (double)C[off];
+            C[off] = (TC)v;
+          }
+        }
+    }
+  }
+}
+
+int tcs_lds_bytes(int prec, int nb, int kp) {
+  const size_t el = prec == TP_F64 ? sizeof(double) : sizeof(float);
+  return (int)(((size_t)kp * tcs_bpad(nb) * el + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
+}
+
+template <class P, class TC, int NB>
+static void launch_tcs_nb(int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
+  const int g = ngroups < TC_GRID_CAP ? ngroups : TC_GRID_CAP;
+  const int lds = tcs_lds_bytes(std::is_same<typename P::T, double>::value ? TP_F64 : TP_F32, NB, kp);
+  switch (ksm) {
+    case 8: tcs_kernel<P, TC, NB, 8><<<g, 256, lds, s>>>(d, nd, ngroups, kp); break;
+    case 16: tcs_kernel<P, TC, NB, 16><<<g, 256, lds, s>>>(d, nd, ngroups, kp); break;
+    default: throw Error(ST_INVALID, "bad skinny k range");
+  }
+}
+
+template <class P, class TC>
+static void launch_tcs_p(int nb, int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
+  switch (nb) {
+    case 1: launch_tcs_nb<P, TC, 1>(ksm, d, nd, ngroups, kp, s); break;
+    case 2: launch_tcs_nb<P, TC, 2>(ksm, d, nd, ngroups, kp, s); break;
+    case 3: launch_tcs_nb<P, TC, 3>(ksm, d, nd, ngroups, kp, s); break;
+    case 4: launch_tcs_nb<P, TC, 4>(ksm, d, nd, ngroups, kp, s); break;
+    case 5: launch_tcs_nb<P, TC, 5>(ksm, d, nd, ngroups, kp, s); break;
+    default: throw Error(ST_INVALID, "bad skinny width");
+  }
+}
+
+void launch_tcs(int prec, int out_dt, int nb, int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
+  if (ngroups <= 0) return;
+  if (kp < 4 || kp % 4 != 0) throw Error(ST_INVALID, "bad skinny k range");
+  if (prec == TP_F64) {
+    if (out_dt != DT_F64) throw Error(ST_INVALID, "f64 contraction writes f64");
+    launch_tcs_p<PolF64, double>(nb, ksm, d, nd, ngroups, kp, s);
+  } else if (prec == TP_F32) {
+    if (out_dt == DT_F64) launch_tcs_p<PolF32, double>(nb, ksm, d, nd, ngroups, kp, s);
+    else launch_tcs_p<PolF32, float>(nb, ksm, d, nd, ngroups, kp, s);
+  } else {
+    throw Error(ST_INVALID, "skinny contraction: f64 or f32 only");
   }
   PE_HIP(hipGetLastError());
 }

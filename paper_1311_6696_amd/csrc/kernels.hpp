@@ -36,13 +36,18 @@ struct TcDesc {
 // Arithmetic of a contraction.
 enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 // Tile shapes (MT x NT per 256-thread workgroup).
-enum TcTile : int { TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_64x32 = 4, TT_64x16 = 5, TT_COUNT = 6 };
+// TT_S16..TT_S80: the skinny kernel (64-row groups, N up to 16..80).
+enum TcTile : int {
+  TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_64x32 = 4, TT_64x16 = 5, TT_128x48 = 6, TT_64x80 = 7,
+  TT_S16 = 8, TT_S32 = 9, TT_S48 = 10, TT_S64 = 11, TT_S80 = 12,
+  TT_COUNT = 13
+};
 inline int tile_mt(int t) {
-  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64};
+  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64, 128, 64, 64, 64, 64, 64, 64};
   return v[t];
 }
 inline int tile_nt(int t) {
-  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16};
+  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16, 48, 80, 16, 32, 48, 64, 80};
   return v[t];
 }
 // Statistics slot of a contraction variant.
@@ -52,6 +57,14 @@ inline int tc_stat_index(int prec, int out_dt, int tile) { return (prec * 2 + ou
 // TP_F64 and float32 for TP_F32/TP_BF16.
 void launch_tc(int prec, int out_dt, int tile, const TcDesc* d_desc, int n_desc, int n_tiles,
                hipStream_t s);
+// Skinny contraction (N <= 16*nb, unit stride along m in A and C):
+// descriptors' tile_base counts groups of 64 rows; kp = 4*ceil(max K/4) rows
+// of B staged per descriptor; ksm in {8, 16} k-steps of A per load batch,
+// nb in 1..5.
+void launch_tcs(int prec, int out_dt, int nb, int ksm, const TcDesc* d_desc, int n_desc, int n_groups, int kp,
+                hipStream_t s);
+// Shared memory of one skinny workgroup (bytes).
+int tcs_lds_bytes(int prec, int nb, int kp);
 // Second half of a split-K contraction: C = alpha * (sum of the slices in
 // slice order) + beta * C, one workgroup per output tile (n_tiles in all).
 void launch_tc_reduce(int out_dt, int tile, const TcDesc* d_desc, int n_desc, int n_tiles, hipStream_t s);

@@ -209,7 +209,7 @@ TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha, double beta
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -219,19 +219,24 @@ size_t Rec::push_bytes(const void* p, size_t n) {
 }
 
 // Tile family of one contraction: skinny outputs (N <= 16, N <= 32), short
-// M, or general.  A grouped launch runs one tile shape, so a group is split
-// by family before the shape is chosen.
+// M, outputs whose width fits 48 or 80 columns (dD^2-type legs, little
+// padding), or general.  A grouped launch runs one tile shape, so a group is
+// split by family before the shape is chosen.
 static int tile_family(const TcDesc& d) {
   if (d.N <= 16) return 0;
   if (d.N <= 32) return 1;
   if (d.M <= 32) return 2;
-  return 3;
+  if (d.N <= 48) return 3;
+  if (d.N > 64 && d.N <= 80) return 4;
+  return 5;
 }
+constexpr int N_FAMILIES = 6;
 
 // Largest tile of the family that still gives two workgroups per CU.
 static int pick_tile(int family, const std::vector<TcDesc>& ds) {
-  static const std::vector<int> CAND[4] = {
-      {TT_256x16, TT_64x16}, {TT_128x32, TT_64x32}, {TT_32x128}, {TT_64x64, TT_64x32}};
+  static const std::vector<int> CAND[N_FAMILIES] = {{TT_256x16, TT_64x16}, {TT_128x32, TT_64x32}, {TT_32x128},
+                                                    {TT_128x48, TT_64x32}, {TT_64x80, TT_64x32},
+                                                    {TT_64x64, TT_64x32}};
   const std::vector<int>& cand = CAND[family];
   constexpr int64_t WANT = 2 * 256;
   for (int t : cand) {
@@ -247,13 +252,50 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
   // the descriptors of one group are independent, so families may run as
   // separate launches in any order
-  std::vector<TcDesc> fam[4];
+  std::vector<TcDesc> fam[N_FAMILIES];
   for (const auto& d : ds) fam[tile_family(d)].push_back(d);
-  for (int f = 0; f < 4; ++f)
+  for (int f = 0; f < N_FAMILIES; ++f)
     if (!fam[f].empty()) {
+      if (f != 2 && tcs_launch(prec, out_dt, fam[f], algorithmic)) continue;
       const int tile = pick_tile(f, fam[f]);   // before the group is moved into the call
       tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic);
     }
+}
+
+// The skinny kernel takes groups whose outputs are at most 80 wide, with m
+// unit-stride in A and C (coalesced fragment loads and stores), B small
+// enough to stage in 64 KB of shared memory, and at least one 64-row group
+// per CU.  Returns false (nothing recorded) when the group does not qualify.
+bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic) {
+  if (prec == TP_BF16) return false;
+  int maxN = 0, maxK = 0;
+  int64_t groups = 0;
+  for (const auto& d : ds) {
+    if (d.N > 80 || d.sAm[d.nm - 1] != 1 || d.sCm[d.nm - 1] != 1) return false;
+    maxN = std::max(maxN, d.N);
+    maxK = std::max(maxK, d.K);
+    groups += (d.M + 63) / 64;
+  }
+  const int nb = (maxN + 15) / 16, kp = (maxK + 3) / 4 * 4;
+  if (groups < 256 || groups >= INT_MAX || tcs_lds_bytes(prec, nb, kp) > 64 * 1024) return false;
+  int64_t base = 0;
+  double fl = 0.0;
+  for (auto& d : ds) {
+    d.tile_base = (int32_t)base;
+    d.tiles_n = 1;
+    d.ksplit = 1;
+    d.kslice = d.K;
+    d.part = nullptr;
+    base += (d.M + 63) / 64;
+    fl += 2.0 * d.M * (double)d.N * d.K;
+  }
+  Op op{OK_TCS, prec, out_dt, TT_S16 + nb - 1, (int)ds.size(), (int)groups,
+        push_bytes(ds.data(), ds.size() * sizeof(TcDesc)), algorithmic ? fl : 0.0};
+  op.ksm = kp <= 32 ? 8 : 16;
+  op.kp = kp;
+  if (algorithmic) flops_ += fl;
+  ops_.push_back(op);
+  return true;
 }
 
 void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic) {
@@ -430,13 +472,16 @@ void Rec::flush(Arena& arena) {
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
     void* e0 = nullptr;
-    if (ctx_->profile && op.kind == OK_TC) {
+    if (ctx_->profile && (op.kind == OK_TC || op.kind == OK_TCS)) {
       e0 = dev::event_create();
       dev::event_record(e0, s);
     }
     switch (op.kind) {
       case OK_TC: launch_tc(op.prec, op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
       case OK_TCR: launch_tc_reduce(op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
+      case OK_TCS:
+        launch_tcs(op.prec, op.out_dt, op.tile - TT_S16 + 1, op.ksm, (const TcDesc*)d, op.nd, op.grid, op.kp, s);
+        break;
       case OK_QR:
         if (op.tile >= 0) launch_qr_reg(op.tile, (const QrDesc*)d, op.nd, s);
         else launch_qr((const QrDesc*)d, op.nd, s);

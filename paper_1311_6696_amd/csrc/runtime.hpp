@@ -96,9 +96,11 @@ class Rec {
     int kind, prec, out_dt, tile, nd, grid;
     size_t off;
     double flops;
+    int ksm = 0, kp = 0;   // skinny contraction: k-steps per load batch, padded K
   };
   size_t push_bytes(const void* p, size_t n);
   void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic);
+  bool tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic);
   void qr_tall(const std::vector<QrDesc>& ds);
   double* qr_scratch(size_t n);
   static constexpr int TSQR_LEAF = 256, TSQR_NMAX = 80;   // leaf rows, widest tree-factored block
