@@ -1,4 +1,5 @@
 // Device kernels of libpepsenv (gfx950 / CDNA4).
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -391,8 +392,12 @@ __global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds,
   int64_t* oAk = (int64_t*)(tcs_smem + ((size_t)kp * NPAD * sizeof(L) + 15) / 16 * 16);   // [kp]
   int64_t* oCn = oAk + kp;                                                   // [NP]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // contiguous blocks of groups per workgroup: a workgroup crosses few
+  // descriptor boundaries, so B is staged rarely
+  const int per = (ngroups + gridDim.x - 1) / gridDim.x;
+  const int gend = min(ngroups, (blockIdx.x + 1) * per);
   int cur = -1;
-  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+  for (int g = blockIdx.x * per; g < gend; ++g) {
     int lo = cur;
     if (cur < 0 || (cur + 1 < nd && ds[cur + 1].tile_base <= g)) {
       int a = cur < 0 ? 0 : cur + 1, b = nd - 1;
@@ -510,13 +515,36 @@ int tcs_lds_bytes(int prec, int nb, int kp) {
   return (int)(((size_t)kp * tcs_bpad(nb) * el + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
 }
 
+// One resident wave of workgroups (occupancy x compute units), so the
+// contiguous group ranges finish together.
+template <class K>
+static int resident_grid(K kernel, int lds, int want) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    PE_HIP(hipGetDevice(&dev));
+    PE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  int occ = 0;
+  PE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, lds));
+  const int cap = std::max(1, occ) * cus;
+  return want < cap ? want : cap;
+}
+
 template <class P, class TC, int NB>
 static void launch_tcs_nb(int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
-  const int g = ngroups < TC_GRID_CAP ? ngroups : TC_GRID_CAP;
   const int lds = tcs_lds_bytes(std::is_same<typename P::T, double>::value ? TP_F64 : TP_F32, NB, kp);
   switch (ksm) {
-    case 8: tcs_kernel<P, TC, NB, 8><<<g, 256, lds, s>>>(d, nd, ngroups, kp); break;
-    case 16: tcs_kernel<P, TC, NB, 16><<<g, 256, lds, s>>>(d, nd, ngroups, kp); break;
+    case 8: {
+      const int g = resident_grid(tcs_kernel<P, TC, NB, 8>, lds, ngroups);
+      tcs_kernel<P, TC, NB, 8><<<g, 256, lds, s>>>(d, nd, ngroups, kp);
+      break;
+    }
+    case 16: {
+      const int g = resident_grid(tcs_kernel<P, TC, NB, 16>, lds, ngroups);
+      tcs_kernel<P, TC, NB, 16><<<g, 256, lds, s>>>(d, nd, ngroups, kp);
+      break;
+    }
     default: throw Error(ST_INVALID, "bad skinny k range");
   }
 }

@@ -248,30 +248,42 @@ static int pick_tile(int family, const std::vector<TcDesc>& ds) {
   return cand.back();
 }
 
+// Contractions the skinny kernel can take: outputs at most 80 wide, K at
+// most 128 (B staged in shared memory), m unit-stride in A and C.
+static bool skinny_fits(const TcDesc& d) {
+  return d.N <= 80 && d.K <= 128 && d.sAm[d.nm - 1] == 1 && d.sCm[d.nm - 1] == 1;
+}
+
 void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
   // the descriptors of one group are independent, so families may run as
   // separate launches in any order
   std::vector<TcDesc> fam[N_FAMILIES];
   for (const auto& d : ds) fam[tile_family(d)].push_back(d);
-  for (int f = 0; f < N_FAMILIES; ++f)
-    if (!fam[f].empty()) {
-      if (f != 2 && tcs_launch(prec, out_dt, fam[f], algorithmic)) continue;
-      const int tile = pick_tile(f, fam[f]);   // before the group is moved into the call
-      tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic);
+  for (int f = 0; f < N_FAMILIES; ++f) {
+    if (fam[f].empty()) continue;
+    if (f != 2 && prec != TP_BF16) {
+      // contractions the skinny kernel takes leave the family's tiled launch
+      std::vector<TcDesc> sk, rest;
+      for (const auto& d : fam[f]) (skinny_fits(d) ? sk : rest).push_back(d);
+      if (!sk.empty() && tcs_launch(prec, out_dt, sk, algorithmic)) fam[f].swap(rest);
+      if (fam[f].empty()) continue;
     }
+    const int tile = pick_tile(f, fam[f]);   // before the group is moved into the call
+    tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic);
+  }
 }
 
-// The skinny kernel takes groups whose outputs are at most 80 wide, with m
-// unit-stride in A and C (coalesced fragment loads and stores), B small
-// enough to stage in 64 KB of shared memory, and at least one 64-row group
+// The skinny kernel takes a group of fitting contractions whose B tiles
+// stage in 64 KB of shared memory and that give at least one 64-row group
 // per CU.  Returns false (nothing recorded) when the group does not qualify.
+
 bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic) {
   if (prec == TP_BF16) return false;
   int maxN = 0, maxK = 0;
   int64_t groups = 0;
   for (const auto& d : ds) {
-    if (d.N > 80 || d.sAm[d.nm - 1] != 1 || d.sCm[d.nm - 1] != 1) return false;
+    if (!skinny_fits(d)) return false;
     maxN = std::max(maxN, d.N);
     maxK = std::max(maxK, d.K);
     groups += (d.M + 63) / 64;
