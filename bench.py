@@ -20,6 +20,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense MFMA TFLOP/s, MI355X
+HBM_TBS = 8.0                                          # HBM3E, TB/s
+WORKLOAD_TAG = "env_8x8_D4_chi32_f64"
+
+
+def kernel_slug(name):
+    return "".join(ch if ch.isalnum() else "_" for ch in name).strip("_")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` on this workload from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
+    known size); None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_slug(kernel)}__{WORKLOAD_TAG}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = os.path.join(ROOT, "paper_1311_6696_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernels.hip sha256") != digest or "traffic bytes per launch" not in fields:
+        return None
+    return float(fields["traffic bytes per launch"])
 def run_steps(sess, dev_state, chi, dtype, halfsweeps, n, split=None):
     """n full environments; `split` (a list) receives (boundary_s, expect_s) per step."""
     res = None
@@ -207,12 +233,23 @@ def main():
     sess.ctx.profile(True)
     run_steps(sess, dev_state, chi, "f64", H, max(2, args.steps // 4))
     torch.cuda.synchronize()
-    fl, kms, nl = sess.ctx.stats()
+    fl, kms, nl, nbytes = sess.ctx.stats()
     sess.ctx.profile(False)
     dom = int(np.argmax(kms))
-    per_launch_flops = fl[dom] / max(nl[dom], 1)
-    avg_ms = kms[dom] / max(nl[dom], 1)
-    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    nlaunch = max(int(nl[dom]), 1)
+    per_launch_flops = fl[dom] / nlaunch
+    per_launch_bytes = nbytes[dom] / nlaunch
+    avg_ms = kms[dom] / nlaunch
+    kernel = binding.variant_name(dom)
+    # the dominant kernel is bound by HBM when its algorithmic intensity is
+    # below the FP64 machine balance (78.6 TFLOP/s over 8 TB/s)
+    intensity = per_launch_flops / per_launch_bytes if per_launch_bytes > 0 else float("inf")
+    if intensity < PEAK["f64"] / HBM_TBS:
+        bound, unit, peak = "hbm", "GB/s", HBM_TBS * 1000.0
+        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    else:
+        bound, unit, peak = "mfma", "TFLOP/s", PEAK["f64"]
+        achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     tc_total_ms = float(np.sum(kms)) / max(2, args.steps // 4)
 
     out = {
@@ -237,13 +274,16 @@ def main():
         "boundary_ms": 1000.0 * float(np.median([s[0] for s in split])),
         "expect_ms": 1000.0 * float(np.median([s[1] for s in split])),
         "roofline": {
-            "bound": "mfma",
-            "kernel": binding.variant_name(dom),
+            "bound": bound,
+            "kernel": kernel,
             "achieved": achieved,
-            "peak": PEAK["f64"],
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK["f64"],
-            "traffic": None,
+            "peak": peak,
+            "unit": unit,
+            "frac": achieved / peak,
+            "traffic": measured_traffic(kernel),
+            "flops_per_launch": per_launch_flops,
+            "bytes_per_launch": per_launch_bytes,
+            "arithmetic_intensity": intensity,
             "launches_per_env": int(nl[dom] / max(2, args.steps // 4)),
             "avg_launch_us": 1000.0 * avg_ms,
             "contraction_ms_per_env": tc_total_ms,

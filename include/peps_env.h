@@ -145,9 +145,10 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, d
  * 8..12 the skinny kernel for outputs up to 16, 32, 48, 64, 80 wide).
  * Enabling clears the statistics. */
 peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
-/* Copies the 78 per-variant statistics: algorithmic flops, milliseconds and
- * launch counts (host arrays of 78 entries each). */
-peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches);
+/* Copies the 78 per-variant statistics: algorithmic flops, milliseconds,
+ * launch counts and algorithmic bytes (each operand read once, the output
+ * written once) into host arrays of 78 entries each; bytes may be NULL. */
+peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches, double* bytes);
 /* Upper bound (bytes) of the transient workspace one call may hold for the
  * chain intermediates of a batch; larger batches run in several groups. */
 peps_status peps_ctx_set_workspace(peps_ctx* ctx, uint64_t bytes);

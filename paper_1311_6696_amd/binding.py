@@ -85,7 +85,8 @@ def load(path=None):
     lib.peps_env_free.restype = None
     lib.peps_env_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]
     lib.peps_ctx_profile.argtypes = [vp, i32]
-    lib.peps_ctx_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.peps_ctx_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]
     lib.peps_ctx_set_workspace.argtypes = [vp, C.c_uint64]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
@@ -228,11 +229,13 @@ class Context:
         _check(self.lib, self.lib.peps_ctx_profile(self.handle, 1 if enable else 0))
 
     def stats(self):
+        """Per-variant (flops, milliseconds, launches, bytes) since profiling was enabled."""
         f = (C.c_double * N_STATS)()
         m = (C.c_double * N_STATS)()
         n = (C.c_int64 * N_STATS)()
-        _check(self.lib, self.lib.peps_ctx_stats(self.handle, f, m, n))
-        return np.array(f[:]), np.array(m[:]), np.array(n[:])
+        b = (C.c_double * N_STATS)()
+        _check(self.lib, self.lib.peps_ctx_stats(self.handle, f, m, n, b))
+        return np.array(f[:]), np.array(m[:]), np.array(n[:]), np.array(b[:])
 
     def set_workspace(self, nbytes):
         _check(self.lib, self.lib.peps_ctx_set_workspace(self.handle, int(nbytes)))

@@ -244,16 +244,18 @@ peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable) {
     ctx->c->profile = enable != 0;
     for (int i = 0; i < Ctx::NSTAT; ++i) {
       ctx->c->st_flops[i] = 0.0;
+      ctx->c->st_bytes[i] = 0.0;
       ctx->c->st_ms[i] = 0.0;
       ctx->c->st_launch[i] = 0;
     }
   });
 }
 
-peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches) {
+peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches, double* bytes) {
   return guarded([&] {
     PE_REQUIRE(ctx && flops && ms && launches, "arguments must not be NULL");
     for (int i = 0; i < Ctx::NSTAT; ++i) {
+      if (bytes) bytes[i] = ctx->c->st_bytes[i];
       flops[i] = ctx->c->st_flops[i];
       ms[i] = ctx->c->st_ms[i];
       launches[i] = ctx->c->st_launch[i];

@@ -248,6 +248,13 @@ static int pick_tile(int family, const std::vector<TcDesc>& ds) {
   return cand.back();
 }
 
+// Algorithmic bytes of one contraction: A and B read once, C written once
+// (and read when accumulated), in the operand and output element sizes.
+static double tc_bytes(int prec, int out_dt, const TcDesc& d) {
+  const double es = prec == TP_F64 ? 8.0 : 4.0, os = out_dt == DT_F64 ? 8.0 : 4.0;
+  return es * ((double)d.M * d.K + (double)d.K * d.N) + os * (double)d.M * d.N * (d.beta != 0.0 ? 2.0 : 1.0);
+}
+
 // Contractions the skinny kernel can take: outputs at most 80 wide, K at
 // most 128 (B staged in shared memory), m unit-stride in A and C.
 static bool skinny_fits(const TcDesc& d) {
@@ -303,6 +310,7 @@ bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorit
   }
   Op op{OK_TCS, prec, out_dt, TT_S16 + nb - 1, (int)ds.size(), (int)groups,
         push_bytes(ds.data(), ds.size() * sizeof(TcDesc)), algorithmic ? fl : 0.0};
+  for (const auto& d : ds) op.bytes += tc_bytes(prec, out_dt, d);
   op.ksm = kp <= 32 ? 8 : 16;
   op.kp = kp;
   if (algorithmic) flops_ += fl;
@@ -354,6 +362,7 @@ void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool
   PE_REQUIRE(tiles < INT_MAX, "too many tiles in one launch");
   Op op{OK_TC, prec, out_dt, tile, (int)ds.size(), (int)tiles, push_bytes(ds.data(), ds.size() * sizeof(TcDesc)),
         algorithmic ? fl : 0.0};
+  for (const auto& d : ds) op.bytes += tc_bytes(prec, out_dt, d);
   if (algorithmic) flops_ += fl;
   ops_.push_back(op);
   if (ksplit > 1) ops_.push_back(Op{OK_TCR, prec, out_dt, tile, (int)ds.size(), (int)tbase, op.off, 0.0});
@@ -505,7 +514,7 @@ void Rec::flush(Arena& arena) {
     if (e0) {
       void* e1 = dev::event_create();
       dev::event_record(e1, s);
-      events_.push_back({{e0, e1}, {tc_stat_index(op.prec, op.out_dt, op.tile), op.flops}});
+      events_.push_back(Timed{e0, e1, tc_stat_index(op.prec, op.out_dt, op.tile), op.flops, op.bytes});
     }
   }
   ops_.clear();
@@ -519,12 +528,12 @@ void Rec::run(Arena& arena) {
   // staging buffers and descriptors stay valid until the stream drains
   dev::sync(ctx_->stream);
   for (auto& e : events_) {
-    const int key = e.second.first;
-    ctx_->st_ms[key] += dev::event_ms(e.first.first, e.first.second);
-    ctx_->st_flops[key] += e.second.second;
-    ctx_->st_launch[key] += 1;
-    dev::event_destroy(e.first.first);
-    dev::event_destroy(e.first.second);
+    ctx_->st_ms[e.key] += dev::event_ms(e.e0, e.e1);
+    ctx_->st_flops[e.key] += e.flops;
+    ctx_->st_bytes[e.key] += e.bytes;
+    ctx_->st_launch[e.key] += 1;
+    dev::event_destroy(e.e0);
+    dev::event_destroy(e.e1);
   }
   events_.clear();
   for (auto& p : pinned_) ctx_->pinned_put(p.first, p.second);
@@ -538,8 +547,8 @@ Rec::~Rec() {
     } catch (...) {
     }
     for (auto& e : events_) {
-      dev::event_destroy(e.first.first);
-      dev::event_destroy(e.first.second);
+      dev::event_destroy(e.e0);
+      dev::event_destroy(e.e1);
     }
     for (auto& p : pinned_) ctx_->pinned_put(p.first, p.second);
   }

@@ -97,6 +97,7 @@ class Rec {
     size_t off;
     double flops;
     int ksm = 0, kp = 0;   // skinny contraction: k-steps per load batch, padded K
+    double bytes = 0.0;    // algorithmic bytes: operands read once, output written once
   };
   size_t push_bytes(const void* p, size_t n);
   void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic);
@@ -117,7 +118,12 @@ class Rec {
   size_t part_cap_ = 0;
   double flops_ = 0.0;
   std::vector<std::pair<void*, size_t>> pinned_;   // staging buffers in flight
-  std::vector<std::pair<std::pair<void*, void*>, std::pair<int, double>>> events_;
+  struct Timed {
+    void *e0, *e1;
+    int key;
+    double flops, bytes;
+  };
+  std::vector<Timed> events_;
 };
 
 // ---------------------------------------------------------------- context ---
@@ -129,6 +135,7 @@ struct Ctx {
   bool profile = false;
   static constexpr int NSTAT = 3 * 2 * TT_COUNT;
   double st_flops[NSTAT] = {0};
+  double st_bytes[NSTAT] = {0};
   double st_ms[NSTAT] = {0};
   int64_t st_launch[NSTAT] = {0};
   std::multimap<size_t, void*> pinned_free;     // pinned staging buffers by capacity
