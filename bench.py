@@ -25,7 +25,9 @@ WORKLOAD_TAG = "env_8x8_D4_chi32_f64"
 
 
 def kernel_slug(name):
-    return "".join(ch if ch.isalnum() else "_" for ch in name).strip("_")
+    """File-name form of a kernel variant: runs of other characters become one '_'."""
+    import re
+    return re.sub(r"[^0-9A-Za-z]+", "_", name).strip("_")
 
 
 def measured_traffic(kernel):
@@ -190,6 +192,10 @@ def main():
     ap.add_argument("--workloads", default="",
                     help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
                          "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the contraction launch shapes on one untimed environment first")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the library's launch sequences from captured HIP graphs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="one device-to-device copy of this many MiB before the run: a plain copy kernel of "
                          "known size against which hardware byte counters are scaled")
@@ -207,6 +213,8 @@ def main():
     A = config_peps(2)
     chi, H = cfg["chi"], args.halfsweeps
     sess = binding.Session(0)
+    if args.graphs:
+        sess.ctx.graphs(True)
     dev_state = binding.to_device(A)
     torch.cuda.synchronize()
     if args.copy_calib_mib > 0:
@@ -216,6 +224,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.autotune:
+        note("autotuning launch shapes on one environment")
+        sess.ctx.autotune(1)
+        run_steps(sess, dev_state, chi, "f64", H, 1)
+        sess.ctx.autotune(0)
     note("warm-up")
     # warm-up, then the timed region (bracketed by synchronisations)
     ref = run_steps(sess, dev_state, chi, "f64", H, args.warmup)
@@ -268,6 +281,8 @@ def main():
         "config": {"workload": "full environment of an 8x8 OBC PEPS, d=2, D=4, near-product, chi=32, "
                                f"{H} ALS half-sweeps per truncated row; norm, 64 <Sz>, 112 bond energies",
                    "lattice": "8x8", "D": 4, "chi": chi, "halfsweeps": H, "parallelism": "single GPU"},
+        "graph_replay": bool(args.graphs),
+        "autotuned": bool(args.autotune),
         "gflops_per_s": flops / (ms * 1e-3) / 1e9,
         "pct_fp64_mfma_peak": 100.0 * flops / (ms * 1e-3) / (PEAK["f64"] * 1e12),
         "gflop_per_env": flops / 1e9,

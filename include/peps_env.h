@@ -137,6 +137,29 @@ void peps_env_free(peps_env* env);
  * (host buffer of at least n_rows*halfsweeps doubles; may be NULL). */
 peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas);
 
+/* Launch-shape autotuning of the contractions.  mode 1: every grouped
+ * contraction (with beta = 0) whose signature - precision, output type,
+ * tile family, widest N, longest K, total rows and group size to the next
+ * power of two - has no stored choice is run and timed with each candidate
+ * launch shape (the skinny kernel where it fits, each tile of the family
+ * with and without split-K), and the fastest is stored; mode 0: stop
+ * tuning, keep using the stored choices; mode 2: forget them (heuristic
+ * shapes again).  Tuning calls synchronize and run each contraction several
+ * times; the results they return are those of the chosen shape. */
+peps_status peps_ctx_autotune(peps_ctx* ctx, int32_t mode);
+
+/* Graph replay: when enabled, every launch sequence the library issues is
+ * captured into a HIP graph, keyed by the bytes its kernels and copies read
+ * from the host (descriptors with their device pointers, launch shapes,
+ * uploaded data).  A later sequence that is byte-identical - the same call
+ * on the same shapes and buffers, e.g. the same lattice again with new
+ * tensor values written into the same device tensors - replays the graph
+ * instead of uploading and launching op by op.  The context keeps at most
+ * 512 graphs with their descriptor copies in device memory; disabling
+ * waits for the stream and releases them.  Not combined with profiling
+ * (profiled calls launch op by op). */
+peps_status peps_ctx_graphs(peps_ctx* ctx, int32_t enable);
+
 /* Profiling of the contraction kernel: when enabled, every contraction
  * launch is bracketed by HIP events on the context's stream; statistics are
  * kept per kernel variant, index = (prec*2 + out_dtype)*13 + tile

@@ -59,7 +59,8 @@ class Result(C.Structure):
 
 
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
-           "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_stats", "peps_ctx_set_workspace",
+           "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
+           "peps_ctx_stats", "peps_ctx_set_workspace",
            "peps_last_error")
 
 _lib = None
@@ -88,10 +89,13 @@ def load(path=None):
     lib.peps_ctx_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
     lib.peps_ctx_set_workspace.argtypes = [vp, C.c_uint64]
+    lib.peps_ctx_graphs.argtypes = [vp, C.c_int32]
+    lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
-                 "peps_ctx_profile", "peps_ctx_stats", "peps_ctx_set_workspace"):
+                 "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
+                 "peps_ctx_set_workspace"):
         getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -224,6 +228,15 @@ class Context:
                          bond_v=bd[R * (Cc - 1): R * (Cc - 1) + (R - 1) * Cc].reshape(R - 1, Cc))
             out.append(d)
         return out
+
+    def autotune(self, mode=1):
+        """1: time launch shapes for new contraction signatures; 0: stop, keep
+        the choices; 2: forget them."""
+        _check(self.lib, self.lib.peps_ctx_autotune(self.handle, int(mode)))
+
+    def graphs(self, enable=True):
+        """Replay byte-identical launch sequences from captured HIP graphs."""
+        _check(self.lib, self.lib.peps_ctx_graphs(self.handle, 1 if enable else 0))
 
     def profile(self, enable=True):
         _check(self.lib, self.lib.peps_ctx_profile(self.handle, 1 if enable else 0))

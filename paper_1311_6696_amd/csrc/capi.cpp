@@ -238,6 +238,27 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, d
   });
 }
 
+peps_status peps_ctx_autotune(peps_ctx* ctx, int32_t mode) {
+  return guarded([&] {
+    PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    PE_REQUIRE(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
+    if (mode == 2) ctx->c->tuned.clear();
+    ctx->c->tuning = mode == 1;
+  });
+}
+
+peps_status peps_ctx_graphs(peps_ctx* ctx, int32_t enable) {
+  return guarded([&] {
+    PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    dev::set_device(ctx->c->device);
+    if (!enable && ctx->c->graphs) {
+      dev::sync(ctx->c->stream);
+      ctx->c->clear_graphs();
+    }
+    ctx->c->graphs = enable != 0;
+  });
+}
+
 peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable) {
   return guarded([&] {
     PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");

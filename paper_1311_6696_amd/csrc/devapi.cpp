@@ -66,5 +66,39 @@ float event_ms(void* a, void* b) {
   return ms;
 }
 
+hipStream_t stream_create() {
+  hipStream_t s = nullptr;
+  PE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  return s;
+}
+
+void stream_destroy(hipStream_t s) {
+  if (s) (void)hipStreamDestroy(s);
+}
+
+void capture_begin(hipStream_t s) { PE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)); }
+
+void* capture_end(hipStream_t s) {
+  hipGraph_t g = nullptr;
+  PE_HIP(hipStreamEndCapture(s, &g));
+  hipGraphExec_t x = nullptr;
+  const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  PE_HIP(e);
+  return (void*)x;
+}
+
+void capture_abort(hipStream_t s) {
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+}
+
+void graph_launch(void* exec, hipStream_t s) { PE_HIP(hipGraphLaunch((hipGraphExec_t)exec, s)); }
+
+void graph_destroy(void* exec) {
+  if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
 }  // namespace dev
 }  // namespace pe

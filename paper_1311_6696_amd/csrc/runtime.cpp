@@ -57,7 +57,20 @@ void Pool::trim() {
   free_.clear();
 }
 
+void Ctx::clear_graphs() {
+  for (auto& kv : graph_cache)
+    for (Graph& g : kv.second) {
+      dev::graph_destroy(g.exec);
+      pool.release(g.dblob);
+      pool.release(g.partials);
+    }
+  graph_cache.clear();
+  graph_count = 0;
+}
+
 Ctx::~Ctx() {
+  clear_graphs();
+  dev::stream_destroy(capture_stream);
   for (auto& p : pinned_free) dev::host_free(p.second);
 }
 
@@ -261,24 +274,128 @@ static bool skinny_fits(const TcDesc& d) {
   return d.N <= 80 && d.K <= 128 && d.sAm[d.nm - 1] == 1 && d.sCm[d.nm - 1] == 1;
 }
 
+// Launch shapes of one group: the skinny kernel, or a tile with the split-K
+// rule on (code = tile) or off (code = NO_SPLIT + tile).  HEURISTIC: the
+// skinny kernel when the group qualifies, else the family's tile.
+enum : int { HEURISTIC = -1, SKINNY = 1000, NO_SPLIT = 100 };
+
+// Signature of a group for the tuned-choice table: precision, output type,
+// family, skinny eligibility, widest N, longest K, total rows and group
+// size (both to the next power of two).
+static uint64_t tune_key(int prec, int out_dt, int fam, bool skinny, const std::vector<TcDesc>& ds) {
+  int64_t rows = 0;
+  int maxN = 0, maxK = 0;
+  for (const auto& d : ds) {
+    rows += d.M;
+    maxN = std::max(maxN, d.N);
+    maxK = std::max(maxK, d.K);
+  }
+  int lr = 0, ld = 0;
+  while ((int64_t(1) << lr) < rows) ++lr;
+  while ((1 << ld) < (int)ds.size()) ++ld;
+  uint64_t k = (uint64_t)prec;
+  k = k * 2 + (uint64_t)out_dt;
+  k = k * 8 + (uint64_t)fam;
+  k = k * 2 + (skinny ? 1 : 0);
+  k = k * 65536 + (uint64_t)std::min(maxN, 65535);
+  k = k * 65536 + (uint64_t)std::min(maxK, 65535);
+  k = k * 64 + (uint64_t)lr;
+  k = k * 32 + (uint64_t)ld;
+  return k;
+}
+
 void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
-  // the descriptors of one group are independent, so families may run as
-  // separate launches in any order
+  // the descriptors of one group are independent, so families (and the
+  // skinny-kernel members of a family) may run as separate launches
   std::vector<TcDesc> fam[N_FAMILIES];
   for (const auto& d : ds) fam[tile_family(d)].push_back(d);
   for (int f = 0; f < N_FAMILIES; ++f) {
     if (fam[f].empty()) continue;
-    if (f != 2 && prec != TP_BF16) {
-      // contractions the skinny kernel takes leave the family's tiled launch
-      std::vector<TcDesc> sk, rest;
-      for (const auto& d : fam[f]) (skinny_fits(d) ? sk : rest).push_back(d);
+    std::vector<TcDesc> sk, rest;
+    for (const auto& d : fam[f]) ((f != 2 && prec != TP_BF16 && skinny_fits(d)) ? sk : rest).push_back(d);
+    const uint64_t key[2] = {sk.empty() ? 0 : tune_key(prec, out_dt, f, true, sk),
+                             rest.empty() ? 0 : tune_key(prec, out_dt, f, false, rest)};
+    bool tuned = ctx_->tuning && scratch_;
+    for (int part = 0; part < 2; ++part)
+      if (key[part] && ctx_->tuned.count(key[part])) tuned = true;
+    if (!tuned) {
+      // heuristic: the skinny members in one skinny launch when they fill the
+      // chip, everything else in one tiled launch
       if (!sk.empty() && tcs_launch(prec, out_dt, sk, algorithmic)) fam[f].swap(rest);
       if (fam[f].empty()) continue;
+      const int tile = pick_tile(f, fam[f]);
+      tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic, true);
+      continue;
     }
-    const int tile = pick_tile(f, fam[f]);   // before the group is moved into the call
-    tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic);
+    for (int part = 0; part < 2; ++part) {
+      std::vector<TcDesc>& X = part == 0 ? sk : rest;
+      if (X.empty()) continue;
+      int choice = HEURISTIC;
+      auto it = ctx_->tuned.find(key[part]);
+      if (it != ctx_->tuned.end()) {
+        choice = it->second;
+      } else if (ctx_->tuning && scratch_) {
+        bool idempotent = true;
+        for (const auto& d : X) idempotent = idempotent && d.beta == 0.0;
+        if (idempotent) choice = tune(prec, out_dt, f, part == 0, X, key[part]);
+      }
+      apply_choice(prec, out_dt, f, choice, X, algorithmic);
+    }
   }
+}
+
+void Rec::apply_choice(int prec, int out_dt, int fam, int choice, std::vector<TcDesc> ds, bool algorithmic) {
+  if (choice == HEURISTIC || choice == SKINNY) {
+    bool fits = true;
+    for (const auto& d : ds) fits = fits && fam != 2 && prec != TP_BF16 && skinny_fits(d);
+    if (fits && tcs_launch(prec, out_dt, ds, algorithmic)) return;
+    const int tile = pick_tile(fam, ds);
+    tc_launch(prec, out_dt, tile, std::move(ds), algorithmic, true);
+    return;
+  }
+  const bool split = choice < NO_SPLIT;
+  tc_launch(prec, out_dt, split ? choice : choice - NO_SPLIT, std::move(ds), algorithmic, split);
+}
+
+// Times every launch shape of the group on its real operands (the group is
+// idempotent: beta = 0), keeps the fastest for the signature.  Work recorded
+// before is flushed first; each candidate runs twice and its second run is
+// timed.
+int Rec::tune(int prec, int out_dt, int fam, bool skinny, const std::vector<TcDesc>& ds, uint64_t key) {
+  std::vector<int> cand;
+  if (skinny) cand.push_back(SKINNY);
+  static const std::vector<int> TILES[N_FAMILIES] = {
+      {TT_256x16, TT_64x16, TT_128x32, TT_64x32}, {TT_128x32, TT_64x32, TT_64x64}, {TT_32x128, TT_64x32},
+      {TT_128x48, TT_64x32, TT_64x64},           {TT_64x80, TT_64x64, TT_64x32},  {TT_64x64, TT_64x32, TT_128x32}};
+  for (int t : TILES[fam]) {
+    cand.push_back(t);
+    cand.push_back(NO_SPLIT + t);
+  }
+  flush(*scratch_);
+  int best = HEURISTIC;
+  float best_ms = 0.f;
+  for (int c : cand) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      void* e0 = dev::event_create();
+      void* e1 = dev::event_create();
+      dev::event_record(e0, ctx_->stream);
+      apply_choice(prec, out_dt, fam, c, ds, false);
+      flush(*scratch_);
+      dev::event_record(e1, ctx_->stream);
+      dev::sync(ctx_->stream);
+      ms = dev::event_ms(e0, e1);
+      dev::event_destroy(e0);
+      dev::event_destroy(e1);
+    }
+    if (best == HEURISTIC || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  ctx_->tuned[key] = best;
+  return best;
 }
 
 // The skinny kernel takes a group of fitting contractions whose B tiles
@@ -318,7 +435,7 @@ bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorit
   return true;
 }
 
-void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic) {
+void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic, bool allow_split) {
   const int mt = tile_mt(tile), nt = tile_nt(tile);
   const int kt = prec == TP_BF16 ? 32 : 16;
   // Split K when the output tiles leave most CUs idle and K is long: each
@@ -330,7 +447,7 @@ void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool
     maxK = std::max<int64_t>(maxK, d.K);
   }
   int ksplit = 1;
-  if (scratch_ && plain < 128 && maxK >= 8 * kt) {
+  if (allow_split && scratch_ && plain < 128 && maxK >= 8 * kt) {
     ksplit = (int)std::min<int64_t>({32, (512 + plain - 1) / plain, maxK / (2 * kt)});
     if (ksplit < 2) ksplit = 1;
   }
@@ -441,7 +558,7 @@ void Rec::qr_tall(const std::vector<QrDesc>& ds) {
   for (const QrDesc& l : leaves) PE_REQUIRE(qr_variant_for(l.m, l.n) >= 0, "TSQR leaf without a register variant");
   qr(leaves);
   qr(stacks);   // recursion while the stack is still taller than a register block
-  tc(TP_F64, DT_F64, rebuild, false);
+  tc(TP_F64, DT_F64, rebuild, false);   // (grouped with the same rules as every contraction)
 }
 
 void Rec::reduce(std::vector<RedDesc> ds) {
@@ -479,21 +596,13 @@ void* Rec::aux(Arena& arena, const void* data, size_t bytes) {
   return d;
 }
 
-void Rec::flush(Arena& arena) {
-  if (ops_.empty()) return;
-  hipStream_t s = ctx_->stream;
-  uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
-  double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
-  void* host = ctx_->pinned_get(blob_.size());
-  pinned_.push_back({host, blob_.size()});
-  std::memcpy(host, blob_.data(), blob_.size());
-  dev::h2d(dblob, host, blob_.size(), s);
+void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t s) {
   for (auto& a : aux_) dev::d2d(a.first, dblob + a.second.first, a.second.second, s);
   for (size_t i = 0; i < ops_.size(); ++i) {
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
     void* e0 = nullptr;
-    if (ctx_->profile && (op.kind == OK_TC || op.kind == OK_TCS)) {
+    if (timed && (op.kind == OK_TC || op.kind == OK_TCS)) {
       e0 = dev::event_create();
       dev::event_record(e0, s);
     }
@@ -517,10 +626,86 @@ void Rec::flush(Arena& arena) {
       events_.push_back(Timed{e0, e1, tc_stat_index(op.prec, op.out_dt, op.tile), op.flops, op.bytes});
     }
   }
+}
+
+void Rec::flush(Arena& arena) {
+  if (ops_.empty()) return;
+  if (ctx_->graphs && !ctx_->profile && !ctx_->tuning) {
+    flush_graph();
+  } else {
+    hipStream_t s = ctx_->stream;
+    uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
+    double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+    void* host = ctx_->pinned_get(blob_.size());
+    pinned_.push_back({host, blob_.size()});
+    std::memcpy(host, blob_.data(), blob_.size());
+    dev::h2d(dblob, host, blob_.size(), s);
+    issue(dblob, partials, ctx_->profile, s);
+  }
   ops_.clear();
   blob_.clear();
   aux_.clear();
   partials_ = 0;
+}
+
+// Graph replay: the launch sequence is identified by everything its kernels
+// and copies read from the host side (descriptor bytes with their device
+// pointers, launch shapes, copy destinations).  A byte-identical sequence
+// replays the instantiated graph with the descriptors it captured; the first
+// occurrence uploads a descriptor copy owned by the cache and is captured.
+void Rec::flush_graph() {
+  hipStream_t s = ctx_->stream;
+  std::vector<uint8_t> key = blob_;
+  auto put = [&key](const void* p, size_t n) {
+    const uint8_t* b = (const uint8_t*)p;
+    key.insert(key.end(), b, b + n);
+  };
+  for (const Op& op : ops_) {
+    const int32_t f[9] = {op.kind, op.prec, op.out_dt, op.tile, op.nd, op.grid, (int32_t)op.off, op.ksm, op.kp};
+    put(f, sizeof(f));
+  }
+  for (const auto& a : aux_) {
+    put(&a.first, sizeof(a.first));
+    put(&a.second, sizeof(a.second));
+  }
+  put(&partials_, sizeof(partials_));
+  uint64_t h = 1469598103934665603ull;   // FNV-1a
+  for (uint8_t c : key) h = (h ^ c) * 1099511628211ull;
+  auto& bucket = ctx_->graph_cache[h];
+  for (const Ctx::Graph& g : bucket)
+    if (g.key == key) {
+      dev::graph_launch(g.exec, s);
+      return;
+    }
+  if (ctx_->graph_count >= Ctx::GRAPH_MAX) {
+    dev::sync(s);   // no cached graph is still executing
+    ctx_->clear_graphs();
+  }
+  Ctx::Graph g;
+  g.dblob = (uint8_t*)ctx_->pool.alloc(blob_.size());
+  g.partials = (double*)ctx_->pool.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+  void* host = ctx_->pinned_get(blob_.size());
+  pinned_.push_back({host, blob_.size()});
+  std::memcpy(host, blob_.data(), blob_.size());
+  dev::h2d(g.dblob, host, blob_.size(), s);
+  // recording executes nothing, so it needs no ordering with the caller's
+  // stream; the graph is then launched there
+  if (!ctx_->capture_stream) ctx_->capture_stream = dev::stream_create();
+  hipStream_t cs = ctx_->capture_stream;
+  dev::capture_begin(cs);
+  try {
+    issue(g.dblob, g.partials, false, cs);
+    g.exec = dev::capture_end(cs);
+  } catch (...) {
+    dev::capture_abort(cs);
+    ctx_->pool.release(g.dblob);
+    ctx_->pool.release(g.partials);
+    throw;
+  }
+  dev::graph_launch(g.exec, s);
+  g.key.swap(key);
+  ctx_->graph_cache[h].push_back(std::move(g));
+  ++ctx_->graph_count;
 }
 
 void Rec::run(Arena& arena) {

@@ -100,7 +100,11 @@ class Rec {
     double bytes = 0.0;    // algorithmic bytes: operands read once, output written once
   };
   size_t push_bytes(const void* p, size_t n);
-  void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic);
+  void issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t s);
+  void flush_graph();
+  void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic, bool allow_split);
+  void apply_choice(int prec, int out_dt, int fam, int choice, std::vector<TcDesc> ds, bool algorithmic);
+  int tune(int prec, int out_dt, int fam, bool skinny, const std::vector<TcDesc>& ds, uint64_t key);
   bool tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic);
   void qr_tall(const std::vector<QrDesc>& ds);
   double* qr_scratch(size_t n);
@@ -138,6 +142,22 @@ struct Ctx {
   double st_bytes[NSTAT] = {0};
   double st_ms[NSTAT] = {0};
   int64_t st_launch[NSTAT] = {0};
+  // launch shapes chosen by timing (see Rec::tune), by group signature
+  bool tuning = false;
+  std::unordered_map<uint64_t, int> tuned;
+  // replayable launch sequences (see Rec::flush_graph)
+  bool graphs = false;
+  struct Graph {
+    std::vector<uint8_t> key;
+    void* exec = nullptr;
+    uint8_t* dblob = nullptr;
+    double* partials = nullptr;
+  };
+  static constexpr int GRAPH_MAX = 512;
+  std::unordered_map<uint64_t, std::vector<Graph>> graph_cache;
+  int graph_count = 0;
+  hipStream_t capture_stream = nullptr;   // graphs are recorded here (the caller's may be the null stream)
+  void clear_graphs();
   std::multimap<size_t, void*> pinned_free;     // pinned staging buffers by capacity
   std::unordered_map<void*, size_t> pinned_size;
   ~Ctx();

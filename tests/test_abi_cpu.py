@@ -41,6 +41,9 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.peps_expect(None, None, 0, None) == -1
     assert lib.peps_env_boundary(None, None, 0, None, None) == -1
     assert lib.peps_cluster_env(None, None, 0, None, 0, None, None) == -1
+    assert lib.peps_ctx_graphs(None, 1) == -1
+    assert lib.peps_ctx_autotune(None, 1) == -1
+    assert lib.peps_ctx_stats(None, None, None, None, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):

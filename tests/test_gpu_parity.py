@@ -135,6 +135,66 @@ def test_wide_and_tall_qr_blocks(sess, L, D, chi, dist, seed):
     assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
 
+def test_graph_replay_bitwise(sess):
+    """Launch sequences replayed from captured HIP graphs give the op-by-op
+    results bit for bit, also after new tensor values are written into the
+    same device buffers (the replay reads them at execution time)."""
+    say("graph replay")
+    A1 = make_peps(5, 5, 3, "normal_unit", 71)
+    A2 = make_peps(5, 5, 3, "normal_unit", 72)
+    dev = binding.to_device(A1)
+
+    def one():
+        envs = sess.env_boundary([dev], 7, "f64", 3)
+        r = sess.expect(envs)[0]
+        for e in envs:
+            e.free()
+        return r
+
+    def load(A):
+        for row_d, row_h in zip(dev, A):
+            for t, h in zip(row_d, row_h):
+                t.copy_(binding.to_device([[h]])[0][0])
+
+    plain1 = one()
+    load(A2)
+    plain2 = one()
+    load(A1)
+    sess.ctx.graphs(True)
+    try:
+        replay = [one(), one()]   # capture, then replay
+        load(A2)
+        replay2 = one()
+    finally:
+        sess.ctx.graphs(False)
+    for r in replay:
+        for k in ("sz", "bond_h", "bond_v"):
+            assert np.array_equal(r[k], plain1[k])
+        assert r["log_norm"] == plain1["log_norm"]
+    for k in ("sz", "bond_h", "bond_v"):
+        assert np.array_equal(replay2[k], plain2[k])
+    ref = api.expect(api.env_boundary(A2, 7, 3))
+    assert max_obs_diff(replay2, ref) < TOL64
+
+
+def test_autotuned_shapes(sess):
+    """Launch shapes chosen by timing give the oracle's results, while tuning
+    and afterwards from the stored choices."""
+    say("autotune")
+    A = make_peps(6, 6, 3, "normal_unit", 81)
+    ref = api.expect(api.env_boundary(A, 9, 3))
+    sess.ctx.autotune(1)
+    try:
+        (r1,), _ = run_gpu(sess, [A], 9, H=3)
+    finally:
+        sess.ctx.autotune(0)
+    (r2,), _ = run_gpu(sess, [A], 9, H=3)
+    sess.ctx.autotune(2)
+    for r in (r1, r2):
+        assert max_obs_diff(r, ref) < TOL64
+        assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
 def test_cfg2_full_parity(sess):
     """8x8, D=4, near-product, chi=32: all 112 bonds and the norm."""
     say("cfg2 8x8 D=4 chi=32 f64")
