@@ -37,6 +37,14 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Value of lane l (uniform) of a double, returned to every lane.
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Sum over the 256 threads of a workgroup; every thread receives the same value.
 __device__ inline double block_sum256(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -760,7 +768,7 @@ __global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restric
           }
         }
       p = wave_sum(p);
-      const double x0 = __shfl(x0loc, j & 63, 64);
+      const double x0 = lane_value(x0loc, j & 63);
       const double nrm = sqrt(p);
       double beta = 0.0, tau = 0.0, scal = 0.0;
       if (nrm > 0.0) {
