@@ -518,7 +518,145 @@ __global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds,
   }
 }
 
+// BF16 form of the skinny contraction: fragments of eight consecutive k per
+// lane (16x16x32 MFMA), A read as float32 and rounded to bf16 (RNE) in
+// registers, B staged once per descriptor as bf16 with k contiguous so a
+// fragment is one 16-byte shared-memory read.  Same accumulation order as
+// the tiled bf16 kernel.
+template <class TC, int NB, int KSM>
+__global__ __launch_bounds__(256) void tcs_bf16_kernel(const TcDesc* __restrict__ ds, int nd, int ngroups, int kp) {
+  constexpr int NP = 16 * NB;
+  const int kpad = kp + 8;
+  extern __shared__ __align__(16) unsigned char tcs_smem[];
+  __bf16* Bs = (__bf16*)tcs_smem;                                                       // [NP][kpad]
+  int64_t* oAk = (int64_t*)(tcs_smem + ((size_t)NP * kpad * sizeof(__bf16) + 15) / 16 * 16);   // [kp]
+  int64_t* oCn = oAk + kp;                                                              // [NP]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (ngroups + gridDim.x - 1) / gridDim.x;
+  const int gend = min(ngroups, (blockIdx.x + 1) * per);
+  int cur = -1;
+  for (int g = blockIdx.x * per; g < gend; ++g) {
+    int lo = cur;
+    if (cur < 0 || (cur + 1 < nd && ds[cur + 1].tile_base <= g)) {
+      int a = cur < 0 ? 0 : cur + 1, b = nd - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ds[mid].tile_base <= g) a = mid; else b = mid - 1;
+      }
+      lo = a;
+    }
+    const TcDesc& d = ds[lo];
+    const int M = d.M, N = d.N, K = d.K;
+    if (lo != cur) {
+      __syncthreads();
+      const float* __restrict__ B = (const float*)d.B;
+      for (int i = tid; i < kp * NP; i += 256) {
+        const int n = i / kp, k = i - n * kp;
+        float v = 0.f;
+        if (k < K && n < N) {
+          int kk = k, nn = n;
+          int64_t o = 0;
+          for (int j = d.nk - 1; j >= 0; --j) {
+            o += (int64_t)(kk % d.dk[j]) * d.sBk[j];
+            kk /= d.dk[j];
+          }
+          for (int j = d.nn - 1; j >= 0; --j) {
+            o += (int64_t)(nn % d.dn[j]) * d.sBn[j];
+            nn /= d.dn[j];
+          }
+          v = B[o];
+        }
+        Bs[n * kpad + k] = (__bf16)v;
+      }
+      for (int k = tid; k < kp; k += 256) {
+        int64_t o = 0;
+        if (k < K) {
+          int kk = k;
+          for (int j = d.nk - 1; j >= 0; --j) {
+            o += (int64_t)(kk % d.dk[j]) * d.sAk[j];
+            kk /= d.dk[j];
+          }
+        }
+        oAk[k] = o;
+      }
+      for (int n = tid; n < NP; n += 256) {
+        int64_t o = 0;
+        if (n < N) {
+          int nn = n;
+          for (int j = d.nn - 1; j >= 0; --j) {
+            o += (int64_t)(nn % d.dn[j]) * d.sCn[j];
+            nn /= d.dn[j];
+          }
+        }
+        oCn[n] = o;
+      }
+      __syncthreads();
+      cur = lo;
+    }
+    const int m = ((g - d.tile_base) * 4 + wave) * 16 + (lane & 15);
+    const bool mok = m < M;
+    int64_t oa = 0, oc = 0;
+    if (mok) {
+      int mm = m;
+      for (int j = d.nm - 1; j >= 0; --j) {
+        const int x = mm % d.dm[j];
+        mm /= d.dm[j];
+        oa += (int64_t)x * d.sAm[j];
+        oc += (int64_t)x * d.sCm[j];
+      }
+    }
+    const float* __restrict__ A = (const float*)d.A;
+    const int nks = (K + 31) >> 5;
+    f4_t acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[j][r] = 0.f;
+    const int k8 = 8 * (lane >> 4);
+    for (int kb = 0; kb < nks; kb += KSM) {
+      float af[KSM][8];
+#pragma unroll
+      for (int q = 0; q < KSM; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = 32 * (kb + q) + k8 + e;
+          af[q][e] = (kb + q < nks && mok && k < K) ? A[oa + oAk[k]] : 0.f;
+        }
+#pragma unroll
+      for (int q = 0; q < KSM; ++q) {
+        if (kb + q >= nks) break;
+        bf8_t a8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a8[e] = (__bf16)af[q][e];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const bf8_t b8 = *(const bf8_t*)(Bs + (16 * j + (lane & 15)) * kpad + 32 * (kb + q) + k8);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b8, a8, acc[j], 0, 0, 0);
+        }
+      }
+    }
+    TC* __restrict__ C = (TC*)d.C;
+    const double alpha = d.alpha, beta = d.beta;
+    if (mok) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = 16 * j + 4 * (lane >> 4) + r;
+          if (n < N) {
+            const int64_t off = oc + oCn[n];
+            double v = alpha * (double)acc[j][r];
+            if (beta != 0.0) v += beta * (double)C[off];
+            C[off] = (TC)v;
+          }
+        }
+    }
+  }
+}
+
 int tcs_lds_bytes(int prec, int nb, int kp) {
+  if (prec == TP_BF16)
+    return (int)(((size_t)16 * nb * (kp + 8) * 2 + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
   const size_t el = prec == TP_F64 ? sizeof(double) : sizeof(float);
   return (int)(((size_t)kp * tcs_bpad(nb) * el + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
 }
@@ -557,6 +695,36 @@ static void launch_tcs_nb(int ksm, const TcDesc* d, int nd, int ngroups, int kp,
   }
 }
 
+template <class TC, int NB>
+static void launch_tcs_bf16_nb(int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
+  const int lds = tcs_lds_bytes(TP_BF16, NB, kp);
+  switch (ksm) {
+    case 2: {
+      const int g = resident_grid(tcs_bf16_kernel<TC, NB, 2>, lds, ngroups);
+      tcs_bf16_kernel<TC, NB, 2><<<g, 256, lds, s>>>(d, nd, ngroups, kp);
+      break;
+    }
+    case 4: {
+      const int g = resident_grid(tcs_bf16_kernel<TC, NB, 4>, lds, ngroups);
+      tcs_bf16_kernel<TC, NB, 4><<<g, 256, lds, s>>>(d, nd, ngroups, kp);
+      break;
+    }
+    default: throw Error(ST_INVALID, "bad skinny k range");
+  }
+}
+
+template <class TC>
+static void launch_tcs_bf16(int nb, int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
+  switch (nb) {
+    case 1: launch_tcs_bf16_nb<TC, 1>(ksm, d, nd, ngroups, kp, s); break;
+    case 2: launch_tcs_bf16_nb<TC, 2>(ksm, d, nd, ngroups, kp, s); break;
+    case 3: launch_tcs_bf16_nb<TC, 3>(ksm, d, nd, ngroups, kp, s); break;
+    case 4: launch_tcs_bf16_nb<TC, 4>(ksm, d, nd, ngroups, kp, s); break;
+    case 5: launch_tcs_bf16_nb<TC, 5>(ksm, d, nd, ngroups, kp, s); break;
+    default: throw Error(ST_INVALID, "bad skinny width");
+  }
+}
+
 template <class P, class TC>
 static void launch_tcs_p(int nb, int ksm, const TcDesc* d, int nd, int ngroups, int kp, hipStream_t s) {
   switch (nb) {
@@ -579,7 +747,9 @@ void launch_tcs(int prec, int out_dt, int nb, int ksm, const TcDesc* d, int nd, 
     if (out_dt == DT_F64) launch_tcs_p<PolF32, double>(nb, ksm, d, nd, ngroups, kp, s);
     else launch_tcs_p<PolF32, float>(nb, ksm, d, nd, ngroups, kp, s);
   } else {
-    throw Error(ST_INVALID, "skinny contraction: f64 or f32 only");
+    if (kp % 32 != 0) throw Error(ST_INVALID, "bad skinny k range");
+    if (out_dt == DT_F64) launch_tcs_bf16<double>(nb, ksm, d, nd, ngroups, kp, s);
+    else launch_tcs_bf16<float>(nb, ksm, d, nd, ngroups, kp, s);
   }
   PE_HIP(hipGetLastError());
 }

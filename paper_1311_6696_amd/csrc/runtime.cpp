@@ -313,7 +313,7 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   for (int f = 0; f < N_FAMILIES; ++f) {
     if (fam[f].empty()) continue;
     std::vector<TcDesc> sk, rest;
-    for (const auto& d : fam[f]) ((f != 2 && prec != TP_BF16 && skinny_fits(d)) ? sk : rest).push_back(d);
+    for (const auto& d : fam[f]) ((f != 2 && skinny_fits(d)) ? sk : rest).push_back(d);
     const uint64_t key[2] = {sk.empty() ? 0 : tune_key(prec, out_dt, f, true, sk),
                              rest.empty() ? 0 : tune_key(prec, out_dt, f, false, rest)};
     bool tuned = ctx_->tuning && scratch_;
@@ -348,7 +348,7 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
 void Rec::apply_choice(int prec, int out_dt, int fam, int choice, std::vector<TcDesc> ds, bool algorithmic) {
   if (choice == HEURISTIC || choice == SKINNY) {
     bool fits = true;
-    for (const auto& d : ds) fits = fits && fam != 2 && prec != TP_BF16 && skinny_fits(d);
+    for (const auto& d : ds) fits = fits && fam != 2 && skinny_fits(d);
     if (fits && tcs_launch(prec, out_dt, ds, algorithmic)) return;
     const int tile = pick_tile(fam, ds);
     tc_launch(prec, out_dt, tile, std::move(ds), algorithmic, true);
@@ -403,7 +403,6 @@ int Rec::tune(int prec, int out_dt, int fam, bool skinny, const std::vector<TcDe
 // per CU.  Returns false (nothing recorded) when the group does not qualify.
 
 bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic) {
-  if (prec == TP_BF16) return false;
   int maxN = 0, maxK = 0;
   int64_t groups = 0;
   for (const auto& d : ds) {
@@ -412,7 +411,8 @@ bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorit
     maxK = std::max(maxK, d.K);
     groups += (d.M + 63) / 64;
   }
-  const int nb = (maxN + 15) / 16, kp = (maxK + 3) / 4 * 4;
+  const int kq = prec == TP_BF16 ? 32 : 4;   // k per MFMA step
+  const int nb = (maxN + 15) / 16, kp = (maxK + kq - 1) / kq * kq;
   if (groups < 256 || groups >= INT_MAX || tcs_lds_bytes(prec, nb, kp) > 64 * 1024) return false;
   int64_t base = 0;
   double fl = 0.0;
@@ -428,7 +428,7 @@ bool Rec::tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorit
   Op op{OK_TCS, prec, out_dt, TT_S16 + nb - 1, (int)ds.size(), (int)groups,
         push_bytes(ds.data(), ds.size() * sizeof(TcDesc)), algorithmic ? fl : 0.0};
   for (const auto& d : ds) op.bytes += tc_bytes(prec, out_dt, d);
-  op.ksm = kp <= 32 ? 8 : 16;
+  op.ksm = prec == TP_BF16 ? (kp <= 64 ? 2 : 4) : (kp <= 32 ? 8 : 16);
   op.kp = kp;
   if (algorithmic) flops_ += fl;
   ops_.push_back(op);
