@@ -18,7 +18,7 @@ STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UN
 OPTS_PER_STATE = 1   # peps_env_opts.flags: one options record per state
 DEFAULT_SEED = 0x13116696
 TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16", "128x48", "64x80",
-         "skinny16", "skinny32", "skinny48", "skinny64", "skinny80")
+         "skinny16", "skinny32", "skinny48", "skinny64", "skinny80", "ketbra16", "ketbra32")
 N_STATS = 3 * 2 * len(TILES)
 
 
@@ -29,6 +29,8 @@ def variant_name(i):
     tile = TILES[i % len(TILES)]
     if tile.startswith("skinny"):
         return f"tcs_kernel<{prec}, out={out}, N<={tile[6:]}>"
+    if tile.startswith("ketbra"):
+        return f"kb_kernel<{prec}, out={out}, dr*p<={tile[6:]}>"
     return f"tc_kernel<{prec}, out={out}, {tile}>"
 
 

@@ -272,6 +272,8 @@ peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable) {
   });
 }
 
+static_assert(Ctx::NSTAT == PEPS_N_STATS, "statistics table size is part of the ABI");
+
 peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches, double* bytes) {
   return guarded([&] {
     PE_REQUIRE(ctx && flops && ms && launches, "arguments must not be NULL");

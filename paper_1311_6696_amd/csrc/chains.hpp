@@ -33,18 +33,36 @@ inline TV site_tv(const Site& s, int op, bool flip, int dt, const std::string& l
 
 inline double tc_flops(const TcDesc& d) { return 2.0 * d.M * (double)d.N * d.K; }
 
-// Per-stage descriptor lists of one batched chain; `flops` sums the
-// algorithmic flops of every descriptor pushed through add().
+// Per-stage descriptor lists of one batched chain (plain and fused ket-bra
+// contractions); `flops` sums the algorithmic flops of every descriptor
+// pushed.  `prec` decides whether a ket-bra pair may run fused.
 struct St {
   std::vector<std::vector<TcDesc>> s;
+  std::vector<std::vector<KbDesc>> k;
   double flops = 0.0;
-  explicit St(int n) : s(n) {}
+  int prec = TP_F64;
+  St(int n, int prec_) : s(n), k(n), prec(prec_) {}
   void add(int stage, const TcDesc& d) {
     s[stage].push_back(d);
     flops += tc_flops(d);
   }
-  void record(Rec& rec, int prec, int cdt) {
-    for (auto& v : s) rec.tc(prec, cdt, v);
+  void add_kb(int stage, const KbDesc& d) {
+    k[stage].push_back(d);
+    flops += kb_flops(d);
+  }
+  // Ket and bra of one site into `out` in one fused launch when the fused
+  // kernel takes it (returns true); else nothing is added.
+  bool add_fused(int stage, const TV& out, const TV& x, const TV& ket, const TV& bra) {
+    const KbDesc d = kb_build(out, x, ket, bra);
+    if (!kb_fits(d, prec)) return false;
+    add_kb(stage, d);
+    return true;
+  }
+  void record(Rec& rec, int prec_, int cdt) {
+    for (size_t i = 0; i < s.size(); ++i) {
+      rec.tc(prec_, cdt, s[i]);
+      rec.kb(prec_, cdt, k[i]);
+    }
   }
 };
 
@@ -54,6 +72,8 @@ inline TV chain_left(St& st, const TV& E, const TV& T, const TV& Ak, const TV& A
   const int64_t p = Ak.dim[0], Dr = Ak.dim[3], Dd = Ak.dim[4];
   TV y1 = dense(P, dt, "xlmuve", {X, Dl, Dl, Du, Du, Ee});
   st.add(0, tc_build(y1, E, T));
+  TV f = dense(Q, dt, "xdgrse", {X, Dd, Dd, Dr, Dr, Ee});   // fused: ket and bra in one launch, into Q
+  if (st.add_fused(1, f, y1, Ak, Ab)) return f;
   TV z = dense(Q, dt, "xdrpmve", {X, Dd, Dr, p, Dl, Du, Ee});
   st.add(1, tc_build(z, y1, Ak));
   TV y3 = dense(P, dt, "xdgrse", {X, Dd, Dd, Dr, Dr, Ee});
@@ -67,6 +87,8 @@ inline TV chain_right(St& st, const TV& F, const TV& T, const TV& Ak, const TV& 
   const int64_t p = Ak.dim[0], Dl = Ak.dim[1], Dd = Ak.dim[4];
   TV y1 = dense(P, dt, "yrsuva", {Y, Dr, Dr, Du, Du, Aa});
   st.add(0, tc_build(y1, F, T));
+  TV f = dense(Q, dt, "ydglma", {Y, Dd, Dd, Dl, Dl, Aa});
+  if (st.add_fused(1, f, y1, Ak, Ab)) return f;
   TV z = dense(Q, dt, "ydlpsva", {Y, Dd, Dl, p, Dr, Du, Aa});
   st.add(1, tc_build(z, y1, Ak));
   TV y3 = dense(P, dt, "ydglma", {Y, Dd, Dd, Dl, Dl, Aa});
@@ -87,6 +109,16 @@ inline TV chain2_left(St& st, const TV& L, const TV& T, const TV& A1k, const TV&
   const int64_t p2 = A2k.dim[0], Dr2 = A2k.dim[3], Dd2 = A2k.dim[4];
   TV y1 = dense(P, dt, "xLMlmuve", {X, D2l, D2l, D1l, D1l, Du, Du, Ee});
   st.add(0, tc_build(y1, L, T));
+  // both rows fused (ket and bra of a row in one launch, Q then P), or both
+  // through the plain chain (P -> Q -> P -> Q -> P)
+  TV y2q = dense(Q, dt, "xLMdgrse", {X, D2l, D2l, Dd1, Dd1, Dr1, Dr1, Ee});
+  TV y3p = dense(P, dt, "xDGRSrse", {X, Dd2, Dd2, Dr2, Dr2, Dr1, Dr1, Ee});
+  const KbDesc k1 = kb_build(y2q, y1, A1k, A1b), k2 = kb_build(y3p, y2q, A2k, A2b);
+  if (kb_fits(k1, st.prec) && kb_fits(k2, st.prec)) {
+    st.add_kb(1, k1);
+    st.add_kb(3, k2);
+    return y3p;
+  }
   TV z1 = dense(Q, dt, "xLMdrpmve", {X, D2l, D2l, Dd1, Dr1, p1, D1l, Du, Ee});
   st.add(1, tc_build(z1, y1, A1k));
   TV y2 = dense(P, dt, "xLMdgrse", {X, D2l, D2l, Dd1, Dd1, Dr1, Dr1, Ee});
@@ -106,6 +138,14 @@ inline TV chain2_right(St& st, const TV& R, const TV& T, const TV& A1k, const TV
   const int64_t p2 = A2k.dim[0], Dl2 = A2k.dim[1], Dd2 = A2k.dim[4];
   TV y1 = dense(P, dt, "yRSrsuva", {Y, Dr2, Dr2, Dr1, Dr1, Du, Du, Aa});
   st.add(0, tc_build(y1, R, T));
+  TV y2q = dense(Q, dt, "yRSdglma", {Y, Dr2, Dr2, Dd1, Dd1, Dl1, Dl1, Aa});
+  TV y3p = dense(P, dt, "yDGLMlma", {Y, Dd2, Dd2, Dl2, Dl2, Dl1, Dl1, Aa});
+  const KbDesc k1 = kb_build(y2q, y1, A1k, A1b), k2 = kb_build(y3p, y2q, A2k, A2b);
+  if (kb_fits(k1, st.prec) && kb_fits(k2, st.prec)) {
+    st.add_kb(1, k1);
+    st.add_kb(3, k2);
+    return y3p;
+  }
   TV z1 = dense(Q, dt, "yRSdlpsva", {Y, Dr2, Dr2, Dd1, Dl1, p1, Dr1, Du, Aa});
   st.add(1, tc_build(z1, y1, A1k));
   TV y2 = dense(P, dt, "yRSdglma", {Y, Dr2, Dr2, Dd1, Dd1, Dl1, Dl1, Aa});

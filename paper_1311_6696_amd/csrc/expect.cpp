@@ -302,7 +302,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         Q[i - g.first] = scr.get(esz * q);
       }
       for (int s = 0; s < maxLc; ++s) {
-        St st1(3), st2(5);
+        St st1(3, prec), st2(5, prec);
         std::vector<TcDesc> fin;
         std::vector<std::pair<TV, double*>> outs;
         for (size_t i = g.first; i < g.second; ++i) {
@@ -407,7 +407,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         }
       }
       for (auto g : budget_groups(sz, budget)) {
-        St st1(3), st2(5);
+        St st1(3, prec), st2(5, prec);
         std::vector<TcDesc> fin;
         std::vector<void*> tmp;
         for (size_t k = g.first; k < g.second; ++k) {

@@ -754,6 +754,195 @@ void launch_tcs(int prec, int out_dt, int nb, int ksm, const TcDesc* d, int nd, 
   PE_HIP(hipGetLastError());
 }
 
+// ===========================================================================
+// Fused ket-bra contraction (see KbDesc).  One workgroup per 16-row block of
+// R at a time.  Phase 1: for a chunk of KB_QC values of q, waves form
+// Z_q[R][dr,p] = X[R; lu, q] K[lu; dr, p] on MFMA (A fragments straight from
+// global memory, K staged in shared memory) and leave Z in shared memory.
+// Phase 2: waves accumulate Y[R; dr, gs] += Z[R; dr, (p, q)] B[(p, q); gs]
+// for their dr values.  The ket intermediate never reaches global memory.
+// Limits of this kernel: dr*p <= 16*NB1, gs <= 16, dr <= 16, lu <= 64.
+// ===========================================================================
+__device__ inline int64_t kb_off(const KbGroup& g, int v, bool second) {
+  int64_t o = 0;
+  for (int j = g.n - 1; j >= 0; --j) {
+    const int x = v % g.dim[j];
+    v /= g.dim[j];
+    o += (int64_t)x * (second ? g.s1[j] : g.s0[j]);
+  }
+  return o;
+}
+
+__host__ __device__ constexpr int kb_np1pad(int nb1) { return 16 * nb1 + 2; }
+
+template <class P, class TC, int NB1>
+__global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, int nd, int nblocks, int lup,
+                                                 int pqp, int qmax) {
+  using T = typename P::T;
+  using L = typename P::L;
+  static_assert(P::KS == 4, "fragments of four k per lane group");
+  constexpr int NP1 = 16 * NB1, NP1PAD = kb_np1pad(NB1), BPAD = 18, KS1 = 16, DRW = 4;
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  L* Ks = (L*)kb_smem;                               // [lup][NP1PAD]
+  L* Bs = Ks + (size_t)lup * NP1PAD;                 // [pqp][BPAD]
+  L* Zs = Bs + (size_t)pqp * BPAD;                   // [KB_QC][NP1][16]
+  int64_t* oXlu = (int64_t*)(kb_smem + (((size_t)lup * NP1PAD + (size_t)pqp * BPAD + (size_t)KB_QC * NP1 * 16) *
+                                          sizeof(L) + 15) / 16 * 16);
+  int64_t* oXq = oXlu + lup;                         // [qmax]
+  int64_t* oYdr = oXq + qmax;                        // [16]
+  int64_t* oYgs = oYdr + 16;                         // [16]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (nblocks + gridDim.x - 1) / gridDim.x;
+  const int bend = min(nblocks, (blockIdx.x + 1) * per);
+  int cur = -1;
+  for (int blk = blockIdx.x * per; blk < bend; ++blk) {
+    int lo = cur;
+    if (cur < 0 || (cur + 1 < nd && ds[cur + 1].tile_base <= blk)) {
+      int a = cur < 0 ? 0 : cur + 1, b = nd - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ds[mid].tile_base <= blk) a = mid; else b = mid - 1;
+      }
+      lo = a;
+    }
+    const KbDesc& d = ds[lo];
+    const int LU = d.lu.size, Q = d.q.size, PP = d.p.size, DR = d.dr.size, GS = d.gs.size;
+    if (lo != cur) {
+      __syncthreads();   // the previous descriptor's tables are no longer read
+      const T* __restrict__ K = (const T*)d.K;
+      const T* __restrict__ B = (const T*)d.B;
+      for (int i = tid; i < lup * NP1; i += 256) {
+        const int k = i / NP1, n = i - k * NP1;
+        T v = T(0);
+        if (k < LU && n < DR * PP)
+          v = K[kb_off(d.lu, k, true) + kb_off(d.dr, n / PP, false) + kb_off(d.p, n % PP, false)];
+        Ks[k * NP1PAD + n] = (L)v;
+      }
+      for (int i = tid; i < pqp * 16; i += 256) {
+        const int k = i >> 4, c = i & 15;
+        T v = T(0);
+        if (k < PP * Q && c < GS) v = B[kb_off(d.p, k % PP, true) + kb_off(d.q, k / PP, true) + kb_off(d.gs, c, false)];
+        Bs[k * BPAD + c] = (L)v;
+      }
+      for (int k = tid; k < lup; k += 256) oXlu[k] = k < LU ? kb_off(d.lu, k, false) : 0;
+      for (int q = tid; q < qmax; q += 256) oXq[q] = q < Q ? kb_off(d.q, q, false) : 0;
+      if (tid < 16) {
+        oYdr[tid] = tid < DR ? kb_off(d.dr, tid, true) : 0;
+        oYgs[tid] = tid < GS ? kb_off(d.gs, tid, true) : 0;
+      }
+      __syncthreads();
+      cur = lo;
+    }
+    const int ridx = (blk - d.tile_base) * 16 + (lane & 15);
+    const bool rok = ridx < d.r.size;
+    const int64_t oxr = rok ? kb_off(d.r, ridx, false) : 0;
+    const int64_t oyr = rok ? kb_off(d.r, ridx, true) : 0;
+    const T* __restrict__ X = (const T*)d.X;
+    const int nks1 = (LU + 3) >> 2;
+    typename P::Acc acc2[DRW];
+#pragma unroll
+    for (int t = 0; t < DRW; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[t][r] = 0;
+    for (int q0 = 0; q0 < Q; q0 += KB_QC) {
+      const int qc = min(KB_QC, Q - q0);
+      // phase 1: ket for this wave's q values of the chunk
+      for (int ql = wave; ql < qc; ql += 4) {
+        const int64_t ox = oxr + oXq[q0 + ql];
+        T af[KS1];
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+          const int k = 4 * ks + (lane >> 4);
+          af[ks] = (ks < nks1 && rok && k < LU) ? X[ox + oXlu[k]] : T(0);
+        }
+        typename P::Acc acc1[NB1];
+#pragma unroll
+        for (int j = 0; j < NB1; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc1[j][r] = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+          if (ks >= nks1) break;
+          const L* brow = Ks + (4 * ks + (lane >> 4)) * NP1PAD + (lane & 15);
+#pragma unroll
+          for (int j = 0; j < NB1; ++j) acc1[j] = P::mma(brow[16 * j], (typename P::F)af[ks], acc1[j]);
+        }
+        L* z = Zs + (size_t)ql * NP1 * 16 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < NB1; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[(16 * j + P::row(lane, r)) * 16] = (L)acc1[j][r];
+      }
+      __syncthreads();
+      // phase 2: bra for this wave's dr values, k = (p, q) with p fastest
+      const int nks2 = (PP * qc + 3) >> 2;
+#pragma unroll
+      for (int t = 0; t < DRW; ++t) {
+        const int dr = wave + 4 * t;
+        if (dr >= DR) break;
+        for (int ks = 0; ks < nks2; ++ks) {
+          const int k = 4 * ks + (lane >> 4);
+          const int ql = k / PP, pp = k - ql * PP;
+          const bool kok = ql < qc;
+          const L av = kok ? Zs[((size_t)ql * NP1 + dr * PP + pp) * 16 + (lane & 15)] : (L)0;
+          const L bv = kok ? Bs[(pp + PP * (q0 + ql)) * BPAD + (lane & 15)] : (L)0;
+          acc2[t] = P::mma(bv, av, acc2[t]);
+        }
+      }
+      __syncthreads();   // Z is rewritten by the next chunk
+    }
+    if (rok) {
+      TC* __restrict__ Y = (TC*)d.Y;
+#pragma unroll
+      for (int t = 0; t < DRW; ++t) {
+        const int dr = wave + 4 * t;
+        if (dr >= DR) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gs = P::row(lane, r);
+          if (gs < GS) Y[oyr + oYdr[dr] + oYgs[gs]] = (TC)acc2[t][r];
+        }
+      }
+    }
+  }
+}
+
+int kb_lds_bytes(int prec, int nb1, int lup, int pqp, int qmax) {
+  const size_t el = prec == TP_F64 ? sizeof(double) : sizeof(float);
+  const size_t tiles = ((size_t)lup * kb_np1pad(nb1) + (size_t)pqp * 18 + (size_t)KB_QC * 16 * nb1 * 16) * el;
+  return (int)((tiles + 15) / 16 * 16 + (size_t)(lup + qmax + 32) * sizeof(int64_t));
+}
+
+template <class P, class TC>
+static void launch_kb_p(int nb1, const KbDesc* d, int nd, int nblocks, int lup, int pqp, int qmax, hipStream_t s) {
+  const int prec = std::is_same<typename P::T, double>::value ? TP_F64 : TP_F32;
+  const int lds = kb_lds_bytes(prec, nb1, lup, pqp, qmax);
+  if (nb1 == 1) {
+    const int g = resident_grid(kb_kernel<P, TC, 1>, lds, nblocks);
+    kb_kernel<P, TC, 1><<<g, 256, lds, s>>>(d, nd, nblocks, lup, pqp, qmax);
+  } else if (nb1 == 2) {
+    const int g = resident_grid(kb_kernel<P, TC, 2>, lds, nblocks);
+    kb_kernel<P, TC, 2><<<g, 256, lds, s>>>(d, nd, nblocks, lup, pqp, qmax);
+  } else {
+    throw Error(ST_INVALID, "bad fused width");
+  }
+}
+
+void launch_kb(int prec, int out_dt, int nb1, const KbDesc* d, int nd, int nblocks, int lup, int pqp, int qmax,
+               hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (prec == TP_F64) {
+    if (out_dt != DT_F64) throw Error(ST_INVALID, "f64 contraction writes f64");
+    launch_kb_p<PolF64, double>(nb1, d, nd, nblocks, lup, pqp, qmax, s);
+  } else if (prec == TP_F32) {
+    if (out_dt == DT_F64) launch_kb_p<PolF32, double>(nb1, d, nd, nblocks, lup, pqp, qmax, s);
+    else launch_kb_p<PolF32, float>(nb1, d, nd, nblocks, lup, pqp, qmax, s);
+  } else {
+    throw Error(ST_INVALID, "fused contraction: f64 or f32 only");
+  }
+  PE_HIP(hipGetLastError());
+}
+
 // Split-K reduction: one thread per output element (256 per workgroup,
 // MT*NT/256 workgroups per tile); the partial slices are summed in slice
 // order, so the result does not depend on scheduling.

@@ -33,21 +33,51 @@ struct TcDesc {
   double* part;
 };
 
+// Fused ket-bra contraction (one site's two layers applied in one launch):
+//   Y[R; dr, gs] = sum_{p, q} (sum_{lu} X[R; lu, q] K[lu; dr, p]) B[p, q; gs]
+// Each index group lists its sub-dimensions outermost first with their
+// strides in the two tensors that hold it.
+constexpr int KB_MAXD = 4;
+struct KbGroup {
+  int32_t n, size;
+  int32_t dim[KB_MAXD];
+  int64_t s0[KB_MAXD], s1[KB_MAXD];
+};
+struct KbDesc {
+  const void* X;
+  const void* K;
+  const void* B;
+  void* Y;
+  KbGroup r;    // strides in X, Y (innermost unit-stride in both)
+  KbGroup lu;   // X, K
+  KbGroup q;    // X, B
+  KbGroup p;    // K, B
+  KbGroup dr;   // K, Y
+  KbGroup gs;   // B, Y
+  int32_t tile_base;   // first 16-row block of R, numbered across descriptors
+};
+// Launch of n_blocks 16-row blocks; nb1 = blocks of 16 over dr*p (1 or 2);
+// lup = 4*ceil(max lu/4), pqp = 4*ceil(max p*q/4), qmax = max q.
+void launch_kb(int prec, int out_dt, int nb1, const KbDesc* d_desc, int n_desc, int n_blocks, int lup, int pqp,
+               int qmax, hipStream_t s);
+int kb_lds_bytes(int prec, int nb1, int lup, int pqp, int qmax);
+constexpr int KB_QC = 8;   // q values per shared-memory chunk
+
 // Arithmetic of a contraction.
 enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 // Tile shapes (MT x NT per 256-thread workgroup).
 // TT_S16..TT_S80: the skinny kernel (64-row groups, N up to 16..80).
 enum TcTile : int {
   TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_64x32 = 4, TT_64x16 = 5, TT_128x48 = 6, TT_64x80 = 7,
-  TT_S16 = 8, TT_S32 = 9, TT_S48 = 10, TT_S64 = 11, TT_S80 = 12,
-  TT_COUNT = 13
+  TT_S16 = 8, TT_S32 = 9, TT_S48 = 10, TT_S64 = 11, TT_S80 = 12, TT_KB16 = 13, TT_KB32 = 14,
+  TT_COUNT = 15
 };
 inline int tile_mt(int t) {
-  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64, 128, 64, 64, 64, 64, 64, 64};
+  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64, 128, 64, 64, 64, 64, 64, 64, 16, 16};
   return v[t];
 }
 inline int tile_nt(int t) {
-  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16, 48, 80, 16, 32, 48, 64, 80};
+  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16, 48, 80, 16, 32, 48, 64, 80, 16, 32};
   return v[t];
 }
 // Statistics slot of a contraction variant.

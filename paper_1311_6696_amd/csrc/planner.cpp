@@ -99,7 +99,7 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
   for (AJob* j : js) maxLc = std::max(maxLc, j->Lc);
   // product tensors via the chain with identity environments (closings at the ends)
   for (int c = 0; c < maxLc; ++c) {
-    St st(3);
+    St st(3, prec);
     std::vector<TcDesc> fin;
     std::vector<EwDesc> fills;
     std::vector<void*> tmp;
@@ -133,7 +133,8 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       }
       const int64_t Ee = j->bin[c + 1];
       const int64_t nP = chain_scratch_P(E.dim[0], Dl, j->Tin->leg[c], Ee, Dr, j->Dd[c]);
-      const int64_t nQ = E.dim[0] * j->Dd[c] * Dr * j->Ak[c].dim[0] * Dl * j->Tin->leg[c] * Ee;
+      // Q also holds the fused ket-bra output, which has the size of a P tensor
+      const int64_t nQ = std::max(nP, E.dim[0] * j->Dd[c] * Dr * j->Ak[c].dim[0] * Dl * j->Tin->leg[c] * Ee);
       void* P = scr.get(nP * esz);
       void* Q = scr.get(nQ * esz);
       tmp.push_back(P);
@@ -143,7 +144,10 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       fin.push_back(tc_build(X, y3, F));
     }
     rec.ew(fills);
-    for (auto& v : st.s) rec.tc(prec, cdt, v, false);
+    for (size_t i = 0; i < st.s.size(); ++i) {
+      rec.tc(prec, cdt, st.s[i], false);
+      rec.kb(prec, cdt, st.k[i], false);
+    }
     rec.tc(prec, DT_F64, fin, false);
     for (void* p : tmp) scr.put(p);
   }
@@ -233,7 +237,7 @@ void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
   cast_copies(rec, js, o);
   // right environments of the start
   for (int s = 0; s + 1 < maxLc; ++s) {
-    St st(3);
+    St st(3, prec);
     std::vector<TcDesc> env;
     for (AJob* j : js) {
       const int c = j->Lc - 1 - s;
@@ -250,7 +254,7 @@ void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
   for (int h = 0; h < H; ++h) {
     const bool l2r = (h % 2 == 0);
     for (int s = 0; s < maxLc; ++s) {
-      St st(3);
+      St st(3, prec);
       std::vector<TcDesc> site, env;
       std::vector<QrDesc> qrs;
       std::vector<AJob*> upd;

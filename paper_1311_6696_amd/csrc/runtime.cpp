@@ -221,8 +221,75 @@ TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha, double beta
   return d;
 }
 
+// Fused ket-bra descriptor from labelled views: every label of the four
+// views lies in exactly two of them, which fixes its group.  Sub-dimensions
+// of a group follow the label order of the view named last (R and the
+// output groups follow Y, so R ends with Y's unit-stride index).
+KbDesc kb_build(const TV& Y, const TV& X, const TV& K, const TV& B) {
+  KbDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.X = X.p;
+  d.K = K.p;
+  d.B = B.p;
+  d.Y = const_cast<void*>(Y.p);
+  auto group = [](KbGroup& g, const TV& t0, const TV& t1, const TV& order, const TV& excl1, const TV& excl2) {
+    std::vector<Sub> subs;
+    for (size_t i = 0; i < order.idx.size(); ++i) {
+      const char c = order.idx[i];
+      const int i0 = find_idx(t0, c), i1 = find_idx(t1, c);
+      if (i0 < 0 || i1 < 0) continue;
+      PE_REQUIRE(find_idx(excl1, c) < 0 && find_idx(excl2, c) < 0, std::string("index '") + c + "' in three views");
+      PE_REQUIRE(t0.dim[i0] == t1.dim[i1], std::string("dimension mismatch of '") + c + "'");
+      if (t0.dim[i0] > 1) subs.push_back({t0.dim[i0], t0.str[i0], t1.str[i1]});
+    }
+    merge_subs(subs);
+    PE_REQUIRE(subs.size() <= (size_t)KB_MAXD, "fused contraction group with more than 4 sub-dimensions");
+    g.n = (int)subs.size();
+    int64_t size = 1;
+    for (int j = 0; j < g.n; ++j) {
+      g.dim[j] = (int32_t)subs[j].dim;
+      g.s0[j] = subs[j].s1;
+      g.s1[j] = subs[j].s2;
+      size *= subs[j].dim;
+    }
+    PE_REQUIRE(size < INT_MAX, "fused contraction too large");
+    g.size = (int32_t)size;
+  };
+  group(d.r, X, Y, Y, K, B);
+  group(d.lu, X, K, K, Y, B);
+  group(d.q, X, B, B, Y, K);
+  group(d.p, K, B, K, X, Y);
+  group(d.dr, K, Y, Y, X, B);
+  group(d.gs, B, Y, Y, X, K);
+  // every label lies in two views
+  for (const TV* t : {&X, &K, &B, &Y})
+    for (size_t i = 0; i < t->idx.size(); ++i) {
+      const char c = t->idx[i];
+      const int n = (find_idx(X, c) >= 0) + (find_idx(K, c) >= 0) + (find_idx(B, c) >= 0) + (find_idx(Y, c) >= 0);
+      PE_REQUIRE(n == 2 || t->dim[i] == 1, std::string("index '") + c + "' must be in exactly two views");
+    }
+  return d;
+}
+
+// The fused kernel pays off for long R (the two-row sandwiches); for short
+// R (ALS site steps) its per-block serial phases cost more latency than the
+// two separate launches.
+bool kb_fits(const KbDesc& d, int prec) {
+  if (prec == TP_BF16 || d.r.size < 4096) return false;
+  if (d.r.n < 1 || d.r.s0[d.r.n - 1] != 1 || d.r.s1[d.r.n - 1] != 1) return false;
+  if (d.dr.size * d.p.size > 32 || d.gs.size > 16 || d.dr.size > 16 || d.lu.size > 64) return false;
+  const int nb1 = d.dr.size * d.p.size > 16 ? 2 : 1;
+  const int lup = (d.lu.size + 3) / 4 * 4, pqp = (d.p.size * d.q.size + 3) / 4 * 4;
+  return kb_lds_bytes(prec, nb1, lup, pqp, d.q.size) <= 64 * 1024;
+}
+
+double kb_flops(const KbDesc& d) {
+  const double r = d.r.size, lu = d.lu.size, q = d.q.size, p = d.p.size, dr = d.dr.size, gs = d.gs.size;
+  return 2.0 * r * lu * q * dr * p + 2.0 * r * dr * p * q * gs;
+}
+
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -485,6 +552,36 @@ void Rec::tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool
   if (ksplit > 1) ops_.push_back(Op{OK_TCR, prec, out_dt, tile, (int)ds.size(), (int)tbase, op.off, 0.0});
 }
 
+void Rec::kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic) {
+  if (ds.empty()) return;
+  int nb1 = 1, lup = 4, pqp = 4, qmax = 1;
+  int64_t blocks = 0;
+  double fl = 0.0, by = 0.0;
+  const double es = prec == TP_F64 ? 8.0 : 4.0, os = out_dt == DT_F64 ? 8.0 : 4.0;
+  for (auto& d : ds) {
+    PE_REQUIRE(kb_fits(d, prec), "fused contraction outside the kernel's limits");
+    nb1 = std::max(nb1, d.dr.size * d.p.size > 16 ? 2 : 1);
+    lup = std::max(lup, (d.lu.size + 3) / 4 * 4);
+    pqp = std::max(pqp, (d.p.size * d.q.size + 3) / 4 * 4);
+    qmax = std::max(qmax, d.q.size);
+    d.tile_base = (int32_t)blocks;
+    blocks += (d.r.size + 15) / 16;
+    fl += kb_flops(d);
+    by += es * ((double)d.r.size * d.lu.size * d.q.size + (double)d.lu.size * d.dr.size * d.p.size +
+                (double)d.p.size * d.q.size * d.gs.size) +
+          os * (double)d.r.size * d.dr.size * d.gs.size;
+  }
+  PE_REQUIRE(blocks < INT_MAX && kb_lds_bytes(prec, nb1, lup, pqp, qmax) <= 64 * 1024, "fused contraction too large");
+  Op op{OK_KB, prec, out_dt, TT_KB16 + nb1 - 1, (int)ds.size(), (int)blocks,
+        push_bytes(ds.data(), ds.size() * sizeof(KbDesc)), algorithmic ? fl : 0.0};
+  op.ksm = lup;
+  op.kp = pqp;
+  op.q = qmax;
+  op.bytes = by;
+  if (algorithmic) flops_ += fl;
+  ops_.push_back(op);
+}
+
 // Householder QR of every block of the group.  Blocks that fit a
 // register-resident variant run as one grouped launch; taller blocks with at
 // most TSQR_NMAX columns are factored as a tree (TSQR): row blocks of at most
@@ -602,7 +699,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
     void* e0 = nullptr;
-    if (timed && (op.kind == OK_TC || op.kind == OK_TCS)) {
+    if (timed && (op.kind == OK_TC || op.kind == OK_TCS || op.kind == OK_KB)) {
       e0 = dev::event_create();
       dev::event_record(e0, s);
     }
@@ -611,6 +708,9 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
       case OK_TCR: launch_tc_reduce(op.out_dt, op.tile, (const TcDesc*)d, op.nd, op.grid, s); break;
       case OK_TCS:
         launch_tcs(op.prec, op.out_dt, op.tile - TT_S16 + 1, op.ksm, (const TcDesc*)d, op.nd, op.grid, op.kp, s);
+        break;
+      case OK_KB:
+        launch_kb(op.prec, op.out_dt, op.tile - TT_KB16 + 1, (const KbDesc*)d, op.nd, op.grid, op.ksm, op.kp, op.q, s);
         break;
       case OK_QR:
         if (op.tile >= 0) launch_qr_reg(op.tile, (const QrDesc*)d, op.nd, s);
@@ -661,7 +761,7 @@ void Rec::flush_graph() {
     key.insert(key.end(), b, b + n);
   };
   for (const Op& op : ops_) {
-    const int32_t f[9] = {op.kind, op.prec, op.out_dt, op.tile, op.nd, op.grid, (int32_t)op.off, op.ksm, op.kp};
+    const int32_t f[10] = {op.kind, op.prec, op.out_dt, op.tile, op.nd, op.grid, (int32_t)op.off, op.ksm, op.kp, op.q};
     put(f, sizeof(f));
   }
   for (const auto& a : aux_) {

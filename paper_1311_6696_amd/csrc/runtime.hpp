@@ -67,6 +67,11 @@ TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_
 TV relabel(TV v, const std::string& idx);
 // C = alpha * contraction(X, Y) + beta * C, every index in exactly two views.
 TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha = 1.0, double beta = 0.0);
+// Y = (X contracted with the ket site K) contracted with the bra site B in one
+// fused launch (see KbDesc); kb_fits tells whether the kernel takes it.
+KbDesc kb_build(const TV& Y, const TV& X, const TV& K, const TV& B);
+bool kb_fits(const KbDesc& d, int prec);
+double kb_flops(const KbDesc& d);
 
 // --------------------------------------------------------------- recorder ---
 // Records grouped launches and their descriptors, then uploads every
@@ -77,6 +82,7 @@ class Rec {
   // `scratch` (optional) provides record-time workspace, e.g. split-K partials.
   explicit Rec(Ctx* c, Arena* scratch = nullptr) : ctx_(c), scratch_(scratch) {}
   void tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic = true);
+  void kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic = true);
   void qr(const std::vector<QrDesc>& ds);
   void reduce(std::vector<RedDesc> ds);
   void ew(std::vector<EwDesc> ds);
@@ -96,7 +102,8 @@ class Rec {
     int kind, prec, out_dt, tile, nd, grid;
     size_t off;
     double flops;
-    int ksm = 0, kp = 0;   // skinny contraction: k-steps per load batch, padded K
+    int ksm = 0, kp = 0;   // skinny contraction: k-steps per load batch, padded K (fused: padded lu, p*q)
+    int q = 0;             // fused contraction: largest q
     double bytes = 0.0;    // algorithmic bytes: operands read once, output written once
   };
   size_t push_bytes(const void* p, size_t n);

@@ -57,3 +57,12 @@ def test_struct_layouts_match_header():
     assert C.sizeof(binding.Opts) == 4 * 4 + 8
     assert C.sizeof(binding.Window) == 7 * 4
     assert C.sizeof(binding.Result) == 5 * 8
+
+
+def test_statistics_table_size_matches_header():
+    """The binding's statistics arrays have the size the header declares
+    (the library writes that many entries)."""
+    text = open(os.path.join(ROOT, "include", "peps_env.h")).read()
+    n = int(re.search(r"#define PEPS_N_STATS (\d+)", text).group(1))
+    assert binding.N_STATS == n
+    assert len(binding.TILES) * 6 == n
