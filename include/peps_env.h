@@ -132,6 +132,28 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
 
 void peps_env_free(peps_env* env);
 
+/* Thin QR of n_blocks float64 blocks, the gauge step of the truncation
+ * (Sec. 2: the ALS sweep keeps every tensor but the centre isometric):
+ * A = Q R with A m x n (m >= n >= 1, n <= 1024), Q m x n with orthonormal
+ * columns, R n x n upper triangular with R_ii >= 0 (for full column rank
+ * the unique such factors).  a, q, r are DEVICE pointers with element
+ * strides (row, column); r may be NULL; q may be a itself with the same
+ * strides (in-place), otherwise the outputs must not overlap any input.
+ * The blk array is host memory.  All blocks run as one batched group with
+ * the kernels of the boundary truncation: CholeskyQR2 for tall blocks up to
+ * 512 x 32 (Householder when a block is too ill-conditioned for it),
+ * register-resident Householder, TSQR or the streaming kernel otherwise. */
+typedef struct {
+  const double* a;
+  int64_t a_rs, a_cs;
+  double* q;
+  int64_t q_rs, q_cs;
+  double* r;
+  int64_t r_rs, r_cs;
+  int32_t m, n;
+} peps_qr_block;
+peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
+
 /* Diagnostics of an environment: number of truncated rows, and the squared
  * norm of the ALS centre tensor after each half-sweep of each truncated row
  * (host buffer of at least n_rows*halfsweeps doubles; may be NULL). */

@@ -55,6 +55,13 @@ class Window(C.Structure):
                 ("c1", C.c_int32), ("ci", C.c_int32), ("cj", C.c_int32)]
 
 
+class QrBlock(C.Structure):
+    _fields_ = [("a", C.c_void_p), ("a_rs", C.c_int64), ("a_cs", C.c_int64),
+                ("q", C.c_void_p), ("q_rs", C.c_int64), ("q_cs", C.c_int64),
+                ("r", C.c_void_p), ("r_rs", C.c_int64), ("r_cs", C.c_int64),
+                ("m", C.c_int32), ("n", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("log_norm", C.c_double), ("norm_sign", C.c_double), ("sz", C.POINTER(C.c_double)),
                 ("bond", C.POINTER(C.c_double)), ("flops", C.c_double)]
@@ -62,7 +69,7 @@ class Result(C.Structure):
 
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
-           "peps_ctx_stats", "peps_ctx_set_workspace",
+           "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr",
            "peps_last_error")
 
 _lib = None
@@ -93,6 +100,7 @@ def load(path=None):
     lib.peps_ctx_set_workspace.argtypes = [vp, C.c_uint64]
     lib.peps_ctx_graphs.argtypes = [vp, C.c_int32]
     lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
+    lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
@@ -255,6 +263,12 @@ class Context:
     def set_workspace(self, nbytes):
         _check(self.lib, self.lib.peps_ctx_set_workspace(self.handle, int(nbytes)))
 
+    def qr_raw(self, blocks):
+        """blocks: sequence of (a, a_rs, a_cs, q, q_rs, q_cs, r, r_rs, r_cs, m, n)
+        with device addresses (r may be 0)."""
+        arr = (QrBlock * len(blocks))(*[QrBlock(*[int(v) if v is not None else None for v in b]) for b in blocks])
+        _check(self.lib, self.lib.peps_qr(self.handle, arr, len(blocks)))
+
 
 # ------------------------------------------------------------ torch layer ---
 
@@ -297,3 +311,21 @@ class Session:
 
     def expect(self, envs):
         return self.ctx.expect(envs)
+
+    def qr(self, mats, inplace=False):
+        """Thin QR (R_ii >= 0) of float64 GPU matrices (2-D tensors, any
+        strides), as one batched call.  Returns [(Q, R)]; with inplace=True
+        Q overwrites each input."""
+        torch = self.torch
+        out, blocks = [], []
+        for A in mats:
+            if not A.is_cuda or A.dtype != torch.float64 or A.dim() != 2:
+                raise ValueError("QR blocks must be 2-D float64 GPU tensors")
+            m, n = A.shape
+            Q = A if inplace else torch.empty((m, n), dtype=torch.float64, device=A.device)
+            R = torch.empty((n, n), dtype=torch.float64, device=A.device)
+            blocks.append((A.data_ptr(), A.stride(0), A.stride(1), Q.data_ptr(), Q.stride(0), Q.stride(1),
+                           R.data_ptr(), R.stride(0), R.stride(1), m, n))
+            out.append((Q, R))
+        self.ctx.qr_raw(blocks)
+        return out

@@ -238,6 +238,30 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, d
   });
 }
 
+peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && blk, "ctx and blk must not be NULL");
+    PE_REQUIRE(n_blocks >= 1, "n_blocks must be >= 1");
+    for (int i = 0; i < n_blocks; ++i) {
+      const peps_qr_block& b = blk[i];
+      const std::string w = "block " + std::to_string(i) + ": ";
+      PE_REQUIRE(b.a && b.q, w + "a and q must not be NULL");
+      PE_REQUIRE(b.n >= 1 && b.m >= b.n && b.n <= 1024, w + "needs m >= n >= 1 and n <= 1024");
+    }
+    dev::set_device(ctx->c->device);
+    Arena call(&ctx->c->pool);
+    Rec rec(ctx->c.get(), &call);
+    std::vector<QrDesc> ds;
+    for (int i = 0; i < n_blocks; ++i) {
+      const peps_qr_block& b = blk[i];
+      double* w = (double*)call.alloc(sizeof(double) * 2 * (size_t)b.m * b.n);   // streaming-kernel workspace
+      ds.push_back(QrDesc{b.a, b.a_rs, b.a_cs, b.q, b.q_rs, b.q_cs, b.r, b.r_rs, b.r_cs, w, b.m, b.n});
+    }
+    rec.qr(ds);
+    rec.run(call);
+  });
+}
+
 peps_status peps_ctx_autotune(peps_ctx* ctx, int32_t mode) {
   return guarded([&] {
     PE_REQUIRE(ctx != nullptr, "ctx must not be NULL");

@@ -1093,15 +1093,19 @@ void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
 // place below the diagonal) and are broadcast through shared memory, so no
 // global memory is touched between the first load and the final stores.
 // ===========================================================================
+// Shared memory of qr_house: 2*64*RPW + 2 + 2*NW*NCW doubles.
 template <int RPW, int NCW, int NW>
-__global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restrict__ ds) {
-  const QrDesc& d = ds[blockIdx.x];
+__host__ __device__ constexpr int qr_house_lds() { return 2 * 64 * RPW + 2 + 2 * NW * NCW; }
+
+template <int RPW, int NCW, int NW>
+__device__ __attribute__((always_inline)) inline void qr_house(const QrDesc& d, double* sm) {
   const int m = d.m, n = d.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NMAX = NW * NCW, MMAX = 64 * RPW;
-  __shared__ double vbuf[2][MMAX];
-  __shared__ double scl[2];
-  __shared__ double taus[NMAX], rdiag[NMAX];
+  double (*vbuf)[MMAX] = (double (*)[MMAX])sm;   // [2][MMAX]
+  double* scl = sm + 2 * MMAX;                   // [2]
+  double* taus = scl + 2;                        // [NMAX]
+  double* rdiag = taus + NMAX;                   // [NMAX]
   double a[RPW][NCW];
 #pragma unroll
   for (int s = 0; s < RPW; ++s)
@@ -1231,6 +1235,375 @@ __global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restric
     }
 }
 
+template <int RPW, int NCW, int NW>
+__global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restrict__ ds) {
+  __shared__ double sm[qr_house_lds<RPW, NCW, NW>()];
+  qr_house<RPW, NCW, NW>(ds[blockIdx.x], sm);
+}
+
+// ===========================================================================
+// CholeskyQR2 for tall blocks: m <= 32*CPW rows, n <= 16*NB columns, eight
+// waves, one workgroup per block.  Pass 1: G = A^T A on MFMA (one partial
+// tile set per wave, summed in wave order), G = R1^T R1 and W1 = R1^-1 in one
+// wave, Q1 = A W1.  Pass 2 does the same for Q1 (G2 = R2^T R2, Q = Q1 W2) and
+// R = R2 R1.  When A is not too ill-conditioned the second pass makes Q
+// orthonormal to working precision and (Q, R) agree with the Householder
+// factors to the conditioning of the problem.  Otherwise the block is
+// factored by Householder in the same launch: the fallback is taken when a
+// pivot of the first Cholesky is not clearly positive relative to its
+// diagonal entry, or when an entry of Q1^T Q1 - I exceeds 1e-2.  Nothing is
+// stored before that decision, so Q may alias A.
+//
+// Wave w owns rows [4*CPW*w, 4*CPW*(w+1)) and keeps two register images:
+//   Gram image  g[c][b] = X[4*CPW*w + 4c + (lane>>4)][16b + (lane&15)]
+//               (operand with k over rows: X^T X),
+//   row image   x[t][s] = X[4*CPW*w + 16t + (lane&15)][4s + (lane>>4)]
+//               (operand with k over columns: X W).
+// Only the image whose lanes follow the smaller stride is read from memory;
+// the other comes from products with 0/1 selectors, which are exact, so both
+// images hold the same bits.  A product from the row image comes out of
+// the MFMA as a Gram image (or, with the operands swapped, as a row image).
+// ===========================================================================
+__device__ inline d4_t mfma64(double x, double y, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+
+// 1/sqrt(x): hardware estimate refined by two Newton steps.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Selector of 4-lane groups: 1 where lane & 15 == 4*cc + (lane >> 4).
+__device__ inline double cq_sel(int cc, int lane) { return (lane & 15) == 4 * cc + (lane >> 4) ? 1.0 : 0.0; }
+
+// Row image from the Gram image.
+template <int NB, int CPW>
+__device__ __attribute__((always_inline)) inline void cq_to_rows(const double (&g)[CPW][NB],
+                                                                 double (&x)[CPW / 4][4 * NB], int lane) {
+#pragma unroll
+  for (int t = 0; t < CPW / 4; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) acc = mfma64(g[4 * t + cc][b], cq_sel(cc, lane), acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[t][4 * b + r] = acc[r];
+    }
+}
+
+// Gram image from the row image.
+template <int NB, int CPW>
+__device__ __attribute__((always_inline)) inline void cq_to_gram(const double (&x)[CPW / 4][4 * NB],
+                                                                 double (&g)[CPW][NB], int lane) {
+#pragma unroll
+  for (int t = 0; t < CPW / 4; ++t)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) acc = mfma64(x[t][4 * b + sl], cq_sel(sl, lane), acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g[4 * t + r][b] = acc[r];
+    }
+}
+
+// Both images of this wave's rows of the block: the Gram image read from
+// memory (GF, lanes along columns) or the row image (lanes along rows), the
+// other one derived.
+template <int NB, int CPW, bool GF>
+__device__ __attribute__((always_inline)) inline void cq_load(const QrDesc& d, double (&g)[CPW][NB],
+                                                              double (&x)[CPW / 4][4 * NB], int wave, int lane) {
+  const int m = d.m, n = d.n, row0 = 4 * CPW * wave, lr = lane & 15, lk = lane >> 4;
+  if (GF) {
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = row0 + 4 * c + lk, k = 16 * b + lr;
+        g[c][b] = (i < m && k < n) ? d.A[(int64_t)i * d.sAr + (int64_t)k * d.sAc] : 0.0;
+      }
+    cq_to_rows<NB, CPW>(g, x, lane);
+  } else {
+#pragma unroll
+    for (int t = 0; t < CPW / 4; ++t)
+#pragma unroll
+      for (int s = 0; s < 4 * NB; ++s) {
+        const int i = row0 + 16 * t + lr, k = 4 * s + lk;
+        x[t][s] = (i < m && k < n) ? d.A[(int64_t)i * d.sAr + (int64_t)k * d.sAc] : 0.0;
+      }
+    cq_to_gram<NB, CPW>(x, g, lane);
+  }
+}
+
+// Partial Gram tiles (bi <= bj) of this wave's rows, written to
+// part[((wave*NT + t)*4 + r)*64 + lane].
+template <int NB, int CPW>
+__device__ __attribute__((always_inline)) inline void cq_gram(const double (&g)[CPW][NB], double* part, int wave,
+                                                              int lane) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  int t = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NB; ++bj) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc = mfma64(g[c][bi], g[c][bj], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[((wave * NT + t) * 4 + r) * 64 + lane] = acc[r];
+      ++t;
+    }
+}
+
+// Sum of the eight partial tile sets in wave order, stored as the full
+// symmetric matrix G[i*(NP+1) + j] over the partial area (all threads).
+template <int NB>
+__device__ __attribute__((always_inline)) inline void cq_reduce(double* part, int tid) {
+  constexpr int NT = NB * (NB + 1) / 2, NE = NT * 256, PER = (NE + 511) / 512, LD = 16 * NB + 1;
+  double v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 512 * q;
+    v[q] = 0.0;
+    if (e < NE)
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[q] += part[w * NE + e];
+  }
+  __syncthreads();   // every partial is read before G overwrites them
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 512 * q;
+    if (e < NE) {
+      int t = e >> 8, bi = 0;
+      while (t >= NB - bi) {
+        t -= NB - bi;
+        ++bi;
+      }
+      const int bj = bi + t, l = e & 63, r = (e >> 6) & 3;
+      const int i = 16 * bi + (l >> 4) + 4 * r, j = 16 * bj + (l & 15);
+      part[i * LD + j] = v[q];
+      if (bi != bj) part[j * LD + i] = v[q];
+    }
+  }
+  __syncthreads();
+}
+
+// 1/x: hardware estimate e0 = 1 - x*y0, corrected to third order,
+// y0 (1 + e0 + e0^2), and returned as f*y0 with f supplied by the caller.
+__device__ inline double rcp_scaled(double x, double f) {
+  const double y0 = __builtin_amdgcn_rcp(x);
+  const double e0 = fma(-x, y0, 1.0);
+  const double t = f * y0;
+  return fma(t, fma(e0, e0, e0), t);
+}
+
+// One wave: Cholesky G = R^T R (R upper, positive diagonal) and W = R^-1 by
+// Gauss-Jordan elimination on [G | I].  Lane j < NP holds column j of G,
+// lane NP + j column j of I, so each row operation is one instruction over
+// the wave.  Rows are eliminated unscaled (G = L D L^T with pivots p_k): the
+// multiplier for row i at step k is G[i][k]/p_k, taken as G[k][i]/p_k by the
+// symmetry of the trailing block, i.e. lane i's entry of row k.  The next
+// pivot's row is updated at once (that multiplier by readlane), the other
+// rows one step later with multipliers published through row[0..128) (two
+// buffers).  At
+// the end row k of both halves is scaled by p_k^-1/2 (one inverse square
+// root per lane), which turns D^-1/2 U into R and L^-T D^-1/2 into W.
+// Columns j >= nv are unit columns.  Returns false when a pivot is not above
+// tol times its original diagonal entry (or not finite), or, for devmax > 0,
+// when an entry of G - I exceeds devmax.  Writes R[k*(NP+1) + j] and
+// W[j*(NP+1) + k], zeros below the diagonal; uses row[0..128 + NP).
+template <int NB>
+__device__ __attribute__((always_inline)) inline bool cq_chol(const double* G, double* R, double* W, double* row,
+                                                              int nv, double tol, double devmax, int lane) {
+  constexpr int NP = 16 * NB, LD = NP + 1;
+  const bool gp = lane < NP, act = lane < 2 * NP;
+  const int j = gp ? lane : (act ? lane - NP : 0);
+  const bool real = gp && j < nv;
+  double* piv = row + 128;
+  double g[NP];
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const double gv = G[i * LD + j];   // a valid address on every lane: no branch per load
+    const double unit = (act && i == j) ? 1.0 : 0.0;
+    g[i] = real ? (i < nv ? gv : 0.0) : unit;
+    if (devmax > 0.0 && real && i < nv && !(fabs(gv - unit) <= devmax)) bad = true;
+  }
+  double mp[NP];        // lane i's entry of the previous row, for its deferred updates
+  double sprev = 0.0;   // the previous row divided by its pivot (this lane's entry)
+#pragma unroll
+  for (int i = 0; i < NP; ++i) mp[i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double p = lane_value(g[k], k);
+    const double gk = g[k];
+    const double sk = rcp_scaled(p, gk);   // row k / p_k
+    double* rb = row + 64 * (k & 1);
+    rb[lane] = gk;
+    piv[k] = p;                            // the same value from every lane
+    if (k + 1 < NP) g[k + 1] = fma(-lane_value(gk, k + 1), sk, g[k + 1]);
+#pragma unroll
+    for (int i = k + 1; i < NP; ++i)
+      if (k >= 1) g[i] = fma(-mp[i], sprev, g[i]);   // row k-1, rows after the pivot's
+#pragma unroll
+    for (int i = k + 2; i < NP; ++i) mp[i] = rb[i];
+    __builtin_amdgcn_sched_barrier(1);   // keep these reads here (ALU work may still move across)
+    sprev = sk;
+  }
+  // pivot checks and p_k^-1/2 (lane k), published in row[0..NP)
+  if (gp) {
+    const double p = piv[lane];
+    if (real && !(p > tol * G[j * LD + j] && p <= 1.0e300)) bad = true;
+    row[lane] = rsqrt_nr(p);
+  }
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const bool keep = gp ? k <= j : j <= k;
+      (gp ? R[k * LD + j] : W[j * LD + k]) = keep ? g[k] * row[k] : 0.0;
+    }
+  }
+  return !__any(bad);
+}
+
+// Gram image of X W (W upper triangular, W[k*(NP+1) + c] in shared memory).
+template <int NB, int CPW>
+__device__ __attribute__((always_inline)) inline void cq_right(const double (&x)[CPW / 4][4 * NB], const double* W,
+                                                               double (&g)[CPW][NB], int lane) {
+  constexpr int LD = 16 * NB + 1;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bj = 0; bj < NB; ++bj) {
+    double wf[4 * NB];
+#pragma unroll
+    for (int s = 0; s < 4 * (bj + 1); ++s) wf[s] = W[(4 * s + lk) * LD + 16 * bj + lr];
+#pragma unroll
+    for (int t = 0; t < CPW / 4; ++t) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4 * (bj + 1); ++s) acc = mfma64(x[t][s], wf[s], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g[4 * t + r][bj] = acc[r];
+    }
+  }
+}
+
+// Q = X W stored to d.Q: from the Gram image of the product (BC, lanes
+// along columns of Q) or from its row image (operands swapped, lanes along
+// rows).
+template <int NB, int CPW, bool BC>
+__device__ __attribute__((always_inline)) inline void cq_store_q(const QrDesc& d, const double (&x)[CPW / 4][4 * NB],
+                                                                 const double* W, int wave, int lane) {
+  constexpr int LD = 16 * NB + 1;
+  const int m = d.m, n = d.n, row0 = 4 * CPW * wave, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bj = 0; bj < NB; ++bj) {
+    double wf[4 * NB];
+#pragma unroll
+    for (int s = 0; s < 4 * (bj + 1); ++s) wf[s] = W[(4 * s + lk) * LD + 16 * bj + lr];
+#pragma unroll
+    for (int t = 0; t < CPW / 4; ++t) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4 * (bj + 1); ++s) acc = BC ? mfma64(x[t][s], wf[s], acc) : mfma64(wf[s], x[t][s], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + 16 * t + (BC ? lk + 4 * r : lr), k = 16 * bj + (BC ? lr : lk + 4 * r);
+        if (i < m && k < n) d.Q[(int64_t)i * d.sQr + (int64_t)k * d.sQc] = acc[r];
+      }
+    }
+  }
+}
+
+// R = R2 R1 on MFMA: wave w < NB*NB forms the 16x16 tile (w / NB, w % NB);
+// entries below the diagonal are stored as zeros.
+template <int NB>
+__device__ __attribute__((always_inline)) inline void cq_store_r(const QrDesc& d, const double* R2, const double* R1,
+                                                                 int wave, int lane) {
+  constexpr int LD = 16 * NB + 1;
+  if (wave >= NB * NB) return;
+  const int n = d.n, bi = wave / NB, bj = wave - bi * NB, lr = lane & 15, lk = lane >> 4;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4 * NB; ++s)
+    acc = mfma64(R2[(16 * bi + lr) * LD + 4 * s + lk], R1[(4 * s + lk) * LD + 16 * bj + lr], acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * bi + lk + 4 * r, j = 16 * bj + lr;
+    if (i < n && j < n) d.R[(int64_t)i * d.sRr + (int64_t)j * d.sRc] = i <= j ? acc[r] : 0.0;
+  }
+}
+
+template <int NB, int CPW>
+__host__ __device__ constexpr int cq_area() {
+  return 8 * (NB * (NB + 1) / 2) * 256 > qr_house_lds<CPW / 2, 2 * NB, 8>() ? 8 * (NB * (NB + 1) / 2) * 256
+                                                                            : qr_house_lds<CPW / 2, 2 * NB, 8>();
+}
+
+template <int NB, int CPW, bool GF>
+__device__ __attribute__((always_inline)) inline void cholqr_body(const QrDesc& d, double* sm) {
+  constexpr int NP = 16 * NB, LD = NP + 1, AREA = cq_area<NB, CPW>();
+  static_assert(CPW % 4 == 0, "whole 16-row tiles per wave");
+  static_assert(3 * NP * LD + 128 + NP <= AREA, "G, R, W and the row buffers fit the partial-tile area");
+  double* Gs = sm;                 // partial tiles, then G (pass 1 and 2)
+  double* Rs = sm + NP * LD;
+  double* Ws = sm + 2 * NP * LD;
+  double* rowb = sm + 3 * NP * LD;
+  double* R1s = sm + AREA;         // R1, kept for R = R2 R1
+  double* flag = R1s + NP * LD;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double g[CPW][NB], x[CPW / 4][4 * NB];
+  cq_load<NB, CPW, GF>(d, g, x, wave, lane);
+  // ---- pass 1
+  cq_gram<NB, CPW>(g, sm, wave, lane);
+  __syncthreads();
+  cq_reduce<NB>(sm, tid);
+  if (wave == 0) {
+    const bool ok = cq_chol<NB>(Gs, Rs, Ws, rowb, d.n, 1e-14, 0.0, lane);
+    if (lane == 0) flag[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (flag[0] == 0.0) {
+    qr_house<CPW / 2, 2 * NB, 8>(d, sm);
+    return;
+  }
+  for (int e = tid; e < NP * LD; e += 512) R1s[e] = Rs[e];
+  cq_right<NB, CPW>(x, Ws, g, lane);   // Q1, Gram image
+  cq_to_rows<NB, CPW>(g, x, lane);     // Q1, row image
+  __syncthreads();                     // W1 and R1 are read before the partial tiles reuse the area
+  // ---- pass 2
+  cq_gram<NB, CPW>(g, sm, wave, lane);
+  __syncthreads();
+  cq_reduce<NB>(sm, tid);
+  if (wave == 0) {
+    const bool ok = cq_chol<NB>(Gs, Rs, Ws, rowb, d.n, 0.5, 1e-2, lane);
+    if (lane == 0) flag[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (flag[0] == 0.0) {
+    qr_house<CPW / 2, 2 * NB, 8>(d, sm);
+    return;
+  }
+  cq_store_q<NB, CPW, GF>(d, x, Ws, wave, lane);
+  if (d.R) cq_store_r<NB>(d, Rs, R1s, wave, lane);
+}
+
+template <int NB, int CPW>
+__global__ __launch_bounds__(512) void cholqr_kernel(const QrDesc* __restrict__ ds) {
+  __shared__ double sm[cq_area<NB, CPW>() + (16 * NB) * (16 * NB + 1) + 2];
+  const QrDesc& d = ds[blockIdx.x];
+  const int64_t ar = d.sAr < 0 ? -d.sAr : d.sAr, ac = d.sAc < 0 ? -d.sAc : d.sAc;
+  if (ac <= ar)
+    cholqr_body<NB, CPW, true>(d, sm);
+  else
+    cholqr_body<NB, CPW, false>(d, sm);
+}
+
 // Register-resident variants: (rows per lane, columns per wave, waves).
 // Sixteen waves keep two or fewer columns per wave for n <= 32, which
 // shortens the per-reflection critical path.  A lane holds its block
@@ -1244,7 +1617,19 @@ constexpr QrVariant QR_VARIANTS[] = {{1, 2, 4},  {1, 4, 4},  {1, 1, 16}, {2, 1, 
                                      {8, 2, 16}, {4, 4, 16}, {4, 5, 16}};
 constexpr int QR_NVAR = sizeof(QR_VARIANTS) / sizeof(QR_VARIANTS[0]);
 
+// CholeskyQR2 variants, numbered after the Householder ones: (column blocks
+// of 16, row chunks of 4 per wave).  Used for tall blocks (m >= 4n, m >= 128)
+// of at most 512 rows and 32 columns.
+struct CqVariant {
+  int nb, cpw;
+};
+constexpr CqVariant CQ_VARIANTS[] = {{1, 8}, {1, 16}, {2, 8}, {2, 16}};
+constexpr int CQ_NVAR = sizeof(CQ_VARIANTS) / sizeof(CQ_VARIANTS[0]);
+
 int qr_variant_for(int m, int n) {
+  if (m >= 128 && m >= 4 * n && m <= 512 && n <= 32)
+    for (int v = 0; v < CQ_NVAR; ++v)
+      if (16 * CQ_VARIANTS[v].nb >= n && 32 * CQ_VARIANTS[v].cpw >= m) return QR_NVAR + v;
   int best = -1, cost = 1 << 30;
   for (int v = 0; v < QR_NVAR; ++v) {
     const QrVariant& q = QR_VARIANTS[v];
@@ -1271,6 +1656,10 @@ void launch_qr_reg(int variant, const QrDesc* d, int nd, hipStream_t s) {
     case 9: qr_reg_kernel<8, 2, 16><<<nd, 1024, 0, s>>>(d); break;
     case 10: qr_reg_kernel<4, 4, 16><<<nd, 1024, 0, s>>>(d); break;
     case 11: qr_reg_kernel<4, 5, 16><<<nd, 1024, 0, s>>>(d); break;
+    case QR_NVAR + 0: cholqr_kernel<1, 8><<<nd, 512, 0, s>>>(d); break;
+    case QR_NVAR + 1: cholqr_kernel<1, 16><<<nd, 512, 0, s>>>(d); break;
+    case QR_NVAR + 2: cholqr_kernel<2, 8><<<nd, 512, 0, s>>>(d); break;
+    case QR_NVAR + 3: cholqr_kernel<2, 16><<<nd, 512, 0, s>>>(d); break;
     default: throw Error(ST_INVALID, "bad QR variant");
   }
   PE_HIP(hipGetLastError());

@@ -44,6 +44,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.peps_ctx_graphs(None, 1) == -1
     assert lib.peps_ctx_autotune(None, 1) == -1
     assert lib.peps_ctx_stats(None, None, None, None, None) == -1
+    assert lib.peps_qr(None, None, 0) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
