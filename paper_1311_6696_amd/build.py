@@ -18,7 +18,11 @@ SOURCES = ["kernels.hip", "devapi.cpp", "runtime.cpp", "planner.cpp", "expect.cp
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # no packed-FP32 instructions in any device code
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: with the matrix-register form
+         # the compiler copies loop-carried accumulators into and out of the
+         # matrix registers around every k loop iteration
+         "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _hipcc():

@@ -271,10 +271,11 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
     if (kc + 1 < nchunks) k_offsets(kc + 1);
     __syncthreads();
     if (kc + 1 < nchunks) load(kc + 1);
-    const int kleft = K - (kbeg + kc * KT);   // k steps past the end are zero in LDS: skip them
+    // Every k step of the chunk runs (those past K multiply the zeros staged
+    // for them): a branch between the MFMAs would make the compiler move the
+    // accumulators out of and back into the matrix registers around it.
 #pragma unroll
     for (int ks = 0; ks < KT / P::KS; ++ks) {
-      if (ks * P::KS >= kleft) break;
       typename P::F af[MB], bf[NB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) af[i] = P::template frag<MT + 2>(As, ks, wm * WTM + i * 16, lane);
@@ -761,7 +762,7 @@ void launch_tcs(int prec, int out_dt, int nb, int ksm, const TcDesc* d, int nd, 
 // global memory, K staged in shared memory) and leave Z in shared memory.
 // Phase 2: waves accumulate Y[R; dr, gs] += Z[R; dr, (p, q)] B[(p, q); gs]
 // for their dr values.  The ket intermediate never reaches global memory.
-// Limits of this kernel: dr*p <= 16*NB1, gs <= 16, dr <= 16, lu <= 64.
+// Limits of this kernel: dr*p <= 16*NB1, p <= 2, gs <= 16, dr <= 16, lu <= 64.
 // ===========================================================================
 __device__ inline int64_t kb_off(const KbGroup& g, int v, bool second) {
   int64_t o = 0;
@@ -775,13 +776,13 @@ __device__ inline int64_t kb_off(const KbGroup& g, int v, bool second) {
 
 __host__ __device__ constexpr int kb_np1pad(int nb1) { return 16 * nb1 + 2; }
 
-template <class P, class TC, int NB1>
+template <class P, class TC, int NB1, int KS1>
 __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, int nd, int nblocks, int lup,
                                                  int pqp, int qmax) {
   using T = typename P::T;
   using L = typename P::L;
   static_assert(P::KS == 4, "fragments of four k per lane group");
-  constexpr int NP1 = 16 * NB1, NP1PAD = kb_np1pad(NB1), BPAD = 18, KS1 = 16, DRW = 4;
+  constexpr int NP1 = 16 * NB1, NP1PAD = kb_np1pad(NB1), BPAD = 18, DRW = 4, QPW = KB_QC / 4;
   extern __shared__ __align__(16) unsigned char kb_smem[];
   L* Ks = (L*)kb_smem;                               // [lup][NP1PAD]
   L* Bs = Ks + (size_t)lup * NP1PAD;                 // [pqp][BPAD]
@@ -794,7 +795,33 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (nblocks + gridDim.x - 1) / gridDim.x;
   const int bend = min(nblocks, (blockIdx.x + 1) * per);
-  int cur = -1;
+  // X fragments of one chunk for this wave's q values (ql = wave + 4i), one
+  // 4-wide k step each: the next chunk's are loaded while the current one
+  // is computed (at a block's last chunk, the next block's first chunk when
+  // it belongs to the same descriptor).
+  T xn[QPW][KS1];
+  int64_t olu[KS1];   // offsets of this lane's k values
+  int cur = -1, pf_blk = -1;
+  int64_t pf_oxr = 0;   // row offset in X of the prefetched block
+  auto row_off = [&](const KbDesc& d, int blk, bool second) -> int64_t {
+    const int ridx = (blk - d.tile_base) * 16 + (lane & 15);
+    return ridx < d.r.size ? kb_off(d.r, ridx, second) : -1;
+  };
+  auto load_chunk = [&](const KbDesc& d, int64_t oxr, int q0) {
+    const T* __restrict__ X = (const T*)d.X;
+    const bool rok = oxr >= 0;
+    const int qc = min(KB_QC, d.q.size - q0), LU = d.lu.size;
+#pragma unroll
+    for (int i = 0; i < QPW; ++i) {
+      const int ql = wave + 4 * i;
+      const int64_t oq = oXq[min(q0 + ql, qmax - 1)];
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        xn[i][ks] = (ql < qc && rok && k < LU) ? X[oxr + oq + olu[ks]] : T(0);
+      }
+    }
+  };
   for (int blk = blockIdx.x * per; blk < bend; ++blk) {
     int lo = cur;
     if (cur < 0 || (cur + 1 < nd && ds[cur + 1].tile_base <= blk)) {
@@ -831,14 +858,15 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
         oYgs[tid] = tid < GS ? kb_off(d.gs, tid, true) : 0;
       }
       __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) olu[ks] = oXlu[min(4 * ks + (lane >> 4), lup - 1)];
       cur = lo;
+      pf_blk = -1;
     }
-    const int ridx = (blk - d.tile_base) * 16 + (lane & 15);
-    const bool rok = ridx < d.r.size;
-    const int64_t oxr = rok ? kb_off(d.r, ridx, false) : 0;
-    const int64_t oyr = rok ? kb_off(d.r, ridx, true) : 0;
-    const T* __restrict__ X = (const T*)d.X;
-    const int nks1 = (LU + 3) >> 2;
+    const int64_t oxr = pf_blk == blk ? pf_oxr : row_off(d, blk, false);
+    if (pf_blk != blk) load_chunk(d, oxr, 0);
+    const bool rok = oxr >= 0;
+    const int64_t oyr = rok ? row_off(d, blk, true) : 0;
     typename P::Acc acc2[DRW];
 #pragma unroll
     for (int t = 0; t < DRW; ++t)
@@ -846,15 +874,24 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
       for (int r = 0; r < 4; ++r) acc2[t][r] = 0;
     for (int q0 = 0; q0 < Q; q0 += KB_QC) {
       const int qc = min(KB_QC, Q - q0);
-      // phase 1: ket for this wave's q values of the chunk
-      for (int ql = wave; ql < qc; ql += 4) {
-        const int64_t ox = oxr + oXq[q0 + ql];
-        T af[KS1];
+      T xa[QPW][KS1];
 #pragma unroll
-        for (int ks = 0; ks < KS1; ++ks) {
-          const int k = 4 * ks + (lane >> 4);
-          af[ks] = (ks < nks1 && rok && k < LU) ? X[ox + oXlu[k]] : T(0);
-        }
+      for (int i = 0; i < QPW; ++i)
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) xa[i][ks] = xn[i][ks];
+      if (q0 + KB_QC < Q) {
+        load_chunk(d, oxr, q0 + KB_QC);
+      } else if (blk + 1 < bend && blk + 1 - d.tile_base < (d.r.size + 15) / 16) {
+        pf_oxr = row_off(d, blk + 1, false);
+        load_chunk(d, pf_oxr, 0);
+        pf_blk = blk + 1;
+      }
+      // phase 1: ket for this wave's q slots of the chunk.  Branch-free, so
+      // the accumulators stay in place: slots past the chunk and k steps
+      // past lu multiply zero fragments (K rows clamped to staged ones).
+#pragma unroll
+      for (int i = 0; i < QPW; ++i) {
+        const int ql = wave + 4 * i;
         typename P::Acc acc1[NB1];
 #pragma unroll
         for (int j = 0; j < NB1; ++j)
@@ -862,10 +899,9 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
           for (int r = 0; r < 4; ++r) acc1[j][r] = 0;
 #pragma unroll
         for (int ks = 0; ks < KS1; ++ks) {
-          if (ks >= nks1) break;
-          const L* brow = Ks + (4 * ks + (lane >> 4)) * NP1PAD + (lane & 15);
+          const L* brow = Ks + min(4 * ks + (lane >> 4), lup - 1) * NP1PAD + (lane & 15);
 #pragma unroll
-          for (int j = 0; j < NB1; ++j) acc1[j] = P::mma(brow[16 * j], (typename P::F)af[ks], acc1[j]);
+          for (int j = 0; j < NB1; ++j) acc1[j] = P::mma(brow[16 * j], (typename P::F)xa[i][ks], acc1[j]);
         }
         L* z = Zs + (size_t)ql * NP1 * 16 + (lane & 15);
 #pragma unroll
@@ -874,19 +910,22 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
           for (int r = 0; r < 4; ++r) z[(16 * j + P::row(lane, r)) * 16] = (L)acc1[j][r];
       }
       __syncthreads();
-      // phase 2: bra for this wave's dr values, k = (p, q) with p fastest
-      const int nks2 = (PP * qc + 3) >> 2;
+      // phase 2: bra for this wave's dr values, k = (p, q) with q fastest
+      // over the chunk's KB_QC slots; p < 2, so four k steps.  Slots past
+      // the chunk, p >= PP and dr >= DR contribute zeros.
+      static_assert(KB_QC == 8, "q slot = k & 7");
 #pragma unroll
       for (int t = 0; t < DRW; ++t) {
         const int dr = wave + 4 * t;
-        if (dr >= DR) break;
-        for (int ks = 0; ks < nks2; ++ks) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
           const int k = 4 * ks + (lane >> 4);
-          const int ql = k / PP, pp = k - ql * PP;
-          const bool kok = ql < qc;
-          const L av = kok ? Zs[((size_t)ql * NP1 + dr * PP + pp) * 16 + (lane & 15)] : (L)0;
-          const L bv = kok ? Bs[(pp + PP * (q0 + ql)) * BPAD + (lane & 15)] : (L)0;
-          acc2[t] = P::mma(bv, av, acc2[t]);
+          const int ql = k & 7, pp = k >> 3;
+          const bool kok = ql < qc && pp < PP && dr < DR;
+          const int zrow = kok ? ql * NP1 + dr * PP + pp : 0, brw = kok ? pp + PP * (q0 + ql) : 0;
+          const L av = Zs[(size_t)zrow * 16 + (lane & 15)];
+          const L bv = Bs[brw * BPAD + (lane & 15)];
+          acc2[t] = P::mma(kok ? bv : (L)0, av, acc2[t]);
         }
       }
       __syncthreads();   // Z is rewritten by the next chunk
@@ -896,11 +935,10 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
 #pragma unroll
       for (int t = 0; t < DRW; ++t) {
         const int dr = wave + 4 * t;
-        if (dr >= DR) break;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gs = P::row(lane, r);
-          if (gs < GS) Y[oyr + oYdr[dr] + oYgs[gs]] = (TC)acc2[t][r];
+          if (dr < DR && gs < GS) Y[oyr + oYdr[dr] + oYgs[gs]] = (TC)acc2[t][r];
         }
       }
     }
@@ -913,16 +951,24 @@ int kb_lds_bytes(int prec, int nb1, int lup, int pqp, int qmax) {
   return (int)((tiles + 15) / 16 * 16 + (size_t)(lup + qmax + 32) * sizeof(int64_t));
 }
 
+template <class P, class TC, int NB1, int KS1>
+static void launch_kb_k(const KbDesc* d, int nd, int nblocks, int lup, int pqp, int qmax, int lds, hipStream_t s) {
+  const int g = resident_grid(kb_kernel<P, TC, NB1, KS1>, lds, nblocks);
+  kb_kernel<P, TC, NB1, KS1><<<g, 256, lds, s>>>(d, nd, nblocks, lup, pqp, qmax);
+}
+
 template <class P, class TC>
 static void launch_kb_p(int nb1, const KbDesc* d, int nd, int nblocks, int lup, int pqp, int qmax, hipStream_t s) {
   const int prec = std::is_same<typename P::T, double>::value ? TP_F64 : TP_F32;
   const int lds = kb_lds_bytes(prec, nb1, lup, pqp, qmax);
+  if (lup > 64) throw Error(ST_INVALID, "fused contraction: lu above 64");
+  const bool short_k = lup <= 16;   // the ket's k index (lu) in at most four 4-wide steps
   if (nb1 == 1) {
-    const int g = resident_grid(kb_kernel<P, TC, 1>, lds, nblocks);
-    kb_kernel<P, TC, 1><<<g, 256, lds, s>>>(d, nd, nblocks, lup, pqp, qmax);
+    if (short_k) launch_kb_k<P, TC, 1, 4>(d, nd, nblocks, lup, pqp, qmax, lds, s);
+    else launch_kb_k<P, TC, 1, 16>(d, nd, nblocks, lup, pqp, qmax, lds, s);
   } else if (nb1 == 2) {
-    const int g = resident_grid(kb_kernel<P, TC, 2>, lds, nblocks);
-    kb_kernel<P, TC, 2><<<g, 256, lds, s>>>(d, nd, nblocks, lup, pqp, qmax);
+    if (short_k) launch_kb_k<P, TC, 2, 4>(d, nd, nblocks, lup, pqp, qmax, lds, s);
+    else launch_kb_k<P, TC, 2, 16>(d, nd, nblocks, lup, pqp, qmax, lds, s);
   } else {
     throw Error(ST_INVALID, "bad fused width");
   }
