@@ -115,11 +115,15 @@ struct PolBF16 {
 };
 
 // Shared-memory staging of one workgroup of tc_kernel.
+// k offsets are kept for a window of TC_KWIN consecutive k values (one
+// index decomposition per thread), refreshed every TC_KWIN / KT chunks.
+constexpr int TC_KWIN = 256;
+
 template <class L, int MT, int NT, int KT>
 struct TcSmem {
   L As[KT][MT + 2];
   L Bs[KT][NT + 2];
-  int64_t oAm[MT], oCm[MT], oBn[NT], oCn[NT], oAk[KT], oBk[KT];
+  int64_t oAm[MT], oCm[MT], oBn[NT], oCn[NT], oAk[TC_KWIN], oBk[TC_KWIN];
 };
 
 // One output tile (or one K-slice of it) of descriptor d; `wg` numbers the
@@ -158,54 +162,54 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
   TC* __restrict__ C = (TC*)d.C;
   const int a_kfast = d.a_kfast, b_kfast = d.b_kfast;
 
-  for (int i = tid; i < MT; i += 256) {
-    int m = m0 + i;
-    int64_t oa = 0, oc = 0;
-    if (m < M) {
-      for (int j = d.nm - 1; j >= 0; --j) {
-        const int dj = d.dm[j];
-        const int x = m % dj;
-        m /= dj;
-        oa += (int64_t)x * d.sAm[j];
-        oc += (int64_t)x * d.sCm[j];
-      }
-    }
-    oAm[i] = oa;
-    oCm[i] = oc;
-  }
-  for (int i = tid; i < NT; i += 256) {
-    int n = n0 + i;
-    int64_t ob = 0, oc = 0;
-    if (n < N) {
-      for (int j = d.nn - 1; j >= 0; --j) {
-        const int dj = d.dn[j];
-        const int x = n % dj;
-        n /= dj;
-        ob += (int64_t)x * d.sBn[j];
-        oc += (int64_t)x * d.sCn[j];
-      }
-    }
-    oBn[i] = ob;
-    oCn[i] = oc;
-  }
-  auto k_offsets = [&](int kc) {
-    if (tid < KT) {
-      int k = kbeg + kc * KT + tid;
-      int64_t oa = 0, ob = 0;
-      if (k < K) {
-        for (int j = d.nk - 1; j >= 0; --j) {
-          const int dj = d.dk[j];
-          const int x = k % dj;
-          k /= dj;
-          oa += (int64_t)x * d.sAk[j];
-          ob += (int64_t)x * d.sBk[j];
+  static_assert(TC_KWIN % KT == 0 && TC_KWIN <= 256, "whole chunks per k window, one entry per thread");
+  // m and n offsets: one decomposition per row or column, spread over the
+  // workgroup (m rows on the first MT threads, n columns after them)
+  for (int i = tid; i < MT + NT; i += 256) {
+    int64_t o1 = 0, o2 = 0;
+    if (i < MT) {
+      int m = m0 + i;
+      if (m < M)
+        for (int j = d.nm - 1; j >= 0; --j) {
+          const int dj = d.dm[j];
+          const int x = m % dj;
+          m /= dj;
+          o1 += (int64_t)x * d.sAm[j];
+          o2 += (int64_t)x * d.sCm[j];
         }
-      }
-      oAk[tid] = oa;
-      oBk[tid] = ob;
+      oAm[i] = o1;
+      oCm[i] = o2;
+    } else {
+      int n = n0 + i - MT;
+      if (n < N)
+        for (int j = d.nn - 1; j >= 0; --j) {
+          const int dj = d.dn[j];
+          const int x = n % dj;
+          n /= dj;
+          o1 += (int64_t)x * d.sBn[j];
+          o2 += (int64_t)x * d.sCn[j];
+        }
+      oBn[i - MT] = o1;
+      oCn[i - MT] = o2;
     }
+  }
+  // k offsets of the window starting at chunk c0
+  constexpr int CPW = TC_KWIN / KT;
+  auto k_window = [&](int c0) {
+    int k = kbeg + c0 * KT + tid;
+    int64_t oa = 0, ob = 0;
+    if (k < K)
+      for (int j = d.nk - 1; j >= 0; --j) {
+        const int dj = d.dk[j];
+        const int x = k % dj;
+        k /= dj;
+        oa += (int64_t)x * d.sAk[j];
+        ob += (int64_t)x * d.sBk[j];
+      }
+    oAk[tid] = oa;
+    oBk[tid] = ob;
   };
-  k_offsets(0);
+  k_window(0);
   __syncthreads();
 
   T ra[EA], rb[EB];
@@ -222,20 +226,20 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
     else { nn = idx % NT; kk = idx / NT; }
   };
   auto load = [&](int kc) {
-    const int k0 = kbeg + kc * KT;
+    const int k0 = kbeg + kc * KT, w0 = (kc % CPW) * KT;   // chunk kc's place in its k window
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int mm, kk;
       a_at(e, mm, kk);
       const bool ok = (m0 + mm < M) && (k0 + kk < K);
-      ra[e] = ok ? A[oAm[mm] + oAk[kk]] : T(0);
+      ra[e] = ok ? A[oAm[mm] + oAk[w0 + kk]] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       int nn, kk;
       b_at(e, nn, kk);
       const bool ok = (n0 + nn < N) && (k0 + kk < K);
-      rb[e] = ok ? B[oBn[nn] + oBk[kk]] : T(0);
+      rb[e] = ok ? B[oBn[nn] + oBk[w0 + kk]] : T(0);
     }
   };
   auto store = [&]() {
@@ -268,7 +272,7 @@ __device__ inline void tc_tile(const TcDesc& d, int wg, TcSmem<typename P::L, MT
   for (int kc = 0; kc < nchunks; ++kc) {
     __syncthreads();
     store();
-    if (kc + 1 < nchunks) k_offsets(kc + 1);
+    if (kc + 1 < nchunks && (kc + 1) % CPW == 0) k_window(kc + 1);   // the last chunk's offsets are read
     __syncthreads();
     if (kc + 1 < nchunks) load(kc + 1);
     // Every k step of the chunk runs (those past K multiply the zeros staged
@@ -390,6 +394,39 @@ void launch_tc(int prec, int out_dt, int tile, const TcDesc* d, int nd, int nt, 
 // ===========================================================================
 __host__ __device__ constexpr int tcs_bpad(int nb) { return 16 * nb + 2; }
 
+// Offsets of every k < kp (in A and in B) and every n < np (in B and in C)
+// of a descriptor: one mixed-radix decomposition per entry, the k and n
+// entries spread over the workgroup's threads.  Entries past K or N are 0.
+__device__ inline void tc_index_tables(const TcDesc& d, int kp, int np, int64_t* oAk, int64_t* oBk, int64_t* oBn,
+                                       int64_t* oCn, int tid) {
+  for (int i = tid; i < kp + np; i += 256) {
+    int64_t o1 = 0, o2 = 0;
+    if (i < kp) {
+      int k = i;
+      if (k < d.K)
+        for (int j = d.nk - 1; j >= 0; --j) {
+          const int x = k % d.dk[j];
+          k /= d.dk[j];
+          o1 += (int64_t)x * d.sAk[j];
+          o2 += (int64_t)x * d.sBk[j];
+        }
+      oAk[i] = o1;
+      oBk[i] = o2;
+    } else {
+      int n = i - kp;
+      if (n < d.N)
+        for (int j = d.nn - 1; j >= 0; --j) {
+          const int x = n % d.dn[j];
+          n /= d.dn[j];
+          o1 += (int64_t)x * d.sBn[j];
+          o2 += (int64_t)x * d.sCn[j];
+        }
+      oBn[i - kp] = o1;
+      oCn[i - kp] = o2;
+    }
+  }
+}
+
 template <class P, class TC, int NB, int KSM>
 __global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds, int nd, int ngroups, int kp) {
   using T = typename P::T;
@@ -399,7 +436,9 @@ __global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds,
   extern __shared__ __align__(16) unsigned char tcs_smem[];
   L* Bs = (L*)tcs_smem;                                                      // [kp][NPAD]
   int64_t* oAk = (int64_t*)(tcs_smem + ((size_t)kp * NPAD * sizeof(L) + 15) / 16 * 16);   // [kp]
-  int64_t* oCn = oAk + kp;                                                   // [NP]
+  int64_t* oBk = oAk + kp;                                                   // [kp]
+  int64_t* oCn = oBk + kp;                                                   // [NP]
+  int64_t* oBn = oCn + NP;                                                   // [NP]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // contiguous blocks of groups per workgroup: a workgroup crosses few
   // descriptor boundaries, so B is staged rarely
@@ -420,46 +459,12 @@ __global__ __launch_bounds__(256) void tcs_kernel(const TcDesc* __restrict__ ds,
     const int M = d.M, N = d.N, K = d.K;
     if (lo != cur) {
       __syncthreads();   // the previous descriptor's tables are no longer read
+      tc_index_tables(d, kp, NP, oAk, oBk, oBn, oCn, tid);
+      __syncthreads();
       const T* __restrict__ B = (const T*)d.B;
       for (int i = tid; i < kp * NP; i += 256) {
         const int k = i / NP, n = i - k * NP;
-        T v = T(0);
-        if (k < K && n < N) {
-          int kk = k, nn = n;
-          int64_t o = 0;
-          for (int j = d.nk - 1; j >= 0; --j) {
-            o += (int64_t)(kk % d.dk[j]) * d.sBk[j];
-            kk /= d.dk[j];
-          }
-          for (int j = d.nn - 1; j >= 0; --j) {
-            o += (int64_t)(nn % d.dn[j]) * d.sBn[j];
-            nn /= d.dn[j];
-          }
-          v = B[o];
-        }
-        Bs[k * NPAD + n] = (L)v;
-      }
-      for (int k = tid; k < kp; k += 256) {
-        int64_t o = 0;
-        if (k < K) {
-          int kk = k;
-          for (int j = d.nk - 1; j >= 0; --j) {
-            o += (int64_t)(kk % d.dk[j]) * d.sAk[j];
-            kk /= d.dk[j];
-          }
-        }
-        oAk[k] = o;
-      }
-      for (int n = tid; n < NP; n += 256) {
-        int64_t o = 0;
-        if (n < N) {
-          int nn = n;
-          for (int j = d.nn - 1; j >= 0; --j) {
-            o += (int64_t)(nn % d.dn[j]) * d.sCn[j];
-            nn /= d.dn[j];
-          }
-        }
-        oCn[n] = o;
+        Bs[k * NPAD + n] = (L)((k < K && n < N) ? B[oBk[k] + oBn[n]] : T(0));
       }
       __syncthreads();
       cur = lo;
@@ -531,7 +536,9 @@ __global__ __launch_bounds__(256) void tcs_bf16_kernel(const TcDesc* __restrict_
   extern __shared__ __align__(16) unsigned char tcs_smem[];
   __bf16* Bs = (__bf16*)tcs_smem;                                                       // [NP][kpad]
   int64_t* oAk = (int64_t*)(tcs_smem + ((size_t)NP * kpad * sizeof(__bf16) + 15) / 16 * 16);   // [kp]
-  int64_t* oCn = oAk + kp;                                                              // [NP]
+  int64_t* oBk = oAk + kp;                                                              // [kp]
+  int64_t* oCn = oBk + kp;                                                              // [NP]
+  int64_t* oBn = oCn + NP;                                                              // [NP]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (ngroups + gridDim.x - 1) / gridDim.x;
   const int gend = min(ngroups, (blockIdx.x + 1) * per);
@@ -550,46 +557,12 @@ __global__ __launch_bounds__(256) void tcs_bf16_kernel(const TcDesc* __restrict_
     const int M = d.M, N = d.N, K = d.K;
     if (lo != cur) {
       __syncthreads();
+      tc_index_tables(d, kp, NP, oAk, oBk, oBn, oCn, tid);
+      __syncthreads();
       const float* __restrict__ B = (const float*)d.B;
       for (int i = tid; i < kp * NP; i += 256) {
-        const int n = i / kp, k = i - n * kp;
-        float v = 0.f;
-        if (k < K && n < N) {
-          int kk = k, nn = n;
-          int64_t o = 0;
-          for (int j = d.nk - 1; j >= 0; --j) {
-            o += (int64_t)(kk % d.dk[j]) * d.sBk[j];
-            kk /= d.dk[j];
-          }
-          for (int j = d.nn - 1; j >= 0; --j) {
-            o += (int64_t)(nn % d.dn[j]) * d.sBn[j];
-            nn /= d.dn[j];
-          }
-          v = B[o];
-        }
-        Bs[n * kpad + k] = (__bf16)v;
-      }
-      for (int k = tid; k < kp; k += 256) {
-        int64_t o = 0;
-        if (k < K) {
-          int kk = k;
-          for (int j = d.nk - 1; j >= 0; --j) {
-            o += (int64_t)(kk % d.dk[j]) * d.sAk[j];
-            kk /= d.dk[j];
-          }
-        }
-        oAk[k] = o;
-      }
-      for (int n = tid; n < NP; n += 256) {
-        int64_t o = 0;
-        if (n < N) {
-          int nn = n;
-          for (int j = d.nn - 1; j >= 0; --j) {
-            o += (int64_t)(nn % d.dn[j]) * d.sCn[j];
-            nn /= d.dn[j];
-          }
-        }
-        oCn[n] = o;
+        const int k = i / NP, n = i - k * NP;
+        Bs[n * kpad + k] = (__bf16)((k < K && n < N) ? B[oBk[k] + oBn[n]] : 0.f);
       }
       __syncthreads();
       cur = lo;
@@ -656,10 +629,10 @@ __global__ __launch_bounds__(256) void tcs_bf16_kernel(const TcDesc* __restrict_
 }
 
 int tcs_lds_bytes(int prec, int nb, int kp) {
-  if (prec == TP_BF16)
-    return (int)(((size_t)16 * nb * (kp + 8) * 2 + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
+  const size_t tables = (size_t)2 * (kp + 16 * nb) * sizeof(int64_t);   // oAk, oBk, oCn, oBn
+  if (prec == TP_BF16) return (int)(((size_t)16 * nb * (kp + 8) * 2 + 15) / 16 * 16 + tables);
   const size_t el = prec == TP_F64 ? sizeof(double) : sizeof(float);
-  return (int)(((size_t)kp * tcs_bpad(nb) * el + 15) / 16 * 16 + (size_t)(kp + 16 * nb) * sizeof(int64_t));
+  return (int)(((size_t)kp * tcs_bpad(nb) * el + 15) / 16 * 16 + tables);
 }
 
 // One resident wave of workgroups (occupancy x compute units), so the
