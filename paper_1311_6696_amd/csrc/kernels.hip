@@ -773,7 +773,8 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
   // is computed (at a block's last chunk, the next block's first chunk when
   // it belongs to the same descriptor).
   T xn[QPW][KS1];
-  int64_t olu[KS1];   // offsets of this lane's k values
+  int64_t olu[KS1];   // offsets of this lane's k values in X
+  int krow[KS1];      // this lane's K row (times the row pitch) per k step
   int cur = -1, pf_blk = -1;
   int64_t pf_oxr = 0;   // row offset in X of the prefetched block
   auto row_off = [&](const KbDesc& d, int blk, bool second) -> int64_t {
@@ -832,7 +833,11 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
       }
       __syncthreads();
 #pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) olu[ks] = oXlu[min(4 * ks + (lane >> 4), lup - 1)];
+      for (int ks = 0; ks < KS1; ++ks) {
+        const int kr = min(4 * ks + (lane >> 4), lup - 1);   // K rows clamped to the staged ones
+        olu[ks] = oXlu[kr];
+        krow[ks] = kr * NP1PAD + (lane & 15);
+      }
       cur = lo;
       pf_blk = -1;
     }
@@ -872,11 +877,11 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
           for (int r = 0; r < 4; ++r) acc1[j][r] = 0;
 #pragma unroll
         for (int ks = 0; ks < KS1; ++ks) {
-          const L* brow = Ks + min(4 * ks + (lane >> 4), lup - 1) * NP1PAD + (lane & 15);
+          const L* brow = Ks + krow[ks];
 #pragma unroll
           for (int j = 0; j < NB1; ++j) acc1[j] = P::mma(brow[16 * j], (typename P::F)xa[i][ks], acc1[j]);
         }
-        L* z = Zs + (size_t)ql * NP1 * 16 + (lane & 15);
+        L* z = Zs + ql * NP1 * 16 + (lane & 15);
 #pragma unroll
         for (int j = 0; j < NB1; ++j)
 #pragma unroll
@@ -884,22 +889,28 @@ __global__ __launch_bounds__(256) void kb_kernel(const KbDesc* __restrict__ ds, 
       }
       __syncthreads();
       // phase 2: bra for this wave's dr values, k = (p, q) with q fastest
-      // over the chunk's KB_QC slots; p < 2, so four k steps.  Slots past
-      // the chunk, p >= PP and dr >= DR contribute zeros.
+      // over the chunk's KB_QC slots; p < 2, so four k steps.  The B
+      // fragment and the Z row of each k step do not depend on dr: read
+      // once per chunk.  Slots past the chunk, p >= PP and dr >= DR
+      // contribute zeros.
       static_assert(KB_QC == 8, "q slot = k & 7");
+      L bvk[4];
+      int zb[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        const int ql = k & 7, pp = k >> 3;
+        const bool kok = ql < qc && pp < PP;
+        zb[ks] = (kok ? ql * NP1 + pp : 0) * 16 + (lane & 15);
+        bvk[ks] = kok ? Bs[(pp + PP * (q0 + ql)) * BPAD + (lane & 15)] : (L)0;
+      }
 #pragma unroll
       for (int t = 0; t < DRW; ++t) {
         const int dr = wave + 4 * t;
+        const bool dok = dr < DR;
+        const int doff = (dok ? dr : 0) * PP * 16;
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = 4 * ks + (lane >> 4);
-          const int ql = k & 7, pp = k >> 3;
-          const bool kok = ql < qc && pp < PP && dr < DR;
-          const int zrow = kok ? ql * NP1 + dr * PP + pp : 0, brw = kok ? pp + PP * (q0 + ql) : 0;
-          const L av = Zs[(size_t)zrow * 16 + (lane & 15)];
-          const L bv = Bs[brw * BPAD + (lane & 15)];
-          acc2[t] = P::mma(kok ? bv : (L)0, av, acc2[t]);
-        }
+        for (int ks = 0; ks < 4; ++ks) acc2[t] = P::mma(dok ? bvk[ks] : (L)0, Zs[zb[ks] + doff], acc2[t]);
       }
       __syncthreads();   // Z is rewritten by the next chunk
     }
