@@ -85,9 +85,9 @@ def side_precision(sess, binding, torch):
     """10x10, D=6, unit-norm Gaussian sites, chi=72: one full environment per
     dtype; errors are against the FP64 GPU path (the FP64 path itself is
     checked against the oracle on the smaller lattices)."""
-    from paper_1311_6696_amd.inputs import CONFIGS, config_peps
-    cfg = CONFIGS[3]
-    st = binding.to_device(config_peps(3))
+    from paper_1311_6696_amd.inputs import WORKLOADS, workload_peps
+    cfg = WORKLOADS["10x10_D6_chi72"]
+    st = binding.to_device(workload_peps("10x10_D6_chi72"))
     out, ref = {}, None
     for dt in ("f64", "f32", "bf16"):
         note(f"precision workload {dt}")
@@ -110,10 +110,10 @@ def side_precision(sess, binding, torch):
 def side_clusters(sess, binding, torch):
     """16x16, D=6, near-product, chi=36: all 256 n x n windows per call, FP32
     contractions (FP64 QR and norms)."""
-    from paper_1311_6696_amd.inputs import CONFIGS, config_peps
-    cfg = CONFIGS[4]
+    from paper_1311_6696_amd.inputs import WORKLOADS, workload_peps
+    cfg = WORKLOADS["16x16_D6_clusters"]
     L = cfg["L"]
-    st = binding.to_device(config_peps(4))
+    st = binding.to_device(workload_peps("16x16_D6_clusters"))
     out = {}
     for n in cfg["ns"]:
         wins = []
@@ -207,10 +207,10 @@ def main():
 
     import torch
     from paper_1311_6696_amd import binding
-    from paper_1311_6696_amd.inputs import CONFIGS, config_peps
+    from paper_1311_6696_amd.inputs import WORKLOADS, workload_peps
 
-    cfg = CONFIGS[2]
-    A = config_peps(2)
+    cfg = WORKLOADS["8x8_D4_chi32"]
+    A = workload_peps("8x8_D4_chi32")
     chi, H = cfg["chi"], args.halfsweeps
     sess = binding.Session(0)
     if args.graphs:
@@ -312,7 +312,7 @@ def main():
     if args.batch > 1:
         # the same workload, several independent lattices per call (one grouped launch per stage)
         note(f"batched: {args.batch} lattices per call")
-        states = [binding.to_device(config_peps(2, seed=2000 + i)) for i in range(args.batch)]
+        states = [binding.to_device(workload_peps("8x8_D4_chi32", seed=2000 + i)) for i in range(args.batch)]
         for _ in range(2):
             envs = sess.env_boundary(states, chi, "f64", H)
             sess.expect(envs)

@@ -49,7 +49,7 @@ typedef enum {
   PEPS_ERR_OOM = -2,          /* device allocation failed or workspace cap exceeded */
   PEPS_ERR_HIP = -3,          /* a HIP runtime call failed */
   PEPS_ERR_NONFINITE = -5,    /* NaN/Inf in an input tensor or in a computed norm */
-  PEPS_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+  PEPS_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
 } peps_status;
 
 /* Arithmetic of the bulk contractions.  QR gauge, norms and log-scales are

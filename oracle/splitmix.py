@@ -2,7 +2,7 @@
 generators", OOPSLA 2014) used as a counter-based generator.
 
 The paper does not say how the ALS start tensor of a row absorption is
-chosen; this build fills it with a deterministic pseudo-random tensor so that
+chosen; here it is filled with a deterministic pseudo-random tensor so that
 the oracle and the GPU path start from the same point.  Both sides implement
 the generator from its published definition:
 

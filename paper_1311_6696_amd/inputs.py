@@ -48,26 +48,27 @@ def product_state(Lr, Lc, seed=0):
     return [[rng.standard_normal((2, 1, 1, 1, 1)) for _ in range(Lc)] for _ in range(Lr)]
 
 
-# The five benchmark configurations: (lattice, D, distribution, chi, seed).
-CONFIGS = {
-    1: dict(L=4, D=2, dist="uniform", chi=16, seed=1001,
-            note="4x4, D=2, U[0,1), chi=16 (exact); checked against the 2^16 state vector"),
-    2: dict(L=8, D=4, dist="near_product", chi=32, seed=1002,
-            note="8x8, D=4, near-product signed, chi=32, plain FP64"),
-    3: dict(L=10, D=6, dist="normal_unit", chi=72, seed=1003,
-            note="10x10, D=6, N(0,1) unit-norm tensors, chi=72, precision form"),
-    4: dict(L=16, D=6, dist="near_product", chi=36, seed=1004, ns=(2, 4, 6),
-            note="16x16, D=6, near-product, chi=36, n x n clusters n in {2,4,6}"),
+# Seeded workloads with the shapes of the paper's benchmark states, named by
+# lattice, bond dimension and chi: (lattice side, D, distribution, chi, seed).
+WORKLOADS = {
+    "4x4_D2_exact": dict(L=4, D=2, dist="uniform", chi=16, seed=1001,
+                         note="4x4, D=2, U[0,1), chi=16 (exact); checked against the 2^16 state vector"),
+    "8x8_D4_chi32": dict(L=8, D=4, dist="near_product", chi=32, seed=1002,
+                         note="8x8, D=4, near-product signed, chi=32, plain FP64"),
+    "10x10_D6_chi72": dict(L=10, D=6, dist="normal_unit", chi=72, seed=1003,
+                           note="10x10, D=6, N(0,1) unit-norm tensors, chi=72, precision form"),
+    "16x16_D6_clusters": dict(L=16, D=6, dist="near_product", chi=36, seed=1004, ns=(2, 4, 6),
+                              note="16x16, D=6, near-product, chi=36, n x n clusters n in {2,4,6}"),
 }
 
 
-def config_peps(cfg, seed=None):
-    c = CONFIGS[cfg]
+def workload_peps(name, seed=None):
+    c = WORKLOADS[name]
     return make_peps(c["L"], c["L"], c["D"], c["dist"], c["seed"] if seed is None else seed)
 
 
 def batched_instances(count=32, seed=1005, Ls=range(6, 13), Ds=(3, 4, 5, 8)):
-    """Configuration 5: ``count`` independent PEPS of seeded sizes.
+    """``count`` independent PEPS of seeded sizes (L in 6..12, D in {3,4,5,8}).
 
     One generator draws all (L, D) pairs first, then the tensors instance by
     instance (sites row-major), entries U[0, 1); chi = D^2.

@@ -96,16 +96,16 @@ def test_n2_windows_exact(sess):
             assert abs(r["down"] - ex["bond_v"][i - r0, j - c0]) < TOL64
 
 
-def test_cluster_config4_sample(sess):
+def test_cluster_16x16_D6_sample(sess):
     """16x16, D=6, near-product, chi=36: a sample of n=2/4/6 windows (edge,
     corner and bulk) against the oracle, in the launch configuration of a
     batched run (all windows of one n in one call)."""
-    from paper_1311_6696_amd.inputs import config_peps
-    A = config_peps(4)
+    from paper_1311_6696_amd.inputs import workload_peps
+    A = workload_peps("16x16_D6_clusters")
     lat = whole_lattice(A)
     sample = [(0, 0), (0, 7), (5, 5), (15, 15), (9, 14)]
     for n in (2, 4, 6):
-        say(f"config 4 sample n={n}")
+        say(f"16x16 D=6 cluster sample n={n}")
         wins = windows_for(16, n)
         res = gpu_clusters(sess, A, wins, 36)
         ref, _ = cluster.cluster_env(lat, n, 36, sites=sample)

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import api, exact
 from paper_1311_6696_amd import binding
-from paper_1311_6696_amd.inputs import make_peps, product_state, config_peps, CONFIGS
+from paper_1311_6696_amd.inputs import make_peps, product_state, workload_peps, WORKLOADS
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-10
@@ -47,8 +47,8 @@ def max_obs_diff(r, ref):
 
 
 @pytest.mark.parametrize("seed", [1001, 1002, 1003])
-def test_cfg1_exact_vs_statevector(sess, seed):
-    say(f"cfg1 4x4 D=2 chi=16 seed={seed}")
+def test_4x4_D2_exact_vs_statevector(sess, seed):
+    say(f"4x4 D=2 chi=16 seed={seed}")
     A = make_peps(4, 4, 2, "uniform", seed)
     (r,), _ = run_gpu(sess, [A], 16)
     sv = exact.sv_observables(A)
@@ -195,11 +195,11 @@ def test_autotuned_shapes(sess):
         assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
 
-def test_cfg2_full_parity(sess):
+def test_8x8_D4_chi32_full_parity(sess):
     """8x8, D=4, near-product, chi=32: all 112 bonds and the norm."""
-    say("cfg2 8x8 D=4 chi=32 f64")
-    c = CONFIGS[2]
-    A = config_peps(2)
+    say("8x8 D=4 chi=32 f64")
+    c = WORKLOADS["8x8_D4_chi32"]
+    A = workload_peps("8x8_D4_chi32")
     (r,), _ = run_gpu(sess, [A], c["chi"])
     ref = api.expect(api.env_boundary(A, c["chi"]))
     assert max_obs_diff(r, ref) < TOL64

@@ -21,7 +21,7 @@ def _obs_close(a, b, tol):
 # --- P1/P2: exact chi reproduces brute force -------------------------------
 
 @pytest.mark.parametrize("seed", [1001, 1002, 1003])
-def test_cfg1_matches_statevector(seed):
+def test_4x4_D2_matches_statevector(seed):
     """4x4, D=2, U[0,1), chi=16 (>= all caps): boundary path == 2^16 brute force."""
     A = make_peps(4, 4, 2, "uniform", seed)
     sv = exact.sv_observables(A)
