@@ -7,6 +7,11 @@ and cluster windows.  Test infrastructure only (see the package docstring).
   on every site from its row sandwich, horizontal bond energies from the row
   sandwich and vertical ones from the two-row sandwich (readings, see
   ``sandwich``).
+* ``env_columns`` - boundaries from the left and from the right: the top and
+  bottom boundaries of the transposed lattice (the same sandwich contraction
+  run along the other lattice direction, Sec. 2).  Passed to ``expect``, they
+  give the vertical bond energies from single-column sandwiches instead of
+  two-row sandwiches.
 * ``cluster_env`` - per-site n x n windows closed by CU_0 separable
   boundaries (``cluster``), Sec. 5.3.
 """
@@ -14,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .boundary import flip_vertical, top_boundaries, whole_lattice, Lattice
+from .boundary import flip_vertical, top_boundaries, transpose_lattice, whole_lattice, Lattice
 from .sandwich import row_observables, two_row_observables
 
 DEFAULT_SEED = 0x13116696
@@ -45,8 +50,26 @@ def env_boundary(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED
     return Env(lat, top, bottom, chi)
 
 
-def expect(env, rows=None):
-    """Observables of an environment; ``rows`` limits the single-row sandwiches."""
+def env_columns(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED):
+    """Left and right boundaries of a lattice, as an ``Env`` of its transpose:
+    its T(c) holds columns 0..c absorbed from the left, its B(c) columns
+    c..Lc-1 absorbed from the right.  ALS start streams use side 2 (from the
+    left) and side 3 (from the right), so that they differ from the streams
+    of the row boundaries."""
+    lat = lat_or_A if isinstance(lat_or_A, Lattice) else whole_lattice(lat_or_A)
+    tl = transpose_lattice(lat)
+    top = top_boundaries(tl, chi, halfsweeps, seed, side=2)
+    bottom = top_boundaries(flip_vertical(tl), chi, halfsweeps, seed, side=3)
+    return Env(tl, top, bottom, chi)
+
+
+def expect(env, rows=None, columns=None):
+    """Observables of an environment; ``rows`` limits the single-row sandwiches.
+
+    With ``columns`` (from ``env_columns`` of the same lattice), the vertical
+    bond (r, c)-(r+1, c) is the horizontal bond (c, r)-(c, r+1) of the
+    transposed lattice, taken from its single-row sandwich of row c; the
+    two-row sandwiches are then not formed."""
     lat = env.lat
     Lr, Lc = lat.rows, lat.cols
     sz = np.full((Lr, Lc), np.nan)
@@ -62,6 +85,15 @@ def expect(env, rows=None):
         if r == rc:
             log_norm = sT + sB + sLR + np.log(abs(Z))
             sign = 1.0 if Z >= 0 else -1.0
+    if columns is not None:
+        tl = columns.lat
+        assert tl.rows == Lc and tl.cols == Lr, "column environment of another lattice"
+        for c in range(Lc):
+            T, _, _ = columns.T(c - 1)
+            B, _, _ = columns.B(c + 1)
+            _, h, _, _, _ = row_observables(T, tl.A[c], B, tl.lam[c], tl.rho[c])
+            bv[:, c] = h
+        return dict(log_norm=log_norm, sign=sign, sz=sz, bond_h=bh, bond_v=bv)
     for r in (range(Lr - 1) if rows is None else [x for x in rows if x < Lr - 1]):
         T, _, _ = env.T(r - 1)
         B, _, _ = env.B(r + 2)

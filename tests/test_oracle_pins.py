@@ -272,6 +272,70 @@ def test_bond_caps():
     assert boundary.bond_caps(100, [16, 16], [2, 1, 2]) == [4, 4]
 
 
+# --- vertical bonds from column boundaries (the sandwich along columns) -------
+
+def _anisotropic_peps(Lr, Lc, Dh, Dv, seed):
+    """Horizontal bonds of dimension Dh, vertical ones Dv (N(0,1) entries), so
+    that a swapped leg pair cannot pass unnoticed."""
+    rng = np.random.default_rng(seed)
+    return [[rng.standard_normal((2, 1 if c == 0 else Dh, 1 if r == 0 else Dv,
+                                  1 if c == Lc - 1 else Dh, 1 if r == Lr - 1 else Dv))
+             for c in range(Lc)] for r in range(Lr)]
+
+
+@pytest.mark.parametrize("case", [("uniform", 4, 4, 2), ("normal_unit", 3, 4, 2), ("normal_unit", 4, 3, 2),
+                                  ("aniso", 3, 3, 0), ("aniso", 2, 4, 0), ("normal_unit", 1, 4, 2),
+                                  ("normal_unit", 4, 1, 2)])
+def test_column_vertical_bonds_match_statevector(case):
+    """Exact chi: the column path's vertical bonds equal brute force, on
+    rectangular, anisotropic and single-row/column lattices."""
+    dist, Lr, Lc, D = case
+    A = (_anisotropic_peps(Lr, Lc, 2, 3, 70 + Lr * Lc) if dist == "aniso"
+         else make_peps(Lr, Lc, D, dist, 71 + Lr * Lc))
+    sv = exact.sv_observables(A)
+    chi = 4096
+    res = api.expect(api.env_boundary(A, chi), columns=api.env_columns(A, chi))
+    _obs_close(res, sv, 1e-11)
+    assert abs(res["log_norm"] - np.log(sv["norm"])) < 1e-11
+
+
+def test_column_boundaries_are_transposed_row_boundaries():
+    """The left boundaries are the top boundaries of the transposed lattice:
+    at lossless chi the ALS starts differ (other streams), so the MPS agree up
+    to a gauge; their dense contractions times the log-scales agree."""
+    A = make_peps(3, 4, 2, "normal_unit", 73)
+    cols = api.env_columns(A, 4096)
+    rows_t = api.env_boundary(transpose_lattice(whole_lattice(A)), 4096)
+
+    def dense(T):
+        x = T[0]
+        for t in T[1:]:
+            x = np.tensordot(x, t, axes=([-1], [0]))
+        return x
+
+    for c in range(-1, 3):
+        (x, sx, _), (y, sy, _) = cols.T(c), rows_t.T(c)
+        np.testing.assert_allclose(dense(x) * np.exp(sx), dense(y) * np.exp(sy), atol=1e-12)
+        (x, sx, _), (y, sy, _) = cols.B(c + 2), rows_t.B(c + 2)
+        np.testing.assert_allclose(dense(x) * np.exp(sx), dense(y) * np.exp(sy), atol=1e-12)
+
+
+def test_column_and_two_row_paths_converge_together():
+    """Truncated chi: the two routes to a vertical bond are different
+    approximations; both approach the exact-chi value, and each other."""
+    A = make_peps(5, 5, 2, "normal_unit", 75)
+    ref = api.expect(api.env_boundary(A, 1024))["bond_v"]
+    gaps, errs = [], []
+    for chi in (2, 8):
+        e = api.env_boundary(A, chi, halfsweeps=8)
+        two = api.expect(e)["bond_v"]
+        col = api.expect(e, columns=api.env_columns(A, chi, halfsweeps=8))["bond_v"]
+        gaps.append(np.abs(two - col).max())
+        errs.append(np.abs(col - ref).max())
+    assert gaps[1] < gaps[0] and errs[1] < errs[0]
+    assert errs[1] < 1e-3
+
+
 # --- P12/P13 ------------------------------------------------------------------
 
 def test_bounds_at_exact_chi():
