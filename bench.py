@@ -48,12 +48,13 @@ def measured_traffic(kernel):
     if fields.get("kernels.hip sha256") != digest or "traffic bytes per launch" not in fields:
         return None
     return float(fields["traffic bytes per launch"])
-def run_steps(sess, dev_state, chi, dtype, halfsweeps, n, split=None):
-    """n full environments; `split` (a list) receives (boundary_s, expect_s) per step."""
+def run_steps(sess, dev_state, chi, dtype, halfsweeps, n, split=None, columns=False):
+    """n full environments; `split` (a list) receives (boundary_s, expect_s) per step.
+    columns: vertical bonds from the left/right boundaries instead of two-row sandwiches."""
     res = None
     for _ in range(n):
         t0 = time.perf_counter()
-        envs = sess.env_boundary([dev_state], chi, dtype, halfsweeps)
+        envs = sess.env_boundary([dev_state], chi, dtype, halfsweeps, columns=columns)
         t1 = time.perf_counter()
         res = sess.expect(envs)[0]
         t2 = time.perf_counter()
@@ -187,6 +188,8 @@ def main():
     ap.add_argument("--halfsweeps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32/BF16 measurements")
+    ap.add_argument("--no-columns", action="store_true",
+                    help="skip the measurement of vertical bonds from column boundaries")
     ap.add_argument("--batch", type=int, default=8,
                     help="lattices per call of the batched side measurement (1 = skip)")
     ap.add_argument("--workloads", default="",
@@ -328,6 +331,25 @@ def main():
         tb = time.perf_counter() - t0
         out["batched"] = {"lattices_per_call": args.batch, "value": nb * args.batch / tb, "unit": "env/s",
                           "ms_per_call": 1000.0 * tb / nb}
+
+    if not args.no_columns:
+        # the same workload with the vertical bonds from single-column sandwiches of
+        # the left/right boundaries (built in the same batched run as the row ones)
+        note("vertical bonds from column boundaries")
+        run_steps(sess, dev_state, chi, "f64", H, 2, columns=True)
+        torch.cuda.synchronize()
+        n = max(3, args.steps // 2)
+        csplit = []
+        t0 = time.perf_counter()
+        rc = run_steps(sess, dev_state, chi, "f64", H, n, csplit, columns=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["columns"] = {"value": n / t, "unit": "env/s", "ms_per_step": 1000.0 * t / n,
+                          "speedup_vs_two_row": (n / t) / (args.steps / dt), "gflop_per_env": rc["flops"] / 1e9,
+                          "boundary_ms": 1000.0 * float(np.median([s[0] for s in csplit])),
+                          "expect_ms": 1000.0 * float(np.median([s[1] for s in csplit])),
+                          "max_bond_v_gap_vs_two_row": float(np.max(np.abs(rc["bond_v"] - res["bond_v"]))),
+                          "max_bond_h_diff": float(np.max(np.abs(rc["bond_h"] - res["bond_h"])))}
 
     if not args.no_forms:
         forms = {}

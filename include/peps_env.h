@@ -75,7 +75,7 @@ typedef struct {
   int32_t chi;          /* boundary bond dimension D' >= 1 */
   int32_t dtype;        /* peps_dtype */
   int32_t halfsweeps;   /* ALS half-sweeps per truncated row, >= 1 (default 4 if 0) */
-  int32_t flags;        /* 0, or PEPS_OPTS_PER_STATE (peps_env_boundary only) */
+  int32_t flags;        /* 0, or PEPS_OPTS_PER_STATE | PEPS_OPTS_COLUMNS (peps_env_boundary only) */
   uint64_t seed;        /* SplitMix64 key of the ALS start tensors */
 } peps_env_opts;
 
@@ -83,6 +83,17 @@ typedef struct {
  * record per state (every record carries the flag); chi, dtype, halfsweeps
  * and seed may then differ between the lattices of one batched run. */
 #define PEPS_OPTS_PER_STATE 1
+
+/* opts.flags (peps_env_boundary only): also contract the lattice from the
+ * left and from the right, i.e. the top and bottom boundaries of the
+ * transposed lattice (Sec. 2: the same sandwich contraction along the
+ * other lattice direction), in the same batched run as the row boundaries.
+ * peps_expect then takes each vertical bond (r,c)-(r+1,c) from the
+ * single-column sandwich of column c instead of the two-row sandwich of
+ * rows r and r+1: a different approximation at truncated chi, the same
+ * values at lossless chi.  The transposed sites are strided views of the
+ * packed sites, not copies.  Rejected by peps_cluster_env. */
+#define PEPS_OPTS_COLUMNS 2
 
 /* Cluster window around the centre site (ci, cj) of state `state`,
  * rows r0..r1 and columns c0..c1 inclusive, centre inside the window. */
@@ -95,7 +106,8 @@ typedef struct {
 /* Results of peps_expect for one environment.
  * Whole lattice: sz has rows*cols entries (row-major); bond has
  * rows*(cols-1) horizontal bonds (r,c)-(r,c+1) in row-major order followed
- * by (rows-1)*cols vertical bonds (r,c)-(r+1,c) in row-major order.
+ * by (rows-1)*cols vertical bonds (r,c)-(r+1,c) in row-major order (from
+ * the two-row sandwiches, or the column sandwiches with PEPS_OPTS_COLUMNS).
  * Window: sz has 1 entry (centre), bond has 2 (right, down; NaN if the
  * neighbour lies outside the window).
  * log_norm = log|<psi|psi>| from row floor(rows/2); norm_sign its sign.
@@ -154,7 +166,8 @@ typedef struct {
 } peps_qr_block;
 peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
 
-/* Diagnostics of an environment: number of truncated rows, and the squared
+/* Diagnostics of an environment's row boundaries (the column boundaries of
+ * PEPS_OPTS_COLUMNS are not included): number of truncated rows, and the squared
  * norm of the ALS centre tensor after each half-sweep of each truncated row
  * (host buffer of at least n_rows*halfsweeps doubles; may be NULL). */
 peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas);

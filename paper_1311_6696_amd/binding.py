@@ -16,6 +16,7 @@ PEPS_F64, PEPS_F32, PEPS_BF16 = 0, 1, 2
 DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
 STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
 OPTS_PER_STATE = 1   # peps_env_opts.flags: one options record per state
+OPTS_COLUMNS = 2     # peps_env_opts.flags: also the left/right boundaries (vertical bonds from column sandwiches)
 DEFAULT_SEED = 0x13116696
 TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16", "128x48", "64x80",
          "skinny16", "skinny32", "skinny48", "skinny64", "skinny80", "ketbra16", "ketbra32")
@@ -183,21 +184,26 @@ class Context:
         return Opts(int(chi), DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(halfsweeps), 0,
                     int(seed) & ((1 << 64) - 1))
 
-    def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
-        """chi: one value for all states, or a sequence with one per state
-        (passed as per-state options records)."""
+    def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
+        """chi, halfsweeps, seed: one value for all states, or a sequence with
+        one per state (passed as per-state options records).  columns: also
+        the left and right boundaries (OPTS_COLUMNS)."""
         n = len(states)
         arr = (State * n)(*[s.struct() for s in states])
         out = (C.c_void_p * n)()
-        if np.ndim(chi) == 0:
+        flags = OPTS_COLUMNS if columns else 0
+        per = [np.ndim(x) != 0 for x in (chi, halfsweeps, seed)]
+        if not any(per):
             o = self.opts(chi, dtype, halfsweeps, seed)
+            o.flags = flags
             _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, C.byref(o), out))
         else:
-            if len(chi) != n:
-                raise ValueError("one chi per state")
-            recs = [self.opts(c, dtype, halfsweeps, seed) for c in chi]
+            vals = [list(x) if p else [x] * n for x, p in zip((chi, halfsweeps, seed), per)]
+            if any(len(v) != n for v in vals):
+                raise ValueError("one chi, halfsweeps or seed per state")
+            recs = [self.opts(c, dtype, h, s) for c, h, s in zip(*vals)]
             for r in recs:
-                r.flags = OPTS_PER_STATE
+                r.flags = OPTS_PER_STATE | flags
             o = (Opts * n)(*recs)
             _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, o, out))
         return [Env(self, out[i], s.rows, s.cols) for i, s in enumerate(states)]
@@ -301,9 +307,9 @@ class Session:
         self.stream = torch.cuda.current_stream(dev)
         self.ctx = Context(dev, self.stream.cuda_stream)
 
-    def env_boundary(self, tensors_list, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+    def env_boundary(self, tensors_list, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
         states = [state_of(t) for t in tensors_list]
-        return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed)
+        return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed, columns)
 
     def cluster_env(self, tensors_list, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
         states = [state_of(t) for t in tensors_list]

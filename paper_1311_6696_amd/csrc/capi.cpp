@@ -72,6 +72,7 @@ Opts make_opts(const peps_env_opts* o, int32_t allowed_flags = 0) {
   r.dtype = o->dtype;
   r.halfsweeps = o->halfsweeps == 0 ? 4 : o->halfsweeps;
   r.seed = o->seed;
+  r.columns = (o->flags & PEPS_OPTS_COLUMNS) != 0;
   return r;
 }
 
@@ -102,6 +103,38 @@ void pack_state(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vecto
     out.push_back(std::move(st));
   }
   rec.ew(ew);
+}
+
+// The transposed lattice of `e` (rows <-> columns, left/right legs <-> up/down
+// legs) as an environment whose sites are views of e's packed buffers: its
+// top and bottom boundaries are e's left and right ones.
+std::unique_ptr<peps_env> transposed_env(const peps_env& e) {
+  auto t = std::make_unique<peps_env>(e.ctxref);
+  t->opts = e.opts;
+  t->opts.columns = false;
+  t->side0 = 2;
+  const Lattice& L = e.lat;
+  Lattice& T = t->lat;
+  T.Lr = L.Lc;
+  T.Lc = L.Lr;
+  for (int c = 0; c < L.Lc; ++c)
+    for (int r = 0; r < L.Lr; ++r) {
+      const Site& s = L.at(r, c);
+      PE_REQUIRE(!s.tr, "a transposed lattice is not transposed again");
+      auto v = std::make_unique<Site>(s);
+      v->Dl = s.Du;
+      v->Du = s.Dl;
+      v->Dr = s.Dd;
+      v->Dd = s.Dr;
+      v->tr = true;
+      T.s.push_back(v.get());
+      t->sites.push_back(std::move(v));
+    }
+  T.lam = L.tau;
+  T.rho = L.beta;
+  T.tau = L.lam;
+  T.beta = L.rho;
+  return t;
 }
 
 void* make_one(Rec& rec, Arena& arena, int cdt) {
@@ -166,7 +199,7 @@ peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_sta
     for (int i = 0; i < n_states; ++i) {
       const peps_env_opts* oi = per_state ? opts + i : opts;
       PE_REQUIRE(!per_state || (oi->flags & PEPS_OPTS_PER_STATE), "every per-state options record carries the flag");
-      os.push_back(make_opts(oi, PEPS_OPTS_PER_STATE));
+      os.push_back(make_opts(oi, PEPS_OPTS_PER_STATE | PEPS_OPTS_COLUMNS));
     }
     for (int i = 0; i < n_states; ++i) validate_state(st[i], i);
     dev::set_device(ctx->c->device);
@@ -187,9 +220,13 @@ peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_sta
       L.rho.assign(L.Lr, one);
       L.tau.assign(L.Lc, one);
       L.beta.assign(L.Lc, one);
+      if (o.columns) e->col = transposed_env(*e);
     }
     rec.run(tmp);
-    plan_boundaries(*ctx->c, made);
+    std::vector<peps_env*> all(made);
+    for (peps_env* e : made)
+      if (e->col) all.push_back(e->col.get());
+    plan_boundaries(*ctx->c, all);   // row and column boundaries in one batched run
     for (int i = 0; i < n_states; ++i) out[i] = made[i];
   });
   if (s != PEPS_OK)
@@ -209,8 +246,11 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
       es.push_back(env[i]);
     }
     dev::set_device(ctx->c->device);
-    std::vector<double> f0;
-    for (peps_env* e : es) f0.push_back(e->flops);
+    std::vector<double> f0, f1;
+    for (peps_env* e : es) {
+      f0.push_back(e->flops);
+      f1.push_back(e->col ? e->col->flops : 0.0);
+    }
     std::vector<ExpectOut> res;
     plan_expect(*ctx->c, es, res);
     for (int i = 0; i < n_env; ++i) {
@@ -221,8 +261,9 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
       out[i].norm_sign = r.sign;
       std::memcpy(out[i].sz, r.sz.data(), sizeof(double) * r.sz.size());
       std::memcpy(out[i].bond, r.bond.data(), sizeof(double) * r.bond.size());
-      out[i].flops = es[i]->flops;
+      out[i].flops = es[i]->flops + (es[i]->col ? es[i]->col->flops : 0.0);
       es[i]->flops = f0[i];   // boundary flops stay; this call's sandwich flops are reported once
+      if (es[i]->col) es[i]->col->flops = f1[i];
     }
   });
 }

@@ -21,9 +21,17 @@ inline int64_t prod(const std::vector<int64_t>& v) {
   return n;
 }
 
-// Site view with labels "plurd"-like; flip swaps the up and down legs.
+// Site view with labels "plurd"-like; flip swaps the up and down legs.  A
+// transposed site is a strided view of the stored (p, u, l, d, r) order.
 inline TV site_tv(const Site& s, int op, bool flip, int dt, const std::string& lbl) {
-  TV v = dense(s.op[op], dt, lbl, {s.d, s.Dl, s.Du, s.Dr, s.Dd});
+  TV v = s.tr ? dense(s.op[op], dt, lbl, {s.d, s.Du, s.Dl, s.Dd, s.Dr})
+              : dense(s.op[op], dt, lbl, {s.d, s.Dl, s.Du, s.Dr, s.Dd});
+  if (s.tr) {
+    std::swap(v.dim[1], v.dim[2]);
+    std::swap(v.str[1], v.str[2]);
+    std::swap(v.dim[3], v.dim[4]);
+    std::swap(v.str[3], v.str[4]);
+  }
   if (flip) {
     std::swap(v.dim[2], v.dim[4]);
     std::swap(v.str[2], v.str[4]);

@@ -32,6 +32,8 @@ std::vector<std::pair<size_t, size_t>> budget_groups(const std::vector<size_t>& 
 // One-row sandwich of row r (between T_{r-1} and B_{r+1}).
 struct RJob {
   peps_env* e;
+  peps_env* owner;   // receives the results: e itself, or the lattice e is the transpose of
+  bool tr;           // row r of a transposed lattice: only its bonds (vertical bonds of column r)
   int r, Lc;
   const Mps* T;
   const Mps* B;
@@ -168,7 +170,16 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
   const size_t budget = ctx.scratch_budget;
 
   // ------------------------------------------------------------ jobs ----
+  // An environment with column boundaries adds the single-row sandwiches of
+  // its transposed lattice and forms no two-row sandwiches.
+  std::vector<std::pair<peps_env*, peps_env*>> srcs;   // (environment, owner)
   for (peps_env* e : envs) {
+    srcs.push_back({e, e});
+    if (e->col) srcs.push_back({e->col.get(), e});
+  }
+  for (const auto& src : srcs) {
+    peps_env* e = src.first;
+    const bool tr = src.first != src.second;
     const Lattice& L = e->lat;
     const int Lr = L.Lr, Lc = L.Lc;
     std::vector<int> rows;
@@ -180,6 +191,8 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
     for (int r : rows) {
       RJob j;
       j.e = e;
+      j.owner = src.second;
+      j.tr = tr;
       j.r = r;
       j.Lc = Lc;
       j.T = &e->T(r - 1);
@@ -208,7 +221,9 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       rj.push_back(std::move(j));
     }
     std::vector<int> prs;
-    if (e->window) {
+    if (tr || e->col) {
+      // vertical bonds come from the transposed lattice
+    } else if (e->window) {
       if (e->ci + 1 < Lr) prs.push_back(e->ci);
     } else {
       for (int r = 0; r + 1 < Lr; ++r) prs.push_back(r);
@@ -372,7 +387,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
           for (int c = 0; c < j.Lc; ++c) {
             if (level == 0) {
               for (int op = OP_SZ; op <= OP_SM; ++op) {
-                if (op != OP_SZ && c + 1 >= j.Lc) continue;
+                if ((op != OP_SZ || j.tr) && c + 1 >= j.Lc) continue;
                 if (j.e->window && c != j.e->cj) continue;
                 X1[i][c][op] = call.alloc(esz * env_elems(j, c + 1));
                 items.push_back({0, i, c, op});
@@ -518,12 +533,12 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
   for (size_t i = 0; i < rj.size(); ++i) {
     const RJob& j = rj[i];
     peps_env* e = j.e;
-    ExpectOut& eo = out[pos[e]];
+    ExpectOut& eo = out[pos[j.owner]];
     const int Lc = j.Lc, Lr = e->lat.Lr;
     const std::vector<double>& D = hdots[i];
     const std::vector<double>& nu = hnuL[i];
     for (int c = 0; c < Lc; ++c) {
-      if (!X1[i][c][OP_SZ]) continue;
+      if (j.tr || !X1[i][c][OP_SZ]) continue;
       const double v = D[Lc + 1 + c] / (std::sqrt(nu[c + 1]) * D[c + 1]);
       if (e->window) {
         if (c == e->cj && j.r == e->ci) eo.sz[0] = v;
@@ -536,13 +551,16 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       double num = 0.0;
       for (int t = 0; t < 3; ++t) num += BOND_W[t] * D[2 * Lc + 1 + 3 * c + t];
       const double v = num / (std::sqrt(nu[c + 1] * nu[c + 2]) * D[c + 2]);
-      if (e->window) {
+      if (j.tr) {
+        // bond (j.r, c)-(j.r, c+1) of the transpose is the vertical bond (c, j.r)-(c+1, j.r)
+        eo.bond[(size_t)Lc * (Lr - 1) + (size_t)c * Lr + j.r] = v;
+      } else if (e->window) {
         if (c == e->cj && j.r == e->ci) eo.bond[0] = v;
       } else {
         eo.bond[(size_t)j.r * (Lc - 1) + c] = v;
       }
     }
-    if (j.r == Lr / 2) {
+    if (!j.tr && j.r == Lr / 2) {
       const int cc = Lc / 2;
       double lg = e->Tlog(j.r - 1) + e->Blog(j.r + 1) + std::log(std::fabs(D[cc]));
       for (int k = 1; k <= cc; ++k) lg += 0.5 * std::log(nu[k]);

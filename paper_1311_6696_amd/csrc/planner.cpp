@@ -210,8 +210,8 @@ void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       for (int c = 0; c < j->Lc; ++c) {
         EwDesc e = ew_desc(EW_SPLITMIX, nullptr, DT_F64, j->X[c], DT_F64,
                            j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]);
-        const uint64_t q = (uint64_t(j->side) << 40) | (uint64_t(j->k) << 20) | uint64_t(c);
-        e.key = splitmix_stream_state(o.seed, q);
+        const uint64_t q = (uint64_t(j->env->side0 + j->side) << 40) | (uint64_t(j->k) << 20) | uint64_t(c);
+        e.key = splitmix_stream_state(j->env->opts.seed, q);
         f.push_back(e);
       }
     rec.ew(f);
@@ -450,13 +450,19 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
         ex.push_back(&j);
       }
     }
-    // all jobs of one level share their options' precision; split by precision
-    for (int pass = 0; pass < 3; ++pass) {
+    // one grouped chain per (precision, half-sweep count); seeds are per job
+    std::vector<std::pair<int, int>> groups;
+    for (AJob& j : jobs) {
+      const std::pair<int, int> g{j.env->opts.dtype, j.env->opts.halfsweeps};
+      if (std::find(groups.begin(), groups.end(), g) == groups.end()) groups.push_back(g);
+    }
+    std::sort(groups.begin(), groups.end());
+    for (const auto& g : groups) {
       std::vector<AJob*> a, b;
       for (AJob* j : ex)
-        if (j->env->opts.dtype == pass) a.push_back(j);
+        if (j->env->opts.dtype == g.first && j->env->opts.halfsweeps == g.second) a.push_back(j);
       for (AJob* j : als)
-        if (j->env->opts.dtype == pass) b.push_back(j);
+        if (j->env->opts.dtype == g.first && j->env->opts.halfsweeps == g.second) b.push_back(j);
       if (a.empty() && b.empty()) continue;
       const Opts& o = (a.empty() ? b[0] : a[0])->env->opts;
       plan_exact(rec, scr, a, o);

@@ -178,6 +178,10 @@ struct Ctx {
 struct Site {
   void* op[4] = {nullptr, nullptr, nullptr, nullptr};
   int d = 2, Dl = 1, Du = 1, Dr = 1, Dd = 1;
+  // A site of the transposed lattice (left/right legs exchanged with up/down
+  // ones) that shares the buffers of the original site: they hold the legs
+  // in the order (p, u, l, d, r) of this view.
+  bool tr = false;
 };
 
 struct Lattice {
@@ -201,6 +205,7 @@ struct Mps {
 struct Opts {
   int chi = 1, dtype = 0, halfsweeps = 4;
   uint64_t seed = 0;
+  bool columns = false;   // also the left and right boundaries
   int prec() const { return dtype; }
   int cdt() const { return dtype == 0 ? DT_F64 : DT_F32; }
 };
@@ -231,6 +236,11 @@ struct peps_env {
   bool window = false;
   int ci = 0, cj = 0;                     // centre (window coordinates)
   double flops = 0.0;
+  // Left and right boundaries, as the top and bottom boundaries of the
+  // transposed lattice (its sites are views of this lattice's buffers);
+  // peps_expect then takes the vertical bonds from its single-row sandwiches.
+  std::unique_ptr<peps_env> col;
+  int side0 = 0;   // ALS start-stream side of the top boundaries (bottom: side0 + 1)
   pe::Mps& T(int r) { return top[r + 1]; }
   pe::Mps& B(int r) { return bot[lat.Lr - r]; }
   double Tlog(int r) const { return top_log[r + 1]; }

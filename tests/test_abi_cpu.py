@@ -67,3 +67,10 @@ def test_statistics_table_size_matches_header():
     n = int(re.search(r"#define PEPS_N_STATS (\d+)", text).group(1))
     assert binding.N_STATS == n
     assert len(binding.TILES) * 6 == n
+
+
+def test_option_flags_match_header():
+    text = open(os.path.join(ROOT, "include", "peps_env.h")).read()
+    assert binding.OPTS_PER_STATE == int(re.search(r"#define PEPS_OPTS_PER_STATE (\d+)", text).group(1))
+    assert binding.OPTS_COLUMNS == int(re.search(r"#define PEPS_OPTS_COLUMNS (\d+)", text).group(1))
+    assert binding.OPTS_PER_STATE & binding.OPTS_COLUMNS == 0

@@ -120,6 +120,91 @@ def test_batched_per_state_chi(sess):
         assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
 
+def test_batched_per_state_seed_and_halfsweeps(sess):
+    """Per-state records with different chi, half-sweep counts and seeds in
+    one precision: each state keeps its own ALS start and sweep count."""
+    say("batched per-state chi/halfsweeps/seed")
+    As = [make_peps(4, 4, 2, "normal_unit", 21), make_peps(5, 4, 2, "uniform", 22),
+          make_peps(4, 5, 3, "normal_unit", 23)]
+    chis, Hs, seeds = [4, 3, 6], [3, 5, 4], [11, 12, 13]
+    envs = sess.env_boundary([binding.to_device(A) for A in As], chis, "f64", Hs, seeds)
+    res = sess.expect(envs)
+    for e in envs:
+        e.free()
+    for A, r, chi, H, seed in zip(As, res, chis, Hs, seeds):
+        ref = api.expect(api.env_boundary(A, chi, H, seed))
+        assert max_obs_diff(r, ref) < TOL64
+
+
+# --- vertical bonds from the left/right boundaries (column sandwiches) -------
+
+def _aniso_peps(Lr, Lc, Dh, Dv, seed):
+    rng = np.random.default_rng(seed)
+    return [[rng.standard_normal((2, 1 if c == 0 else Dh, 1 if r == 0 else Dv,
+                                  1 if c == Lc - 1 else Dh, 1 if r == Lr - 1 else Dv))
+             for c in range(Lc)] for r in range(Lr)]
+
+
+def run_cols(sess, A_list, chi, dtype="f64", H=4):
+    envs = sess.env_boundary([binding.to_device(A) for A in A_list], chi, dtype, H, columns=True)
+    res = sess.expect(envs)
+    for e in envs:
+        e.free()
+    return res
+
+
+@pytest.mark.parametrize("case", [
+    ("normal_unit", 3, 4, 2, 4096, 4),   # lossless chi
+    ("normal_unit", 3, 4, 2, 4, 4),
+    ("normal_unit", 4, 3, 3, 5, 3),
+    ("aniso", 3, 4, 0, 6, 4),            # horizontal bonds 2, vertical bonds 3
+    ("near_product", 5, 5, 2, 4, 4),
+    ("uniform", 1, 5, 2, 4, 2),
+    ("uniform", 5, 1, 2, 4, 2),
+])
+def test_columns_parity(sess, case):
+    dist, Lr, Lc, D, chi, H = case
+    say(f"columns {case}")
+    A = (_aniso_peps(Lr, Lc, 2, 3, 90 + Lr * Lc) if dist == "aniso"
+         else make_peps(Lr, Lc, D, dist, 200 + Lr * 10 + Lc))
+    (r,) = run_cols(sess, [A], chi, H=H)
+    ref = api.expect(api.env_boundary(A, chi, H), columns=api.env_columns(A, chi, H))
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+    if chi == 4096:
+        assert max_obs_diff(r, exact.sv_observables(A)) < TOL64
+
+
+def test_columns_mixed_with_row_only_envs(sess):
+    """Environments with and without column boundaries in one expect call."""
+    say("columns mixed with two-row environments")
+    A1, A2 = make_peps(4, 5, 2, "normal_unit", 301), make_peps(5, 4, 2, "uniform", 302)
+    e1 = sess.env_boundary([binding.to_device(A1)], 4, "f64", 3, columns=True)
+    e2 = sess.env_boundary([binding.to_device(A2)], 4, "f64", 3)
+    r1, r2 = sess.expect(e1 + e2)
+    for e in e1 + e2:
+        e.free()
+    assert max_obs_diff(r1, api.expect(api.env_boundary(A1, 4, 3), columns=api.env_columns(A1, 4, 3))) < TOL64
+    assert max_obs_diff(r2, api.expect(api.env_boundary(A2, 4, 3))) < TOL64
+
+
+def test_columns_rejected_for_clusters(sess):
+    """The column flag belongs to whole-lattice environments only."""
+    import ctypes as C
+    say("columns flag on a cluster call")
+    dev = binding.to_device(make_peps(3, 3, 2, "uniform", 5))
+    st = binding.state_of(dev)
+    ctx = sess.ctx
+    o = ctx.opts(4)
+    o.flags = binding.OPTS_COLUMNS
+    arr = (binding.State * 1)(st.struct())
+    w = (binding.Window * 1)(binding.Window(0, 0, 2, 0, 2, 1, 1))
+    out = (C.c_void_p * 1)()
+    code = ctx.lib.peps_cluster_env(ctx.handle, arr, 1, w, 1, C.byref(o), out)
+    assert code != 0 and out[0] is None
+    assert b"flags" in ctx.lib.peps_last_error()
+
+
 @pytest.mark.parametrize("L,D,chi,dist,seed", [
     (4, 3, 72, "normal_unit", 61),   # 81 x 72 QR blocks: five columns per wave
     (4, 5, 30, "uniform", 52),       # 625 x 30 and 625 x 25 blocks: tree QR over row blocks
@@ -202,6 +287,18 @@ def test_8x8_D4_chi32_full_parity(sess):
     A = workload_peps("8x8_D4_chi32")
     (r,), _ = run_gpu(sess, [A], c["chi"])
     ref = api.expect(api.env_boundary(A, c["chi"]))
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
+def test_8x8_D4_chi32_columns_full_parity(sess):
+    """8x8, D=4, near-product, chi=32 with column boundaries: all 112 bonds
+    (vertical ones from the column sandwiches) and the norm."""
+    say("8x8 D=4 chi=32 f64 columns")
+    c = WORKLOADS["8x8_D4_chi32"]
+    A = workload_peps("8x8_D4_chi32")
+    (r,) = run_cols(sess, [A], c["chi"])
+    ref = api.expect(api.env_boundary(A, c["chi"]), columns=api.env_columns(A, c["chi"]))
     assert max_obs_diff(r, ref) < TOL64
     assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
