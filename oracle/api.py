@@ -12,6 +12,9 @@ and cluster windows.  Test infrastructure only (see the package docstring).
   run along the other lattice direction, Sec. 2).  Passed to ``expect``, they
   give the vertical bond energies from single-column sandwiches instead of
   two-row sandwiches.
+* ``site_env`` - norm environment N_l of one site (Sec. 3, the matrix of
+  the ALS tensor update) from its row sandwich, scaled to A N A = +-1, with
+  the log of the scale.
 * ``cluster_env`` - per-site n x n windows closed by CU_0 separable
   boundaries (``cluster``), Sec. 5.3.
 """
@@ -20,7 +23,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .boundary import flip_vertical, top_boundaries, transpose_lattice, whole_lattice, Lattice
-from .sandwich import row_observables, two_row_observables
+from .sandwich import row_observables, site_environment, two_row_observables
 
 DEFAULT_SEED = 0x13116696
 DEFAULT_HALFSWEEPS = 4
@@ -100,6 +103,17 @@ def expect(env, rows=None, columns=None):
         bv[r] = two_row_observables(T, lat.A[r], lat.A[r + 1], B, lat.lam[r], lat.rho[r],
                                     lat.lam[r + 1], lat.rho[r + 1])
     return dict(log_norm=log_norm, sign=sign, sz=sz, bond_h=bh, bond_v=bv)
+
+
+def site_env(env, r, c):
+    """(N, log_z, sign) of site (r, c): N scaled so that sum_p A N A = sign,
+    log_z the log of |<psi|psi>| as this row's sandwich estimates it (so the
+    unscaled environment is sign * exp(log_z) * N)."""
+    lat = env.lat
+    T, sT, _ = env.T(r - 1)
+    B, sB, _ = env.B(r + 1)
+    N, lz, sgn = site_environment(T, lat.A[r], B, lat.lam[r], lat.rho[r], c)
+    return N, lz + sT + sB, sgn
 
 
 def energy(res):

@@ -118,6 +118,29 @@ def row_observables(T, Arow, B, lam, rho):
     return sz, hb, Z, sL[c] + sR[c], (Lenv, Renv, sL, sR)
 
 
+def site_environment(T, Arow, B, lam, rho, c):
+    """Norm environment of site c of one row: the network of <psi|psi> with
+    the ket and bra tensors of that site taken out, the matrix N_l of the
+    ALS tensor update N_l A_l = b_l (Sec. 3).
+
+    N[l,u,r,d,m,v,s,g] = sum L[o,l,m,a] T[a,u,v,e] R[o',r,s,e] B[o,d,g,o']
+    with the normalised environments L = Lenv[c], R = Renv[c+1] of the row,
+    returned as a (Dl Du Dr Dd) x (Dl Du Dr Dd) matrix (ket legs as rows)
+    divided by |w|, w = sum_p A[p,k] N[k,k'] A[p,k'] of this row's own
+    site, with log|w| + sL[c] + sR[c+1] and the sign of w.
+    """
+    Lenv, Renv, sL, sR = row_environments(T, Arow, B, lam, rho)
+    Y = np.einsum("olma,auve->olmuve", Lenv[c], T[c], **EIN)
+    Y = np.einsum("olmuve,odgy->lmuvedgy", Y, B[c], **EIN)
+    N = np.einsum("lmuvedgy,yrse->lurdmvsg", Y, Renv[c + 1], **EIN)
+    _, Dl, Du, Dr, Dd = Arow[c].shape
+    K = Dl * Du * Dr * Dd
+    N = N.reshape(K, K)
+    A = Arow[c].reshape(-1, K)
+    w = float(np.einsum("pk,kj,pj->", A, N, A))
+    return N / abs(w), np.log(abs(w)) + sL[c] + sR[c + 1], (1.0 if w >= 0 else -1.0)
+
+
 def two_row_observables(T, Arow1, Arow2, B, lam1, rho1, lam2, rho2):
     """Vertical bond energies between two adjacent rows, per column."""
     Lc = len(Arow1)

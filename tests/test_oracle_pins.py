@@ -336,6 +336,60 @@ def test_column_and_two_row_paths_converge_together():
     assert errs[1] < 1e-3
 
 
+# --- norm environments of single sites (the ALS update matrix N_l) ---------------
+
+def _open_site_env(A, r0, c0):
+    """Brute force N_l: site (r0, c0) replaced by the tensor that maps its
+    virtual legs onto a physical index of dimension Dl Du Dr Dd; the state
+    vector then holds psi_rest[sigma, k] and N = psi_rest^T psi_rest."""
+    Lr, Lc = len(A), len(A[0])
+    sh = A[r0][c0].shape[1:]
+    K = int(np.prod(sh))
+    O = np.eye(K).reshape((K,) + sh)
+    B = [[O if (r, c) == (r0, c0) else A[r][c] for c in range(Lc)] for r in range(Lr)]
+    i = r0 * Lc + c0
+    psi = exact.statevector(B).reshape(2 ** i, K, -1)
+    M = psi.transpose(0, 2, 1).reshape(-1, K)
+    return M.T @ M
+
+
+@pytest.mark.parametrize("case", [("normal_unit", 3, 4), ("aniso", 3, 3), ("uniform", 1, 4), ("uniform", 4, 1)])
+def test_site_env_matches_brute_force(case):
+    """Lossless chi: N_l / <psi|psi> and log<psi|psi> of every site equal the
+    brute-force environment (corner, edge and bulk sites)."""
+    dist, Lr, Lc = case
+    A = (_anisotropic_peps(Lr, Lc, 2, 3, 80 + Lr * Lc) if dist == "aniso"
+         else make_peps(Lr, Lc, 2, dist, 81 + Lr * Lc))
+    psi = exact.statevector(A)
+    Z = float(psi @ psi)
+    env = api.env_boundary(A, 4096)
+    for r in range(Lr):
+        for c in range(Lc):
+            N, lz, sgn = api.site_env(env, r, c)
+            Ne = _open_site_env(A, r, c) / Z
+            assert np.abs(N - Ne).max() <= 1e-12 * np.abs(Ne).max()
+            assert abs(lz - np.log(Z)) < 1e-12 and sgn == 1.0
+
+
+def test_site_env_symmetric_psd_and_consistent_with_sz():
+    """N_l is symmetric and positive semidefinite at lossless chi; at
+    truncated chi (S^z A) N A equals the row sandwich's <S^z>."""
+    A = make_peps(4, 4, 2, "normal_unit", 83)
+    env = api.env_boundary(A, 4096)
+    N, _, _ = api.site_env(env, 1, 2)
+    assert np.abs(N - N.T).max() < 1e-14 * np.abs(N).max()
+    assert np.linalg.eigvalsh(N).min() > -1e-12 * np.abs(N).max()
+    envt = api.env_boundary(A, 3, 4)
+    res = api.expect(envt)
+    for (r, c) in [(0, 0), (1, 2), (3, 3), (2, 1)]:
+        N, _, sgn = api.site_env(envt, r, c)
+        a = A[r][c].reshape(2, -1)
+        sz_a = sandwich.apply_op(spin.SZ, A[r][c]).reshape(2, -1)
+        v = np.einsum("pk,kj,pj->", sz_a, N, a) / np.einsum("pk,kj,pj->", a, N, a)
+        assert abs(v - res["sz"][r, c]) < 1e-12
+        assert abs(np.einsum("pk,kj,pj->", a, N, a) - sgn) < 1e-12
+
+
 # --- P12/P13 ------------------------------------------------------------------
 
 def test_bounds_at_exact_chi():
