@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--halfsweeps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32/BF16 measurements")
+    ap.add_argument("--no-site-env", action="store_true",
+                    help="skip the measurement of the single-site norm environments")
     ap.add_argument("--no-columns", action="store_true",
                     help="skip the measurement of vertical bonds from column boundaries")
     ap.add_argument("--batch", type=int, default=8,
@@ -350,6 +352,24 @@ def main():
                           "expect_ms": 1000.0 * float(np.median([s[1] for s in csplit])),
                           "max_bond_v_gap_vs_two_row": float(np.max(np.abs(rc["bond_v"] - res["bond_v"]))),
                           "max_bond_h_diff": float(np.max(np.abs(rc["bond_h"] - res["bond_h"])))}
+
+    if not args.no_site_env:
+        # norm environments N_l of all 64 sites of one environment, one batched call
+        note("site norm environments")
+        env = sess.env_boundary([dev_state], chi, "f64", H)[0]
+        sites = [(env, r, c) for r in range(len(A)) for c in range(len(A[0]))]
+        sess.site_env(sites)
+        torch.cuda.synchronize()
+        n = max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            got, sfl = sess.site_env(sites)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n
+        env.free()
+        out["site_env"] = {"sites_per_call": len(sites), "ms_per_call": 1000.0 * t, "value": len(sites) / t,
+                           "unit": "site environments/s", "gflop_per_call": sfl / 1e9,
+                           "tflops": sfl / t / 1e12}
 
     if not args.no_forms:
         forms = {}

@@ -144,6 +144,27 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
 
 void peps_env_free(peps_env* env);
 
+/* Norm environment N_l of single sites (Sec. 3: the network of <psi|psi>
+ * with the ket and bra tensors of site l taken out, the matrix of the ALS
+ * tensor update N_l A_l = b_l), from the single-row sandwich of the site's
+ * row between the stored boundaries; one batched run over all requests.
+ * n (device, caller-allocated, K*K doubles with K = Dl*Du*Dr*Dd of the
+ * site): N[k][k'] row-major, k = ((l*Du + u)*Dr + r)*Dd + d the ket legs and
+ * k' the same bra legs, scaled so that sum_p A[p,k] N[k][k'] A[p,k'] = sign.
+ * log_z (out): log|<psi|psi>| as this row's sandwich estimates it, so the
+ * unscaled environment is sign * exp(log_z) * N.  (r, c) are window
+ * coordinates for a cluster environment (its cut legs closed by the CU_0
+ * boundaries: the environment of the cluster update).  All requests share
+ * one precision; *flops (may be NULL) receives the algorithmic flops. */
+typedef struct {
+  peps_env* env;
+  int32_t r, c;
+  double* n;
+  double log_z;   /* out */
+  double sign;    /* out */
+} peps_site_req;
+peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops);
+
 /* Thin QR of n_blocks float64 blocks, the gauge step of the truncation
  * (Sec. 2: the ALS sweep keeps every tensor but the centre isometric):
  * A = Q R with A m x n (m >= n >= 1, n <= 1024), Q m x n with orthonormal

@@ -124,9 +124,10 @@ def window_lattice(sep, r0, r1, c0, c1):
 
 
 def cluster_env(lat, n, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED,
-                tol=1e-14, max_sweeps=500, sites=None):
-    """Per-site window results: dict (i, j) -> (sz, bond_right, bond_down)."""
-    sep = SeparableEnv(lat, tol, max_sweeps)
+                tol=1e-14, max_sweeps=500, sites=None, sep=None):
+    """Per-site window results: dict (i, j) -> (sz, bond_right, bond_down).
+    ``sep``: CU_0 boundaries of ``lat`` from an earlier call (else built here)."""
+    sep = sep if sep is not None else SeparableEnv(lat, tol, max_sweeps)
     Lr, Lc = lat.rows, lat.cols
     out = {}
     for (i, j) in (sites if sites is not None else [(i, j) for i in range(Lr) for j in range(Lc)]):

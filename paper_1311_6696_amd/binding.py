@@ -63,6 +63,11 @@ class QrBlock(C.Structure):
                 ("m", C.c_int32), ("n", C.c_int32)]
 
 
+class SiteReq(C.Structure):
+    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("n", C.c_void_p),
+                ("log_z", C.c_double), ("sign", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("log_norm", C.c_double), ("norm_sign", C.c_double), ("sz", C.POINTER(C.c_double)),
                 ("bond", C.POINTER(C.c_double)), ("flops", C.c_double)]
@@ -70,7 +75,7 @@ class Result(C.Structure):
 
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
-           "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr",
+           "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
            "peps_last_error")
 
 _lib = None
@@ -102,11 +107,12 @@ def load(path=None):
     lib.peps_ctx_graphs.argtypes = [vp, C.c_int32]
     lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
     lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
+    lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
-                 "peps_ctx_set_workspace"):
+                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env"):
         getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -136,8 +142,14 @@ class RawState:
 
 
 class Env:
-    def __init__(self, ctx, handle, rows, cols, window=False):
+    def __init__(self, ctx, handle, rows, cols, window=False, shapes=None):
         self.ctx, self.handle, self.rows, self.cols, self.window = ctx, handle, rows, cols, window
+        self.shapes = shapes   # shapes[r][c] = (d, Dl, Du, Dr, Dd) of the (window) lattice
+
+    def site_dim(self, r, c):
+        """K = Dl Du Dr Dd of site (r, c): its norm environment is K x K."""
+        _, Dl, Du, Dr, Dd = self.shapes[r][c]
+        return int(Dl * Du * Dr * Dd)
 
     def info(self):
         lib = self.ctx.lib
@@ -206,7 +218,7 @@ class Context:
                 r.flags = OPTS_PER_STATE | flags
             o = (Opts * n)(*recs)
             _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, o, out))
-        return [Env(self, out[i], s.rows, s.cols) for i, s in enumerate(states)]
+        return [Env(self, out[i], s.rows, s.cols, shapes=s.shapes) for i, s in enumerate(states)]
 
     def cluster_env_raw(self, states, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
         n = len(states)
@@ -215,7 +227,8 @@ class Context:
         out = (C.c_void_p * len(windows))()
         o = self.opts(chi, dtype, halfsweeps, seed)
         _check(self.lib, self.lib.peps_cluster_env(self.handle, arr, n, w, len(windows), C.byref(o), out))
-        return [Env(self, out[i], win[2] - win[1] + 1, win[4] - win[3] + 1, window=True)
+        return [Env(self, out[i], win[2] - win[1] + 1, win[4] - win[3] + 1, window=True,
+                    shapes=[row[win[3]: win[4] + 1] for row in states[win[0]].shapes[win[1]: win[2] + 1]])
                 for i, win in enumerate(windows)]
 
     def expect(self, envs):
@@ -269,6 +282,14 @@ class Context:
     def set_workspace(self, nbytes):
         _check(self.lib, self.lib.peps_ctx_set_workspace(self.handle, int(nbytes)))
 
+    def site_env_raw(self, reqs):
+        """reqs: sequence of (env, r, c, device address of K*K doubles).
+        Returns ([(log_z, sign)], flops)."""
+        arr = (SiteReq * len(reqs))(*[SiteReq(e.handle, int(r), int(c), int(p), 0.0, 0.0) for e, r, c, p in reqs])
+        fl = C.c_double()
+        _check(self.lib, self.lib.peps_site_env(self.handle, arr, len(reqs), C.byref(fl)))
+        return [(arr[i].log_z, arr[i].sign) for i in range(len(reqs))], fl.value
+
     def qr_raw(self, blocks):
         """blocks: sequence of (a, a_rs, a_cs, q, q_rs, q_cs, r, r_rs, r_cs, m, n)
         with device addresses (r may be 0)."""
@@ -317,6 +338,15 @@ class Session:
 
     def expect(self, envs):
         return self.ctx.expect(envs)
+
+    def site_env(self, reqs):
+        """reqs: sequence of (env, r, c).  Returns ([(N, log_z, sign)], flops)
+        with N a K x K float64 GPU tensor (ket legs (l, u, r, d) as rows)
+        scaled so that sum_p A N A = sign."""
+        torch = self.torch
+        outs = [torch.empty((e.site_dim(r, c),) * 2, dtype=torch.float64, device="cuda") for e, r, c in reqs]
+        res, fl = self.ctx.site_env_raw([(e, r, c, n.data_ptr()) for (e, r, c), n in zip(reqs, outs)])
+        return [(n, lz, sg) for n, (lz, sg) in zip(outs, res)], fl
 
     def qr(self, mats, inplace=False):
         """Thin QR (R_ii >= 0) of float64 GPU matrices (2-D tensors, any

@@ -1,4 +1,5 @@
 // extern "C" entry points of libpepsenv (declared in include/peps_env.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <functional>
@@ -269,6 +270,47 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
 }
 
 void peps_env_free(peps_env* env) { delete env; }
+
+peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && req, "ctx and req must not be NULL");
+    PE_REQUIRE(n_req >= 1, "n_req must be >= 1");
+    std::vector<SiteReq> rs;
+    for (int i = 0; i < n_req; ++i) {
+      const peps_site_req& q = req[i];
+      const std::string w = "request " + std::to_string(i) + ": ";
+      PE_REQUIRE(q.env != nullptr && q.n != nullptr, w + "env and n must not be NULL");
+      PE_REQUIRE(q.env->ctx == ctx->c.get(), w + "environment belongs to another context");
+      PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c < q.env->lat.Lc, w + "site outside the lattice");
+      rs.push_back(SiteReq{q.env, q.r, q.c, q.n});
+    }
+    dev::set_device(ctx->c->device);
+    std::vector<peps_env*> es;
+    std::vector<double> f0;
+    for (const SiteReq& q : rs)
+      if (std::find(es.begin(), es.end(), q.e) == es.end()) {
+        es.push_back(q.e);
+        f0.push_back(q.e->flops);
+      }
+    std::vector<double> lz, sg;
+    double fl = 0.0;
+    try {
+      plan_site_env(*ctx->c, rs, lz, sg, fl);
+    } catch (...) {
+      for (size_t k = 0; k < es.size(); ++k) es[k]->flops = f0[k];
+      throw;
+    }
+    for (size_t k = 0; k < es.size(); ++k) {   // the row sandwiches' flops are this call's, not the environment's
+      fl += es[k]->flops - f0[k];
+      es[k]->flops = f0[k];
+    }
+    for (int i = 0; i < n_req; ++i) {
+      req[i].log_z = lz[i];
+      req[i].sign = sg[i];
+    }
+    if (flops) *flops = fl;
+  });
+}
 
 peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas) {
   return guarded([&] {

@@ -10,6 +10,7 @@
 // stage), then all operator insertions of all rows form two more batched
 // levels, then every scalar is one reduction.
 #include <array>
+#include <map>
 
 #include "chains.hpp"
 
@@ -154,6 +155,139 @@ void normalise(Rec& rec, const std::vector<std::pair<TV, double*>>& outs) {
   rec.ew(ew);
 }
 
+// One single-row sandwich job: row r of e between T_{r-1} and B_{r+1}, its
+// environment buffers in `call`; results go to `owner`.
+RJob make_row_job(peps_env* e, peps_env* owner, bool tr, int r, Arena& call, size_t esz) {
+  const Lattice& L = e->lat;
+  const int Lc = L.Lc;
+  RJob j;
+  j.e = e;
+  j.owner = owner;
+  j.tr = tr;
+  j.r = r;
+  j.Lc = Lc;
+  j.T = &e->T(r - 1);
+  j.B = &e->B(r + 1);
+  for (int c = 0; c < Lc; ++c) j.s.push_back(&L.at(r, c));
+  for (int c = 0; c <= Lc; ++c) {
+    j.bT.push_back(j.T->bond[c]);
+    j.bB.push_back(j.B->bond[c]);
+    j.Dl.push_back(c < Lc ? L.at(r, c).Dl : L.at(r, Lc - 1).Dr);
+  }
+  j.L.assign(Lc + 1, nullptr);
+  j.R.assign(Lc + 1, nullptr);
+  j.L[0] = const_cast<void*>(L.lam[r]);
+  j.R[Lc] = const_cast<void*>(L.rho[r]);
+  for (int c = 1; c < Lc; ++c) {
+    j.L[c] = call.alloc(esz * env_elems(j, c));
+    j.R[c] = call.alloc(esz * env_elems(j, c));
+  }
+  if (Lc >= 1) {
+    j.L[Lc] = call.alloc(esz * env_elems(j, Lc));
+    j.R[0] = call.alloc(esz * env_elems(j, 0));
+  }
+  j.nuL = (double*)call.alloc(sizeof(double) * (Lc + 1));
+  j.nuR = (double*)call.alloc(sizeof(double) * (Lc + 1));
+  j.dots = (double*)call.alloc(sizeof(double) * (Lc + 1 + Lc + 3 * Lc));
+  return j;
+}
+
+// Left and right column environments of every job (normalised, squared
+// norms in nuL/nuR), grouped by the scratch budget; one grouped launch per
+// stage and column step.
+void column_envs(Rec& rec, Arena& call, Scratch& scr, std::vector<RJob>& rj, std::vector<R2Job>& r2, int prec,
+                 int cdt, size_t esz, size_t budget) {
+  struct Slot {
+    int kind;   // 0 one-row left, 1 one-row right, 2 two-row left, 3 two-row right
+    size_t job;
+  };
+  std::vector<Slot> slots;
+  std::vector<size_t> sz;
+  for (size_t i = 0; i < rj.size(); ++i)
+    for (int k = 0; k < 2; ++k) {
+      size_t m = 0;
+      for (int c = 0; c < rj[i].Lc; ++c) {
+        auto pq = step_scratch(rj[i], c);
+        m = std::max(m, (size_t)(pq.first + pq.second));
+      }
+      slots.push_back({k, i});
+      sz.push_back(m * esz);
+    }
+  for (size_t i = 0; i < r2.size(); ++i)
+    for (int k = 2; k < 4; ++k) {
+      size_t m = 0;
+      for (int c = 0; c < r2[i].Lc; ++c) {
+        auto pq = step2_scratch(r2[i], c);
+        m = std::max(m, (size_t)(pq.first + pq.second));
+      }
+      slots.push_back({k, i});
+      sz.push_back(m * esz);
+    }
+  for (auto g : budget_groups(sz, budget)) {
+    std::vector<void*> P(g.second - g.first), Q(g.second - g.first);
+    int maxLc = 0;
+    for (size_t i = g.first; i < g.second; ++i) {
+      const Slot& sl = slots[i];
+      int64_t p = 0, q = 0;
+      const int Lc = sl.kind < 2 ? rj[sl.job].Lc : r2[sl.job].Lc;
+      maxLc = std::max(maxLc, Lc);
+      for (int c = 0; c < Lc; ++c) {
+        auto pq = sl.kind < 2 ? step_scratch(rj[sl.job], c) : step2_scratch(r2[sl.job], c);
+        p = std::max(p, pq.first);
+        q = std::max(q, pq.second);
+      }
+      P[i - g.first] = scr.get(esz * p);
+      Q[i - g.first] = scr.get(esz * q);
+    }
+    for (int s = 0; s < maxLc; ++s) {
+      St st1(3, prec), st2(5, prec);
+      std::vector<TcDesc> fin;
+      std::vector<std::pair<TV, double*>> outs;
+      for (size_t i = g.first; i < g.second; ++i) {
+        const Slot& sl = slots[i];
+        void* p = P[i - g.first];
+        void* q = Q[i - g.first];
+        if (sl.kind < 2) {
+          RJob& j = rj[sl.job];
+          if (s >= j.Lc) continue;
+          const double f0 = st1.flops;
+          if (sl.kind == 0) {
+            const int c = s;
+            TV o = step_left(st1, fin, j, c, envv(j, j.L[c], c, "xlma", cdt), 0, j.L[c + 1], p, q, cdt);
+            outs.push_back({o, j.nuL + c + 1});
+          } else {
+            const int c = j.Lc - 1 - s;
+            TV o = step_right(st1, fin, j, c, envv(j, j.R[c + 1], c + 1, "yrse", cdt), j.R[c], p, q, cdt);
+            outs.push_back({o, j.nuR + c});
+          }
+          j.e->flops += st1.flops - f0;
+        } else {
+          R2Job& j = r2[sl.job];
+          if (s >= j.Lc) continue;
+          const double f0 = st2.flops;
+          if (sl.kind == 2) {
+            const int c = s;
+            TV o = step2_left(st2, fin, j, c, env2v(j, j.L[c], c, "xLMlma", cdt), 0, 0, j.L[c + 1], p, q, cdt);
+            outs.push_back({o, j.nuL + c + 1});
+          } else {
+            const int c = j.Lc - 1 - s;
+            TV o = step2_right(st2, fin, j, c, env2v(j, j.R[c + 1], c + 1, "yRSrse", cdt), j.R[c], p, q, cdt);
+            outs.push_back({o, j.nuR + c});
+          }
+          j.e->flops += st2.flops - f0;
+        }
+      }
+      st1.record(rec, prec, cdt);
+      st2.record(rec, prec, cdt);
+      rec.tc(prec, cdt, fin);
+      normalise(rec, outs);
+      rec.flush(call);
+    }
+    for (void* p : P) scr.put(p);
+    for (void* q : Q) scr.put(q);
+  }
+}
+
 }  // namespace
 
 void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>& out) {
@@ -188,38 +322,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
     } else {
       for (int r = 0; r < Lr; ++r) rows.push_back(r);
     }
-    for (int r : rows) {
-      RJob j;
-      j.e = e;
-      j.owner = src.second;
-      j.tr = tr;
-      j.r = r;
-      j.Lc = Lc;
-      j.T = &e->T(r - 1);
-      j.B = &e->B(r + 1);
-      for (int c = 0; c < Lc; ++c) j.s.push_back(&L.at(r, c));
-      for (int c = 0; c <= Lc; ++c) {
-        j.bT.push_back(j.T->bond[c]);
-        j.bB.push_back(j.B->bond[c]);
-        j.Dl.push_back(c < Lc ? L.at(r, c).Dl : L.at(r, Lc - 1).Dr);
-      }
-      j.L.assign(Lc + 1, nullptr);
-      j.R.assign(Lc + 1, nullptr);
-      j.L[0] = const_cast<void*>(L.lam[r]);
-      j.R[Lc] = const_cast<void*>(L.rho[r]);
-      for (int c = 1; c < Lc; ++c) {
-        j.L[c] = call.alloc(esz * env_elems(j, c));
-        j.R[c] = call.alloc(esz * env_elems(j, c));
-      }
-      if (Lc >= 1) {
-        j.L[Lc] = call.alloc(esz * env_elems(j, Lc));
-        j.R[0] = call.alloc(esz * env_elems(j, 0));
-      }
-      j.nuL = (double*)call.alloc(sizeof(double) * (Lc + 1));
-      j.nuR = (double*)call.alloc(sizeof(double) * (Lc + 1));
-      j.dots = (double*)call.alloc(sizeof(double) * (Lc + 1 + Lc + 3 * Lc));
-      rj.push_back(std::move(j));
-    }
+    for (int r : rows) rj.push_back(make_row_job(e, src.second, tr, r, call, esz));
     std::vector<int> prs;
     if (tr || e->col) {
       // vertical bonds come from the transposed lattice
@@ -273,97 +376,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
   }
 
   // ------------------------------------- phase 1: column environments ----
-  {
-    struct Slot {
-      int kind;   // 0 one-row left, 1 one-row right, 2 two-row left, 3 two-row right
-      size_t job;
-    };
-    std::vector<Slot> slots;
-    std::vector<size_t> sz;
-    for (size_t i = 0; i < rj.size(); ++i)
-      for (int k = 0; k < 2; ++k) {
-        size_t m = 0;
-        for (int c = 0; c < rj[i].Lc; ++c) {
-          auto pq = step_scratch(rj[i], c);
-          m = std::max(m, (size_t)(pq.first + pq.second));
-        }
-        slots.push_back({k, i});
-        sz.push_back(m * esz);
-      }
-    for (size_t i = 0; i < r2.size(); ++i)
-      for (int k = 2; k < 4; ++k) {
-        size_t m = 0;
-        for (int c = 0; c < r2[i].Lc; ++c) {
-          auto pq = step2_scratch(r2[i], c);
-          m = std::max(m, (size_t)(pq.first + pq.second));
-        }
-        slots.push_back({k, i});
-        sz.push_back(m * esz);
-      }
-    for (auto g : budget_groups(sz, budget)) {
-      std::vector<void*> P(g.second - g.first), Q(g.second - g.first);
-      int maxLc = 0;
-      for (size_t i = g.first; i < g.second; ++i) {
-        const Slot& sl = slots[i];
-        int64_t p = 0, q = 0;
-        const int Lc = sl.kind < 2 ? rj[sl.job].Lc : r2[sl.job].Lc;
-        maxLc = std::max(maxLc, Lc);
-        for (int c = 0; c < Lc; ++c) {
-          auto pq = sl.kind < 2 ? step_scratch(rj[sl.job], c) : step2_scratch(r2[sl.job], c);
-          p = std::max(p, pq.first);
-          q = std::max(q, pq.second);
-        }
-        P[i - g.first] = scr.get(esz * p);
-        Q[i - g.first] = scr.get(esz * q);
-      }
-      for (int s = 0; s < maxLc; ++s) {
-        St st1(3, prec), st2(5, prec);
-        std::vector<TcDesc> fin;
-        std::vector<std::pair<TV, double*>> outs;
-        for (size_t i = g.first; i < g.second; ++i) {
-          const Slot& sl = slots[i];
-          void* p = P[i - g.first];
-          void* q = Q[i - g.first];
-          if (sl.kind < 2) {
-            RJob& j = rj[sl.job];
-            if (s >= j.Lc) continue;
-            const double f0 = st1.flops;
-            if (sl.kind == 0) {
-              const int c = s;
-              TV o = step_left(st1, fin, j, c, envv(j, j.L[c], c, "xlma", cdt), 0, j.L[c + 1], p, q, cdt);
-              outs.push_back({o, j.nuL + c + 1});
-            } else {
-              const int c = j.Lc - 1 - s;
-              TV o = step_right(st1, fin, j, c, envv(j, j.R[c + 1], c + 1, "yrse", cdt), j.R[c], p, q, cdt);
-              outs.push_back({o, j.nuR + c});
-            }
-            j.e->flops += st1.flops - f0;
-          } else {
-            R2Job& j = r2[sl.job];
-            if (s >= j.Lc) continue;
-            const double f0 = st2.flops;
-            if (sl.kind == 2) {
-              const int c = s;
-              TV o = step2_left(st2, fin, j, c, env2v(j, j.L[c], c, "xLMlma", cdt), 0, 0, j.L[c + 1], p, q, cdt);
-              outs.push_back({o, j.nuL + c + 1});
-            } else {
-              const int c = j.Lc - 1 - s;
-              TV o = step2_right(st2, fin, j, c, env2v(j, j.R[c + 1], c + 1, "yRSrse", cdt), j.R[c], p, q, cdt);
-              outs.push_back({o, j.nuR + c});
-            }
-            j.e->flops += st2.flops - f0;
-          }
-        }
-        st1.record(rec, prec, cdt);
-        st2.record(rec, prec, cdt);
-        rec.tc(prec, cdt, fin);
-        normalise(rec, outs);
-        rec.flush(call);
-      }
-      for (void* p : P) scr.put(p);
-      for (void* q : Q) scr.put(q);
-    }
-  }
+  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, budget);
 
   // ------------------------------------ phase 2: operator insertions ----
   // one-row: X1[c][op] (op Sz for every c, S+/S- for c < Lc-1), then X2[c][t]
@@ -588,6 +601,139 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       }
     }
   }
+}
+
+}  // namespace pe
+
+namespace pe {
+
+void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log_z, std::vector<double>& sign,
+                   double& flops) {
+  Arena call(&ctx.pool);
+  Rec rec(&ctx, &call);
+  Scratch scr(call);
+  const Opts& o = req[0].e->opts;
+  for (const SiteReq& q : req) PE_REQUIRE(q.e->opts.dtype == o.dtype, "one precision per site-environment call");
+  const int prec = o.prec(), cdt = o.cdt();
+  const size_t esz = dtype_size(cdt);
+
+  // one single-row sandwich per distinct (environment, row)
+  std::vector<RJob> rj;
+  std::vector<R2Job> r2;
+  std::map<std::pair<peps_env*, int>, size_t> job_of;
+  std::vector<size_t> jid(req.size());
+  for (size_t i = 0; i < req.size(); ++i) {
+    const auto key = std::make_pair(req[i].e, req[i].r);
+    auto it = job_of.find(key);
+    if (it == job_of.end()) {
+      it = job_of.emplace(key, rj.size()).first;
+      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
+    }
+    jid[i] = it->second;
+  }
+  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
+
+  // N[l,u,r,d,m,v,s,g] = L[c][x,l,m,a] T[c][a,u,v,e] B[c][x,d,g,y] R[c+1][y,r,s,e]
+  // (the norm network of the row with site c's ket and bra taken out):
+  // three grouped stages per budget group, N in the compute dtype
+  std::vector<void*> raw(req.size());
+  std::vector<int64_t> nel(req.size());
+  std::vector<size_t> sz(req.size());
+  struct Dims {
+    int64_t x, y, a, e, Dl, Du, Dr, Dd;
+  };
+  std::vector<Dims> dm(req.size());
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    const int c = req[i].c;
+    Dims d{j.bB[c], j.bB[c + 1], j.bT[c], j.bT[c + 1], j.Dl[c], j.T->leg[c], j.Dl[c + 1], j.B->leg[c]};
+    dm[i] = d;
+    nel[i] = d.Dl * d.Du * d.Dr * d.Dd * d.Dl * d.Du * d.Dr * d.Dd;
+    raw[i] = cdt == DT_F64 ? (void*)req[i].out : call.alloc(esz * nel[i]);
+    sz[i] = esz * (size_t)(d.x * d.Dl * d.Dl * d.Du * d.Du * d.e + d.Dl * d.Dl * d.Du * d.Du * d.e * d.Dd * d.Dd * d.y);
+  }
+  flops = 0.0;
+  std::vector<RedDesc> rd;
+  for (auto g : budget_groups(sz, ctx.scratch_budget)) {
+    std::vector<TcDesc> s1, s2, s3;
+    std::vector<void*> tmp;
+    for (size_t i = g.first; i < g.second; ++i) {
+      const RJob& j = rj[jid[i]];
+      const int c = req[i].c;
+      const Dims& d = dm[i];
+      void* p = scr.get(esz * d.x * d.Dl * d.Dl * d.Du * d.Du * d.e);
+      void* q = scr.get(esz * d.Dl * d.Dl * d.Du * d.Du * d.e * d.Dd * d.Dd * d.y);
+      tmp.push_back(p);
+      tmp.push_back(q);
+      TV L = envv(j, j.L[c], c, "xlma", cdt);
+      TV T = dense(j.T->tc[c], cdt, "auve", {d.a, d.Du, d.Du, d.e});
+      TV B = dense(j.B->tc[c], cdt, "xdgy", {d.x, d.Dd, d.Dd, d.y});
+      TV R = envv(j, j.R[c + 1], c + 1, "yrse", cdt);
+      // intermediate leg orders chosen so that every index group of each
+      // contraction merges into at most four strided sub-dimensions
+      TV y1 = dense(p, cdt, "xlumve", {d.x, d.Dl, d.Du, d.Dl, d.Du, d.e});
+      TV y2 = dense(q, cdt, "ludmvgye", {d.Dl, d.Du, d.Dd, d.Dl, d.Du, d.Dd, d.y, d.e});
+      TV n = dense(raw[i], cdt, "lurdmvsg", {d.Dl, d.Du, d.Dr, d.Dd, d.Dl, d.Du, d.Dr, d.Dd});
+      s1.push_back(tc_build(y1, L, T));
+      s2.push_back(tc_build(y2, y1, B));
+      s3.push_back(tc_build(n, y2, R));
+      flops += tc_flops(s1.back()) + tc_flops(s2.back()) + tc_flops(s3.back());
+    }
+    rec.tc(prec, cdt, s1);
+    rec.tc(prec, cdt, s2);
+    rec.tc(prec, cdt, s3);
+    for (void* p : tmp) scr.put(p);
+    rec.flush(call);
+  }
+  // <L[c+1], R[c+1]>: with the left step's squared norm, the value of A N A
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    const int c = req[i].c;
+    rd.push_back(red_desc(j.L[c + 1], j.R[c + 1], env_elems(j, c + 1), j.dots + c + 1, cdt));
+  }
+  rec.reduce(rd);
+  rec.run(call);
+
+  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
+  for (size_t k = 0; k < rj.size(); ++k) {
+    const int Lc = rj[k].Lc;
+    hd[k].resize(Lc + 1);
+    hl[k].resize(Lc + 1);
+    hr[k].resize(Lc + 1);
+    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
+  }
+  dev::sync(ctx.stream);
+  log_z.assign(req.size(), 0.0);
+  sign.assign(req.size(), 1.0);
+  double* w2 = (double*)call.alloc(sizeof(double) * req.size());
+  std::vector<EwDesc> fill, scale;
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    peps_env* e = req[i].e;
+    const int c = req[i].c, r = req[i].r;
+    const double w = std::sqrt(hl[jid[i]][c + 1]) * hd[jid[i]][c + 1];
+    if (!(std::isfinite(w) && w != 0.0))
+      throw Error(ST_NONFINITE, "site environment (" + std::to_string(r) + "," + std::to_string(c) + ") has A N A = " +
+                                    std::to_string(w));
+    double lg = e->Tlog(r - 1) + e->Blog(r + 1) + std::log(std::fabs(w));
+    for (int k = 1; k <= c; ++k) lg += 0.5 * std::log(hl[jid[i]][k]);
+    for (int k = c + 1; k < j.Lc; ++k) lg += 0.5 * std::log(hr[jid[i]][k]);
+    log_z[i] = lg;
+    sign[i] = w < 0 ? -1.0 : 1.0;
+    EwDesc f = ew_desc(EW_FILL, nullptr, DT_F64, w2 + i, DT_F64, 1);
+    f.a = w * w;
+    fill.push_back(f);
+    EwDesc s = ew_desc(EW_RSQRT, raw[i], cdt, req[i].out, DT_F64, nel[i]);
+    s.sptr = w2 + i;
+    scale.push_back(s);
+  }
+  Rec rec2(&ctx, &call);
+  rec2.ew(fill);
+  rec2.ew(scale);
+  rec2.run(call);
+  dev::sync(ctx.stream);
 }
 
 }  // namespace pe

@@ -31,4 +31,17 @@ struct ExpectOut {
 };
 void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>& out);
 
+// Norm environments of single sites (one batched run): site (r, c) of e
+// (window coordinates for a window), written as a float64 matrix into the
+// device buffer `out`, scaled so that sum_p A N A = sign; log|<psi|psi>| as
+// that row's sandwich estimates it, the sign, and the algorithmic flops of
+// the environment chains on the host.
+struct SiteReq {
+  peps_env* e;
+  int r, c;
+  double* out;
+};
+void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log_z, std::vector<double>& sign,
+                   double& flops);
+
 }  // namespace pe

@@ -1,0 +1,134 @@
+"""Norm environments N_l of single sites on the GPU (through the C ABI)
+against the FP64 oracle: whole lattices, cluster windows, batching, the full
+8x8 D=4 chi=32 workload and the FP32 form."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import api, cluster
+from oracle.boundary import whole_lattice
+from paper_1311_6696_amd import binding
+from paper_1311_6696_amd.inputs import make_peps, workload_peps, WORKLOADS
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sess():
+    return binding.Session(0)
+
+
+def check(got, ref, tol):
+    (N, lz, sg), (Nr, lzr, sgr) = got, ref
+    N = N.cpu().numpy()
+    assert N.shape == Nr.shape
+    assert np.abs(N - Nr).max() <= tol * max(1.0, np.abs(Nr).max())
+    assert abs(lz - lzr) <= tol * max(1.0, abs(lzr))
+    assert sg == sgr
+
+
+@pytest.mark.parametrize("case", [
+    (3, 4, 2, "normal_unit", 4096, 4),   # lossless chi
+    (4, 3, 3, "normal_unit", 5, 3),
+    (5, 5, 2, "near_product", 4, 4),
+    (1, 4, 2, "uniform", 4, 2),
+    (4, 1, 2, "uniform", 4, 2),
+])
+def test_site_env_parity_every_site(sess, case):
+    Lr, Lc, D, dist, chi, H = case
+    say(f"site environments {case}")
+    A = make_peps(Lr, Lc, D, dist, 300 + Lr * 10 + Lc)
+    env = sess.env_boundary([binding.to_device(A)], chi, "f64", H)[0]
+    sites = [(r, c) for r in range(Lr) for c in range(Lc)]
+    got, fl = sess.site_env([(env, r, c) for r, c in sites])
+    env.free()
+    ref_env = api.env_boundary(A, chi, H)
+    for (r, c), g in zip(sites, got):
+        check(g, api.site_env(ref_env, r, c), TOL64)
+    assert fl > 0
+
+
+def test_site_env_batched_over_lattices(sess):
+    """Requests on two lattices of different shapes in one call."""
+    say("site environments batched over two lattices")
+    A1, A2 = make_peps(4, 5, 2, "normal_unit", 311), make_peps(5, 3, 3, "uniform", 312)
+    e1, e2 = sess.env_boundary([binding.to_device(A1), binding.to_device(A2)], [4, 6], "f64", 3)
+    reqs = [(e1, 0, 0), (e2, 4, 2), (e1, 2, 3), (e2, 1, 1), (e1, 2, 1)]
+    got, _ = sess.site_env(reqs)
+    r1, r2 = api.env_boundary(A1, 4, 3), api.env_boundary(A2, 6, 3)
+    for (e, r, c), g in zip(reqs, got):
+        check(g, api.site_env(r1 if e is e1 else r2, r, c), TOL64)
+    # the environments still give their observables afterwards
+    res = sess.expect([e1])[0]
+    assert np.abs(res["sz"] - api.expect(r1)["sz"]).max() < TOL64
+    e1.free()
+    e2.free()
+
+
+def test_site_env_of_cluster_windows(sess):
+    """Centre-site environments of n = 3 windows (cut legs closed by CU_0):
+    the environment a cluster update of that site uses."""
+    say("site environments of n=3 windows")
+    L, n, chi = 5, 3, 4
+    A = make_peps(L, L, 2, "near_product", 321)
+    sample = [(0, 0), (2, 2), (4, 1), (1, 4)]
+    wins = []
+    for (i, j) in sample:
+        r0, r1 = cluster.window_bounds(i, n, L)
+        c0, c1 = cluster.window_bounds(j, n, L)
+        wins.append((0, r0, r1, c0, c1, i, j))
+    envs = sess.cluster_env([binding.to_device(A)], wins, chi, "f64", 4)
+    got, _ = sess.site_env([(e, w[5] - w[1], w[6] - w[3]) for e, w in zip(envs, wins)])
+    for e in envs:
+        e.free()
+    sep = cluster.SeparableEnv(whole_lattice(A))
+    for w, g in zip(wins, got):
+        _, r0, r1, c0, c1, i, j = w
+        wenv = api.env_boundary(cluster.window_lattice(sep, r0, r1, c0, c1), chi, 4)
+        check(g, api.site_env(wenv, i - r0, j - c0), TOL64)
+
+
+def test_site_env_8x8_D4_chi32_sample(sess):
+    """8x8, D=4, near-product, chi=32: every site in one batched call, a
+    sample (corner, edges, bulk) against the oracle."""
+    say("site environments 8x8 D=4 chi=32")
+    c = WORKLOADS["8x8_D4_chi32"]
+    A = workload_peps("8x8_D4_chi32")
+    env = sess.env_boundary([binding.to_device(A)], c["chi"], "f64", 4)[0]
+    sites = [(r, s) for r in range(8) for s in range(8)]
+    got, _ = sess.site_env([(env, r, s) for r, s in sites])
+    env.free()
+    ref_env = api.env_boundary(A, c["chi"], 4)
+    for k in (0, 7, 19, 27, 36, 56, 63):
+        r, s = sites[k]
+        check(got[k], api.site_env(ref_env, r, s), TOL64)
+
+
+def test_site_env_fp32_form(sess):
+    """FP32 contractions (FP64 QR and norms): error against the FP64 oracle."""
+    say("site environments fp32")
+    A = make_peps(5, 5, 3, "normal_unit", 331)
+    env = sess.env_boundary([binding.to_device(A)], 9, "f32", 4)[0]
+    sites = [(0, 0), (2, 2), (4, 3)]
+    got, _ = sess.site_env([(env, r, c) for r, c in sites])
+    env.free()
+    ref_env = api.env_boundary(A, 9, 4)
+    for (r, c), g in zip(sites, got):
+        check(g, api.site_env(ref_env, r, c), 1e-4)
+
+
+def test_site_env_rejects_bad_requests(sess):
+    A = make_peps(3, 3, 2, "uniform", 5)
+    env = sess.env_boundary([binding.to_device(A)], 4)[0]
+    with pytest.raises(binding.PepsError):
+        sess.ctx.site_env_raw([(env, 3, 0, 1 << 20)])
+    with pytest.raises(binding.PepsError):
+        sess.ctx.site_env_raw([(env, 0, 0, 0)])
+    env.free()
