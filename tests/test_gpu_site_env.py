@@ -132,3 +132,46 @@ def test_site_env_rejects_bad_requests(sess):
     with pytest.raises(binding.PepsError):
         sess.ctx.site_env_raw([(env, 0, 0, 0)])
     env.free()
+
+
+def test_strip_cluster_site_env(sess):
+    """A strip cluster (delta = 3 rows around row 2, every column) is a
+    window spanning the lattice's width: its boundaries, observables and the
+    environments of the centre row's sites for a strip cluster update."""
+    say("strip cluster delta=3")
+    L, chi = 6, 4
+    A = make_peps(L, L, 2, "near_product", 341)
+    wins = [(0, 1, 3, 0, L - 1, 2, j) for j in range(L)]
+    envs = sess.cluster_env([binding.to_device(A)], wins, chi, "f64", 4)
+    res = sess.expect(envs)
+    got, _ = sess.site_env([(e, 1, w[6]) for e, w in zip(envs, wins)])
+    for e in envs:
+        e.free()
+    sep = cluster.SeparableEnv(whole_lattice(A))
+    wenv = api.env_boundary(cluster.window_lattice(sep, 1, 3, 0, L - 1), chi, 4)
+    ref = api.expect(wenv, rows=[1])
+    for w, r, g in zip(wins, res, got):
+        j = w[6]
+        assert abs(r["sz"] - ref["sz"][1, j]) < TOL64
+        if j < L - 1:
+            assert abs(r["right"] - ref["bond_h"][1, j]) < TOL64
+        check(g, api.site_env(wenv, 1, j), TOL64)
+
+
+def test_site_env_with_column_environment_and_fp32_columns(sess):
+    """Site environments of an environment that also holds column
+    boundaries; the column path in the FP32 form against the FP64 oracle."""
+    say("site env on a column environment; fp32 columns")
+    A = make_peps(4, 5, 2, "normal_unit", 351)
+    env = sess.env_boundary([binding.to_device(A)], 4, "f64", 4, columns=True)[0]
+    got, _ = sess.site_env([(env, 1, 3), (env, 3, 0)])
+    env.free()
+    ref_env = api.env_boundary(A, 4, 4)
+    check(got[0], api.site_env(ref_env, 1, 3), TOL64)
+    check(got[1], api.site_env(ref_env, 3, 0), TOL64)
+    env32 = sess.env_boundary([binding.to_device(A)], 4, "f32", 4, columns=True)[0]
+    r = sess.expect([env32])[0]
+    env32.free()
+    ref = api.expect(ref_env, columns=api.env_columns(A, 4, 4))
+    for k in ("sz", "bond_h", "bond_v"):
+        assert np.abs(r[k] - ref[k]).max() < 1e-5
