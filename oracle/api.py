@@ -15,6 +15,8 @@ and cluster windows.  Test infrastructure only (see the package docstring).
 * ``site_env`` - norm environment N_l of one site (Sec. 3, the matrix of
   the ALS tensor update) from its row sandwich, scaled to A N A = +-1, with
   the log of the scale.
+* ``bond_env`` - right-hand sides b_l of the ALS update of a horizontal
+  bond under a two-site gate (Sec. 3), in the scaling of ``site_env``.
 * ``cluster_env`` - per-site n x n windows closed by CU_0 separable
   boundaries (``cluster``), Sec. 5.3.
 """
@@ -23,7 +25,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .boundary import flip_vertical, top_boundaries, transpose_lattice, whole_lattice, Lattice
-from .sandwich import row_observables, site_environment, two_row_observables
+from .sandwich import bond_gate_environment, row_observables, site_environment, two_row_observables
 
 DEFAULT_SEED = 0x13116696
 DEFAULT_HALFSWEEPS = 4
@@ -114,6 +116,16 @@ def site_env(env, r, c):
     B, sB, _ = env.B(r + 1)
     N, lz, sgn = site_environment(T, lat.A[r], B, lat.lam[r], lat.rho[r], c)
     return N, lz + sT + sB, sgn
+
+
+def bond_env(env, r, c, G):
+    """(b_left, b_right) of the horizontal bond (r, c)-(r, c+1) under the
+    two-site gate G[p, P, q, Q], each (d, Dl Du Dr Dd), in the scaling of
+    ``site_env`` of the same site (G = 1 gives b = N A)."""
+    lat = env.lat
+    T, _, _ = env.T(r - 1)
+    B, _, _ = env.B(r + 1)
+    return bond_gate_environment(T, lat.A[r], B, lat.lam[r], lat.rho[r], c, G)
 
 
 def energy(res):

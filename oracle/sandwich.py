@@ -141,6 +141,44 @@ def site_environment(T, Arow, B, lam, rho, c):
     return N / abs(w), np.log(abs(w)) + sL[c] + sR[c + 1], (1.0 if w >= 0 else -1.0)
 
 
+def bond_gate_environment(T, Arow, B, lam, rho, c, G):
+    """Right-hand sides b of the ALS update of the horizontal bond (c, c+1)
+    under a two-site gate (Sec. 3, N_l A_l = b_l): the overlap <psi'|G psi>
+    with psi' = psi, differentiated by the bra tensor of site c (b_left) or
+    of site c+1 (b_right).
+
+    G[p, P, q, Q] maps the physical indices (q, Q) of sites (c, c+1) to
+    (p, P).  The pair environment with both bra tensors removed is
+    E[p,P,m,v,g,V,S,G'] = sum L[o,l,m,a] T_c[a,u,v,e] T_c+1[e,U,V,f]
+        Theta[p,P,l,u,d,U,R,D] B_c[o,d,g,y] B_c+1[y,D,G',z] R[z,R,S,f],
+    Theta = G . (A_c A_c+1) summed over the shared bond, with the normalised
+    Lenv[c], Renv[c+2]; b_left = E . A_c+1 (bra), b_right = E . A_c (bra),
+    each as a (d, Dl Du Dr Dd) matrix divided by the same numbers as the
+    site's norm environment (``site_environment``), so that G = 1 gives
+    b[p, k'] = sum_k A[p, k] N[k, k'] (k the ket, k' the bra legs).
+    """
+    Lenv, Renv, sL, sR = row_environments(T, Arow, B, lam, rho)
+    A1, A2 = Arow[c], Arow[c + 1]
+    Theta = np.einsum("pPqQ,qlurd,QrURD->pPludURD", G, A1, A2, **EIN)
+    X = np.einsum("olma,auve,odgy->lumvdgye", Lenv[c], T[c], B[c], **EIN)
+    Z = np.einsum("zRSf,eUVf,yDGz->RSeUVyDG", Renv[c + 2], T[c + 1], B[c + 1], **EIN)
+    E = np.einsum("lumvdgye,pPludURD,RSeUVyDG->pPmvgVSG", X, Theta, Z, **EIN)
+    bl = np.einsum("pPmvgVSG,PsVSG->pmvsg", E, A2, **EIN)
+    br = np.einsum("pPmvgVSG,pmvsg->PsVSG", E, A1, **EIN)
+
+    def absw(k):   # |sum_p A N A| of site k, N from the normalised environments
+        Y = np.einsum("olma,auve->olmuve", Lenv[k], T[k], **EIN)
+        Y = np.einsum("olmuve,odgy->lmuvedgy", Y, B[k], **EIN)
+        N = np.einsum("lmuvedgy,yrse->lurdmvsg", Y, Renv[k + 1], **EIN)
+        K = int(np.prod(Arow[k].shape[1:]))
+        a = Arow[k].reshape(-1, K)
+        return abs(float(np.einsum("pk,kj,pj->", a, N.reshape(K, K), a)))
+
+    sc_l = np.exp(sR[c + 1] - sR[c + 2]) * absw(c)       # Renv[c+1] = step(Renv[c+2]) / its norm
+    sc_r = np.exp(sL[c + 1] - sL[c]) * absw(c + 1)       # Lenv[c+1] = step(Lenv[c]) / its norm
+    return (bl.reshape(A1.shape[0], -1) / sc_l, br.reshape(A2.shape[0], -1) / sc_r)
+
+
 def two_row_observables(T, Arow1, Arow2, B, lam1, rho1, lam2, rho2):
     """Vertical bond energies between two adjacent rows, per column."""
     Lc = len(Arow1)

@@ -390,6 +390,55 @@ def test_site_env_symmetric_psd_and_consistent_with_sz():
         assert abs(np.einsum("pk,kj,pj->", a, N, a) - sgn) < 1e-12
 
 
+def _gate_applied(psi, N, i, j, G):
+    """G[p, P, q, Q] on sites i < j of a 2^N state vector."""
+    t = np.tensordot(G, psi.reshape((2,) * N), axes=([2, 3], [i, j]))
+    return np.moveaxis(t, [0, 1], [i, j])
+
+
+@pytest.mark.parametrize("case", [("normal_unit", 3, 4), ("aniso", 3, 3), ("uniform", 1, 4)])
+def test_bond_env_matches_brute_force(case):
+    """Lossless chi: b of both sites of every horizontal bond under a random
+    two-site gate equals d<psi|G psi>/dA (brute force) over <psi|psi>."""
+    dist, Lr, Lc = case
+    A = (_anisotropic_peps(Lr, Lc, 2, 3, 90 + Lr * Lc) if dist == "aniso"
+         else make_peps(Lr, Lc, 2, dist, 91 + Lr * Lc))
+    G = np.random.default_rng(Lr * Lc).standard_normal((2, 2, 2, 2))
+    psi = exact.statevector(A)
+    Z = float(psi @ psi)
+    N = Lr * Lc
+    env = api.env_boundary(A, 4096)
+    for r in range(Lr):
+        for c in range(Lc - 1):
+            i, j = r * Lc + c, r * Lc + c + 1
+            phi = _gate_applied(psi, N, i, j, G)
+            got = api.bond_env(env, r, c, G)
+            for site, b in ((i, got[0]), (j, got[1])):
+                rr, cc = divmod(site, Lc)
+                K = int(np.prod(A[rr][cc].shape[1:]))
+                O = np.eye(K).reshape((K,) + A[rr][cc].shape[1:])
+                Bt = [[O if (x, y) == (rr, cc) else A[x][y] for y in range(Lc)] for x in range(Lr)]
+                M = exact.statevector(Bt).reshape(2 ** site, K, -1)
+                ref = np.einsum("akb,apb->pk", M, phi.reshape(2 ** site, 2, -1)) / Z
+                assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_bond_env_identity_gate_is_N_times_A():
+    """Truncated chi: for the identity gate b[p, k'] = sum_k A[p, k] N[k, k']
+    for both sites (the scalings of the bond and site environments agree;
+    truncated boundaries need not be symmetric under ket <-> bra, so the
+    contraction runs over N's ket index)."""
+    A = make_peps(4, 4, 2, "normal_unit", 93)
+    env = api.env_boundary(A, 3, 4)
+    eye = np.eye(4).reshape(2, 2, 2, 2)
+    for (r, c) in [(0, 0), (1, 2), (3, 1)]:
+        bl, br = api.bond_env(env, r, c, eye)
+        for b, cc in ((bl, c), (br, c + 1)):
+            Nm, _, sgn = api.site_env(env, r, cc)
+            a = A[r][cc].reshape(2, -1)
+            assert np.abs(b - a @ Nm).max() < 1e-12 * np.abs(b).max()
+
+
 # --- P12/P13 ------------------------------------------------------------------
 
 def test_bounds_at_exact_chi():
