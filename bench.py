@@ -370,6 +370,27 @@ def main():
         out["site_env"] = {"sites_per_call": len(sites), "ms_per_call": 1000.0 * t, "value": len(sites) / t,
                            "unit": "site environments/s", "gflop_per_call": sfl / 1e9,
                            "tflops": sfl / t / 1e12}
+        # right-hand sides b of both sites of all 56 horizontal bonds under one
+        # imaginary-time Heisenberg gate exp(-0.02 S.S), one batched call
+        note("gated bond environments")
+        h = np.zeros((4, 4))
+        sz, sp = np.diag([0.5, -0.5]), np.array([[0.0, 1.0], [0.0, 0.0]])
+        h += np.kron(sz, sz) + 0.5 * (np.kron(sp, sp.T) + np.kron(sp.T, sp))
+        ev, U = np.linalg.eigh(h)
+        gate = torch.as_tensor((U @ np.diag(np.exp(-0.02 * ev)) @ U.T).reshape(2, 2, 2, 2), device="cuda")
+        env = sess.env_boundary([dev_state], chi, "f64", H)[0]
+        bonds = [(env, r, c, gate) for r in range(len(A)) for c in range(len(A[0]) - 1)]
+        sess.bond_env(bonds)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            got, bfl = sess.bond_env(bonds)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n
+        env.free()
+        out["bond_env"] = {"bonds_per_call": len(bonds), "ms_per_call": 1000.0 * t, "value": len(bonds) / t,
+                           "unit": "gated bond environments/s", "gflop_per_call": bfl / 1e9,
+                           "tflops": bfl / t / 1e12}
 
     if not args.no_forms:
         forms = {}

@@ -154,8 +154,10 @@ void peps_env_free(peps_env* env);
  * log_z (out): log|<psi|psi>| as this row's sandwich estimates it, so the
  * unscaled environment is sign * exp(log_z) * N.  (r, c) are window
  * coordinates for a cluster environment (its cut legs closed by the CU_0
- * boundaries: the environment of the cluster update).  All requests share
- * one precision; *flops (may be NULL) receives the algorithmic flops. */
+ * boundaries: the environment of the cluster update).  N is symmetric and
+ * positive semidefinite at lossless chi; truncated boundaries need not be
+ * symmetric under ket <-> bra.  All requests share one precision; *flops
+ * (may be NULL) receives the algorithmic flops. */
 typedef struct {
   peps_env* env;
   int32_t r, c;
@@ -164,6 +166,28 @@ typedef struct {
   double sign;    /* out */
 } peps_site_req;
 peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops);
+
+/* Right-hand sides b_l of the ALS update of a horizontal bond (Sec. 3,
+ * N_l A_l = b_l) under a two-site gate: the overlap <psi|G psi> of the
+ * stored state with the gated one, differentiated by the bra tensor of the
+ * left site (r,c) and of the right site (r,c+1), from the row sandwich of
+ * row r (both bra tensors of the bond are taken out of the network once,
+ * then contracted with either neighbour).  gate (device): d^2 x d^2 float64
+ * row-major, G[(p*d + P)*d*d + q*d + Q] maps the physical indices (q, Q) of
+ * the left and right site to (p, P).  b_left / b_right (device, may be
+ * NULL): d*K doubles [p][k] of that site, k as in peps_site_env, in the
+ * scaling of that site's peps_site_env matrix: for the identity gate
+ * b[p][k'] = sum_k A[p][k] N[k][k'].  (At truncated chi the boundaries need
+ * not be symmetric under ket <-> bra, so neither need N.)  All requests
+ * share one precision; *flops (may be NULL) receives the algorithmic flops. */
+typedef struct {
+  peps_env* env;
+  int32_t r, c;           /* bond (r,c)-(r,c+1), window coordinates for a cluster environment */
+  const double* gate;
+  double* b_left;
+  double* b_right;
+} peps_bond_req;
+peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req, double* flops);
 
 /* Thin QR of n_blocks float64 blocks, the gauge step of the truncation
  * (Sec. 2: the ALS sweep keeps every tensor but the centre isometric):

@@ -159,10 +159,12 @@ def bond_gate_environment(T, Arow, B, lam, rho, c, G):
     """
     Lenv, Renv, sL, sR = row_environments(T, Arow, B, lam, rho)
     A1, A2 = Arow[c], Arow[c + 1]
-    Theta = np.einsum("pPqQ,qlurd,QrURD->pPludURD", G, A1, A2, **EIN)
-    X = np.einsum("olma,auve,odgy->lumvdgye", Lenv[c], T[c], B[c], **EIN)
-    Z = np.einsum("zRSf,eUVf,yDGz->RSeUVyDG", Renv[c + 2], T[c + 1], B[c + 1], **EIN)
-    E = np.einsum("lumvdgye,pPludURD,RSeUVyDG->pPmvgVSG", X, Theta, Z, **EIN)
+    Theta = np.einsum("pPqQ,qQludURD->pPludURD", G, np.einsum("qlurd,QrURD->qQludURD", A1, A2, **EIN), **EIN)
+    X = np.einsum("olmuve,odgy->lumvdgye", np.einsum("olma,auve->olmuve", Lenv[c], T[c], **EIN), B[c], **EIN)
+    Z = np.einsum("zRSeUV,yDGz->RSeUVyDG", np.einsum("zRSf,eUVf->zRSeUV", Renv[c + 2], T[c + 1], **EIN),
+                  B[c + 1], **EIN)
+    W = np.einsum("RSeUVyDG,pPludURD->SeVyGpPlud", Z, Theta, **EIN)
+    E = np.einsum("lumvdgye,SeVyGpPlud->pPmvgVSG", X, W, **EIN)
     bl = np.einsum("pPmvgVSG,PsVSG->pmvsg", E, A2, **EIN)
     br = np.einsum("pPmvgVSG,pmvsg->PsVSG", E, A1, **EIN)
 

@@ -68,6 +68,11 @@ class SiteReq(C.Structure):
                 ("log_z", C.c_double), ("sign", C.c_double)]
 
 
+class BondReq(C.Structure):
+    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("gate", C.c_void_p),
+                ("b_left", C.c_void_p), ("b_right", C.c_void_p)]
+
+
 class Result(C.Structure):
     _fields_ = [("log_norm", C.c_double), ("norm_sign", C.c_double), ("sz", C.POINTER(C.c_double)),
                 ("bond", C.POINTER(C.c_double)), ("flops", C.c_double)]
@@ -76,7 +81,7 @@ class Result(C.Structure):
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
            "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
-           "peps_last_error")
+           "peps_bond_env", "peps_last_error")
 
 _lib = None
 
@@ -108,11 +113,12 @@ def load(path=None):
     lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
     lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
     lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
+    lib.peps_bond_env.argtypes = [vp, C.POINTER(BondReq), i32, C.POINTER(C.c_double)]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
-                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env"):
+                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env", "peps_bond_env"):
         getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -290,6 +296,15 @@ class Context:
         _check(self.lib, self.lib.peps_site_env(self.handle, arr, len(reqs), C.byref(fl)))
         return [(arr[i].log_z, arr[i].sign) for i in range(len(reqs))], fl.value
 
+    def bond_env_raw(self, reqs):
+        """reqs: sequence of (env, r, c, gate, b_left, b_right) with device
+        addresses (0 for an output not wanted).  Returns the flops."""
+        arr = (BondReq * len(reqs))(*[BondReq(e.handle, int(r), int(c), int(g), int(bl) or None, int(br) or None)
+                                      for e, r, c, g, bl, br in reqs])
+        fl = C.c_double()
+        _check(self.lib, self.lib.peps_bond_env(self.handle, arr, len(reqs), C.byref(fl)))
+        return fl.value
+
     def qr_raw(self, blocks):
         """blocks: sequence of (a, a_rs, a_cs, q, q_rs, q_cs, r, r_rs, r_cs, m, n)
         with device addresses (r may be 0)."""
@@ -347,6 +362,23 @@ class Session:
         outs = [torch.empty((e.site_dim(r, c),) * 2, dtype=torch.float64, device="cuda") for e, r, c in reqs]
         res, fl = self.ctx.site_env_raw([(e, r, c, n.data_ptr()) for (e, r, c), n in zip(reqs, outs)])
         return [(n, lz, sg) for n, (lz, sg) in zip(outs, res)], fl
+
+    def bond_env(self, reqs):
+        """reqs: sequence of (env, r, c, gate) with gate a (d, d, d, d)
+        float64 GPU tensor G[p, P, q, Q].  Returns ([(b_left, b_right)], flops),
+        each b a (d, K) float64 GPU tensor of that site."""
+        torch = self.torch
+        outs, raw = [], []
+        for e, r, c, g in reqs:
+            if not g.is_cuda or g.dtype != torch.float64 or not g.is_contiguous():
+                raise ValueError("the gate must be a contiguous float64 GPU tensor")
+            d = int(e.shapes[r][c][0])
+            bl = torch.empty((d, e.site_dim(r, c)), dtype=torch.float64, device="cuda")
+            br = torch.empty((d, e.site_dim(r, c + 1)), dtype=torch.float64, device="cuda")
+            outs.append((bl, br))
+            raw.append((e, r, c, g.data_ptr(), bl.data_ptr(), br.data_ptr()))
+        fl = self.ctx.bond_env_raw(raw)
+        return outs, fl
 
     def qr(self, mats, inplace=False):
         """Thin QR (R_ii >= 0) of float64 GPU matrices (2-D tensors, any

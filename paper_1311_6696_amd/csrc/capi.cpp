@@ -271,6 +271,44 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
 
 void peps_env_free(peps_env* env) { delete env; }
 
+peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req, double* flops) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && req, "ctx and req must not be NULL");
+    PE_REQUIRE(n_req >= 1, "n_req must be >= 1");
+    std::vector<BondReq> rs;
+    for (int i = 0; i < n_req; ++i) {
+      const peps_bond_req& q = req[i];
+      const std::string w = "request " + std::to_string(i) + ": ";
+      PE_REQUIRE(q.env != nullptr && q.gate != nullptr, w + "env and gate must not be NULL");
+      PE_REQUIRE(q.b_left != nullptr || q.b_right != nullptr, w + "no output requested");
+      PE_REQUIRE(q.env->ctx == ctx->c.get(), w + "environment belongs to another context");
+      PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c + 1 < q.env->lat.Lc,
+                 w + "bond outside the lattice");
+      rs.push_back(BondReq{q.env, q.r, q.c, q.gate, q.b_left, q.b_right});
+    }
+    dev::set_device(ctx->c->device);
+    std::vector<peps_env*> es;
+    std::vector<double> f0;
+    for (const BondReq& q : rs)
+      if (std::find(es.begin(), es.end(), q.e) == es.end()) {
+        es.push_back(q.e);
+        f0.push_back(q.e->flops);
+      }
+    double fl = 0.0;
+    try {
+      plan_bond_env(*ctx->c, rs, fl);
+    } catch (...) {
+      for (size_t k = 0; k < es.size(); ++k) es[k]->flops = f0[k];
+      throw;
+    }
+    for (size_t k = 0; k < es.size(); ++k) {
+      fl += es[k]->flops - f0[k];
+      es[k]->flops = f0[k];
+    }
+    if (flops) *flops = fl;
+  });
+}
+
 peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops) {
   return guarded([&] {
     PE_REQUIRE(ctx && req, "ctx and req must not be NULL");

@@ -737,3 +737,205 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
 }
 
 }  // namespace pe
+
+namespace pe {
+
+void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
+  Arena call(&ctx.pool);
+  Rec rec(&ctx, &call);
+  Scratch scr(call);
+  const Opts& o = req[0].e->opts;
+  for (const BondReq& q : req) PE_REQUIRE(q.e->opts.dtype == o.dtype, "one precision per bond-environment call");
+  const int prec = o.prec(), cdt = o.cdt();
+  const size_t esz = dtype_size(cdt);
+
+  std::vector<RJob> rj;
+  std::vector<R2Job> r2;
+  std::map<std::pair<peps_env*, int>, size_t> job_of;
+  std::vector<size_t> jid(req.size());
+  for (size_t i = 0; i < req.size(); ++i) {
+    const auto key = std::make_pair(req[i].e, req[i].r);
+    auto it = job_of.find(key);
+    if (it == job_of.end()) {
+      it = job_of.emplace(key, rj.size()).first;
+      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
+    }
+    jid[i] = it->second;
+  }
+  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
+
+  // gates in the compute dtype
+  std::vector<const void*> gate(req.size());
+  {
+    std::vector<EwDesc> cv;
+    for (size_t i = 0; i < req.size(); ++i) {
+      const int64_t d = rj[jid[i]].s[req[i].c]->d;
+      if (cdt == DT_F64) {
+        gate[i] = req[i].gate;
+      } else {
+        void* g = call.alloc(esz * d * d * d * d);
+        cv.push_back(ew_desc(EW_COPY, req[i].gate, DT_F64, g, cdt, d * d * d * d));
+        gate[i] = g;
+      }
+    }
+    if (!cv.empty()) rec.ew(cv);
+  }
+
+  // Per bond (c, c+1) of row r, with both bra tensors taken out:
+  //   X[l,u,d,m,v,g,y,e]  = L[c] T[c] B[c]
+  //   Z[R,S,e,U,V,y,D,G]  = R[c+2] T[c+1] B[c+1]
+  //   Th[p,P,l,u,d,U,R,D] = gate[p,P,q,Q] A_c[q,l,u,r,d] A_c+1[Q,r,U,R,D]
+  //   W[S,e,V,y,G,p,P,l,u,d] = Z Th,   E[p,P,m,v,g,V,S,G] = X W,
+  //   b_left = E . A_c+1 (bra),  b_right = E . A_c (bra).
+  // Leg orders are chosen so that every index group of each contraction
+  // merges into at most four strided sub-dimensions.
+  struct Dims {
+    int64_t d, x, y, z, a, e, f, Dl, Du, Dd, R, U, D;
+  };
+  std::vector<Dims> dm(req.size());
+  std::vector<size_t> sz(req.size());
+  std::vector<void*> rawl(req.size(), nullptr), rawr(req.size(), nullptr);
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    const int c = req[i].c;
+    const Site& s1 = *j.s[c];
+    const Site& s2 = *j.s[c + 1];
+    PE_REQUIRE(s1.d == s2.d, "the two sites of a gated bond need one physical dimension");
+    Dims q{s1.d, j.bB[c], j.bB[c + 1], j.bB[c + 2], j.bT[c], j.bT[c + 1], j.bT[c + 2],
+           j.Dl[c], j.T->leg[c], j.B->leg[c], j.Dl[c + 2], j.T->leg[c + 1], j.B->leg[c + 1]};
+    dm[i] = q;
+    const int64_t K1 = q.Dl * q.Du * j.Dl[c + 1] * q.Dd, K2 = j.Dl[c + 1] * q.U * q.R * q.D;
+    if (req[i].bl) rawl[i] = cdt == DT_F64 ? (void*)req[i].bl : call.alloc(esz * q.d * K1);
+    if (req[i].br) rawr[i] = cdt == DT_F64 ? (void*)req[i].br : call.alloc(esz * q.d * K2);
+    const int64_t n = q.x * q.Dl * q.Du * q.Dl * q.Du * q.e                 // X1
+                      + q.Dl * q.Du * q.Dd * q.Dl * q.Du * q.Dd * q.y * q.e   // X
+                      + q.z * q.R * q.R * q.e * q.U * q.U                     // Z1
+                      + q.R * q.R * q.e * q.U * q.U * q.y * q.D * q.D         // Z
+                      + 2 * q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D   // A_c A_c+1, Th
+                      + q.R * q.e * q.U * q.y * q.D * q.d * q.d * q.Dl * q.Du * q.Dd   // W
+                      + q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D;     // E
+    sz[i] = esz * (size_t)n;
+  }
+  flops = 0.0;
+  for (auto g : budget_groups(sz, ctx.scratch_budget)) {
+    std::vector<TcDesc> st[5];
+    std::vector<void*> tmp;
+    auto add = [&](int k, const TcDesc& t) {
+      st[k].push_back(t);
+      flops += tc_flops(t);
+    };
+    for (size_t i = g.first; i < g.second; ++i) {
+      const RJob& j = rj[jid[i]];
+      const int c = req[i].c;
+      const Dims& q = dm[i];
+      const int64_t h = j.Dl[c + 1];
+      auto get = [&](int64_t n) {
+        void* p = scr.get(esz * n);
+        tmp.push_back(p);
+        return p;
+      };
+      TV L = envv(j, j.L[c], c, "xlma", cdt);
+      TV T1 = dense(j.T->tc[c], cdt, "auve", {q.a, q.Du, q.Du, q.e});
+      TV B1 = dense(j.B->tc[c], cdt, "xdgy", {q.x, q.Dd, q.Dd, q.y});
+      TV T2 = dense(j.T->tc[c + 1], cdt, "eUVf", {q.e, q.U, q.U, q.f});
+      TV B2 = dense(j.B->tc[c + 1], cdt, "yDGz", {q.y, q.D, q.D, q.z});
+      TV R = envv(j, j.R[c + 2], c + 2, "zRSf", cdt);
+      TV G = dense(gate[i], cdt, "pPqQ", {q.d, q.d, q.d, q.d});
+      TV x1 = dense(get(q.x * q.Dl * q.Du * q.Dl * q.Du * q.e), cdt, "xlumve", {q.x, q.Dl, q.Du, q.Dl, q.Du, q.e});
+      TV X = dense(get(q.Dl * q.Du * q.Dd * q.Dl * q.Du * q.Dd * q.y * q.e), cdt, "ludmvgye",
+                   {q.Dl, q.Du, q.Dd, q.Dl, q.Du, q.Dd, q.y, q.e});
+      TV z1 = dense(get(q.z * q.R * q.R * q.e * q.U * q.U), cdt, "zRSeUV", {q.z, q.R, q.R, q.e, q.U, q.U});
+      TV Z = dense(get(q.R * q.R * q.e * q.U * q.U * q.y * q.D * q.D), cdt, "RSeUVyDG",
+                   {q.R, q.R, q.e, q.U, q.U, q.y, q.D, q.D});
+      TV aa = dense(get(q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D), cdt, "qQludURD",
+                    {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
+      TV th = dense(get(q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D), cdt, "pPludURD",
+                    {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
+      TV W = dense(get(q.R * q.e * q.U * q.y * q.D * q.d * q.d * q.Dl * q.Du * q.Dd), cdt, "SeVyGpPlud",
+                   {q.R, q.e, q.U, q.y, q.D, q.d, q.d, q.Dl, q.Du, q.Dd});
+      TV E = dense(get(q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D), cdt, "pPmvgVSG",
+                   {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
+      const Site& s1 = *j.s[c];
+      const Site& s2 = *j.s[c + 1];
+      add(0, tc_build(x1, L, T1));
+      add(0, tc_build(z1, R, T2));
+      add(0, tc_build(aa, site_tv(s1, OP_ID, false, cdt, "qlurd"), site_tv(s2, OP_ID, false, cdt, "QrURD")));
+      add(1, tc_build(X, x1, B1));
+      add(1, tc_build(Z, z1, B2));
+      add(1, tc_build(th, G, aa));
+      add(2, tc_build(W, Z, th));
+      add(3, tc_build(E, X, W));
+      if (rawl[i])
+        add(4, tc_build(dense(rawl[i], cdt, "pmvsg", {q.d, q.Dl, q.Du, h, q.Dd}), E,
+                        site_tv(s2, OP_ID, false, cdt, "PsVSG")));
+      if (rawr[i])
+        add(4, tc_build(dense(rawr[i], cdt, "PsVSG", {q.d, h, q.U, q.R, q.D}), E,
+                        site_tv(s1, OP_ID, false, cdt, "pmvsg")));
+    }
+    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
+    for (void* p : tmp) scr.put(p);
+    rec.flush(call);
+  }
+  // <L[k], R[k]> at k = c+1, c+2 (once per job and column)
+  {
+    std::vector<RedDesc> rd;
+    std::vector<std::vector<char>> done(rj.size());
+    for (size_t k = 0; k < rj.size(); ++k) done[k].assign(rj[k].Lc + 1, 0);
+    for (size_t i = 0; i < req.size(); ++i) {
+      const RJob& j = rj[jid[i]];
+      for (int k = req[i].c + 1; k <= req[i].c + 2; ++k) {
+        if (done[jid[i]][k]) continue;
+        done[jid[i]][k] = 1;
+        rd.push_back(red_desc(j.L[k], j.R[k], env_elems(j, k), j.dots + k, cdt));
+      }
+    }
+    rec.reduce(rd);
+  }
+  rec.run(call);
+
+  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
+  for (size_t k = 0; k < rj.size(); ++k) {
+    const int Lc = rj[k].Lc;
+    hd[k].resize(Lc + 1);
+    hl[k].resize(Lc + 1);
+    hr[k].resize(Lc + 1);
+    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
+  }
+  dev::sync(ctx.stream);
+  // b_left / (sqrt(nuR[c+1]) |w_c|), b_right / (sqrt(nuL[c+1]) |w_c+1|), with
+  // w_k = sqrt(nuL[k+1]) <L[k+1], R[k+1]> (= sum_p A N A of site k): the
+  // scaling of the sites' norm environments
+  double* s2 = (double*)call.alloc(sizeof(double) * 2 * req.size());
+  std::vector<EwDesc> fill, scale;
+  for (size_t i = 0; i < req.size(); ++i) {
+    const size_t k = jid[i];
+    const int c = req[i].c;
+    const double w0 = std::sqrt(hl[k][c + 1]) * hd[k][c + 1], w1 = std::sqrt(hl[k][c + 2]) * hd[k][c + 2];
+    const double sl = std::sqrt(hr[k][c + 1]) * std::fabs(w0), sr = std::sqrt(hl[k][c + 1]) * std::fabs(w1);
+    if (!(std::isfinite(sl) && sl > 0.0 && std::isfinite(sr) && sr > 0.0))
+      throw Error(ST_NONFINITE, "bond environment (" + std::to_string(req[i].r) + "," + std::to_string(c) +
+                                    ") has a zero or non-finite scale");
+    const Dims& q = dm[i];
+    const int64_t h = rj[k].Dl[c + 1];
+    for (int side = 0; side < 2; ++side) {
+      void* raw = side == 0 ? rawl[i] : rawr[i];
+      if (!raw) continue;
+      EwDesc f = ew_desc(EW_FILL, nullptr, DT_F64, s2 + 2 * i + side, DT_F64, 1);
+      f.a = side == 0 ? sl * sl : sr * sr;
+      fill.push_back(f);
+      const int64_t n = side == 0 ? q.d * q.Dl * q.Du * h * q.Dd : q.d * h * q.U * q.R * q.D;
+      EwDesc e = ew_desc(EW_RSQRT, raw, cdt, side == 0 ? req[i].bl : req[i].br, DT_F64, n);
+      e.sptr = s2 + 2 * i + side;
+      scale.push_back(e);
+    }
+  }
+  Rec rec2(&ctx, &call);
+  rec2.ew(fill);
+  rec2.ew(scale);
+  rec2.run(call);
+  dev::sync(ctx.stream);
+}
+
+}  // namespace pe

@@ -44,4 +44,17 @@ struct SiteReq {
 void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log_z, std::vector<double>& sign,
                    double& flops);
 
+// Right-hand sides b of the ALS update of the horizontal bond (r,c)-(r,c+1)
+// under a two-site gate (one batched run): b of either site (device float64
+// [p][l][u][r][d], may be null) in the scaling of that site's norm
+// environment; algorithmic flops on the host.
+struct BondReq {
+  peps_env* e;
+  int r, c;
+  const double* gate;   // device, d^2 x d^2 float64
+  double* bl;
+  double* br;
+};
+void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops);
+
 }  // namespace pe

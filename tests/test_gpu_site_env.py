@@ -1,6 +1,7 @@
-"""Norm environments N_l of single sites on the GPU (through the C ABI)
-against the FP64 oracle: whole lattices, cluster windows, batching, the full
-8x8 D=4 chi=32 workload and the FP32 form."""
+"""Norm environments N_l of single sites and right-hand sides b_l of gated
+bonds (the two sides of the ALS tensor update) on the GPU, through the C
+ABI, against the FP64 oracle: whole lattices, cluster windows, batching, the
+full 8x8 D=4 chi=32 workload and the FP32 form."""
 import sys
 
 import numpy as np
@@ -175,3 +176,146 @@ def test_site_env_with_column_environment_and_fp32_columns(sess):
     ref = api.expect(ref_env, columns=api.env_columns(A, 4, 4))
     for k in ("sz", "bond_h", "bond_v"):
         assert np.abs(r[k] - ref[k]).max() < 1e-5
+
+
+# --- right-hand sides b_l of a gated horizontal bond -------------------------
+
+def _gate(seed):
+    return np.random.default_rng(seed).standard_normal((2, 2, 2, 2))
+
+
+def _heisenberg_gate(tau):
+    """exp(-tau S.S) on two spins 1/2, G[p, P, q, Q]."""
+    from oracle import spin
+    h = sum(w * np.kron(a, b) for w, a, b in spin.BOND_TERMS)
+    ev, U = np.linalg.eigh(h)
+    return (U @ np.diag(np.exp(-tau * ev)) @ U.T).reshape(2, 2, 2, 2)
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def check_b(got, ref, tol):
+    for g, r in zip(got, ref):
+        g = g.cpu().numpy()
+        assert g.shape == r.shape
+        assert np.abs(g - r).max() <= tol * max(1.0, np.abs(r).max())
+
+
+@pytest.mark.parametrize("case", [
+    ("normal_unit", 3, 4, 4096, 4),   # lossless chi
+    ("normal_unit", 4, 4, 3, 4),
+    ("aniso", 3, 4, 5, 3),
+    ("uniform", 1, 4, 4, 2),
+])
+def test_bond_env_parity_every_bond(sess, case):
+    dist, Lr, Lc, chi, H = case
+    say(f"bond environments {case}")
+    if dist == "aniso":
+        rng = np.random.default_rng(360)
+        A = [[rng.standard_normal((2, 1 if c == 0 else 2, 1 if r == 0 else 3, 1 if c == Lc - 1 else 2,
+                                   1 if r == Lr - 1 else 3)) for c in range(Lc)] for r in range(Lr)]
+    else:
+        A = make_peps(Lr, Lc, 2, dist, 361 + Lr * Lc)
+    G = _gate(Lr * Lc)
+    env = sess.env_boundary([binding.to_device(A)], chi, "f64", H)[0]
+    g = _dev(G)
+    bonds = [(r, c) for r in range(Lr) for c in range(Lc - 1)]
+    got, fl = sess.bond_env([(env, r, c, g) for r, c in bonds])
+    env.free()
+    ref_env = api.env_boundary(A, chi, H)
+    for (r, c), b in zip(bonds, got):
+        check_b(b, api.bond_env(ref_env, r, c, G), TOL64)
+    assert fl > 0
+
+
+def test_bond_env_identity_gate_matches_site_env(sess):
+    """GPU against GPU: for the identity gate b = A N with N from
+    peps_site_env, at truncated chi; a Heisenberg imaginary-time gate
+    against the oracle."""
+    say("bond environments: identity and Heisenberg gates")
+    A = make_peps(5, 5, 3, "near_product", 371)
+    env = sess.env_boundary([binding.to_device(A)], 6, "f64", 4)[0]
+    eye = _dev(np.eye(4).reshape(2, 2, 2, 2))
+    bonds = [(0, 0), (2, 1), (4, 3)]
+    got, _ = sess.bond_env([(env, r, c, eye) for r, c in bonds])
+    sites, _ = sess.site_env([(env, r, c + k) for r, c in bonds for k in (0, 1)])
+    for i, (r, c) in enumerate(bonds):
+        for k in (0, 1):
+            N = sites[2 * i + k][0].cpu().numpy()
+            a = A[r][c + k].reshape(2, -1)
+            assert np.abs(got[i][k].cpu().numpy() - a @ N).max() < 1e-12 * np.abs(a @ N).max()
+    Gh = _heisenberg_gate(0.05)
+    got, _ = sess.bond_env([(env, r, c, _dev(Gh)) for r, c in bonds])
+    env.free()
+    ref_env = api.env_boundary(A, 6, 4)
+    for (r, c), b in zip(bonds, got):
+        check_b(b, api.bond_env(ref_env, r, c, Gh), TOL64)
+
+
+def test_bond_env_of_cluster_window(sess):
+    """Bonds inside n = 3 windows (cut legs closed by CU_0)."""
+    say("bond environments of n=3 windows")
+    L, n, chi = 5, 3, 4
+    A = make_peps(L, L, 2, "near_product", 381)
+    sample = [(2, 2), (0, 1)]
+    wins = []
+    for (i, j) in sample:
+        r0, r1 = cluster.window_bounds(i, n, L)
+        c0, c1 = cluster.window_bounds(j, n, L)
+        wins.append((0, r0, r1, c0, c1, i, j))
+    envs = sess.cluster_env([binding.to_device(A)], wins, chi, "f64", 4)
+    G = _gate(5)
+    got, _ = sess.bond_env([(e, w[5] - w[1], w[6] - w[3], _dev(G)) for e, w in zip(envs, wins)])
+    for e in envs:
+        e.free()
+    sep = cluster.SeparableEnv(whole_lattice(A))
+    for w, b in zip(wins, got):
+        _, r0, r1, c0, c1, i, j = w
+        wenv = api.env_boundary(cluster.window_lattice(sep, r0, r1, c0, c1), chi, 4)
+        check_b(b, api.bond_env(wenv, i - r0, j - c0, G), TOL64)
+
+
+def test_bond_env_8x8_D4_chi32_sample(sess):
+    """8x8, D=4, near-product, chi=32: every horizontal bond in one batched
+    call, a sample against the oracle."""
+    say("bond environments 8x8 D=4 chi=32")
+    c = WORKLOADS["8x8_D4_chi32"]
+    A = workload_peps("8x8_D4_chi32")
+    env = sess.env_boundary([binding.to_device(A)], c["chi"], "f64", 4)[0]
+    G = _heisenberg_gate(0.02)
+    g = _dev(G)
+    bonds = [(r, s) for r in range(8) for s in range(7)]
+    got, _ = sess.bond_env([(env, r, s, g) for r, s in bonds])
+    env.free()
+    ref_env = api.env_boundary(A, c["chi"], 4)
+    for k in (0, 6, 24, 55):
+        r, s = bonds[k]
+        check_b(got[k], api.bond_env(ref_env, r, s, G), TOL64)
+
+
+def test_bond_env_fp32_form(sess):
+    say("bond environments fp32")
+    A = make_peps(4, 4, 3, "normal_unit", 391)
+    G = _gate(7)
+    env = sess.env_boundary([binding.to_device(A)], 9, "f32", 4)[0]
+    got, _ = sess.bond_env([(env, 1, 1, _dev(G)), (env, 3, 2, _dev(G))])
+    env.free()
+    ref_env = api.env_boundary(A, 9, 4)
+    check_b(got[0], api.bond_env(ref_env, 1, 1, G), 1e-4)
+    check_b(got[1], api.bond_env(ref_env, 3, 2, G), 1e-4)
+
+
+def test_bond_env_rejects_bad_requests(sess):
+    A = make_peps(3, 3, 2, "uniform", 5)
+    env = sess.env_boundary([binding.to_device(A)], 4)[0]
+    g = _dev(np.eye(4))
+    with pytest.raises(binding.PepsError):   # bond leaves the lattice
+        sess.ctx.bond_env_raw([(env, 0, 2, g.data_ptr(), 1 << 20, 0)])
+    with pytest.raises(binding.PepsError):   # no output
+        sess.ctx.bond_env_raw([(env, 0, 0, g.data_ptr(), 0, 0)])
+    with pytest.raises(binding.PepsError):   # no gate
+        sess.ctx.bond_env_raw([(env, 0, 0, 0, 1 << 20, 0)])
+    env.free()
