@@ -177,7 +177,55 @@ def side_instances(sess, binding, torch):
     return out
 
 
-SIDE = {"precision": side_precision, "clusters": side_clusters, "instances": side_instances}
+def side_convergence(sess, binding, torch):
+    """Convergence on synthetic states (the analogue of the paper's boundary
+    and cluster studies, Sec. 6): 8x8, D=4, near-product and N(0,1)
+    unit-norm sites.  Energy error of the full environment against chi (two-
+    row and column sandwiches), and of n x n cluster windows against n, both
+    relative to the full environment at chi = 128."""
+    from paper_1311_6696_amd.inputs import make_peps
+    L, D = 8, 4
+    out = {}
+    for dist, seed in (("near_product", 1002), ("normal_unit", 1003)):
+        st = binding.to_device(make_peps(L, L, D, dist, seed))
+        note(f"convergence {dist}: reference chi=128")
+        ref = sess.expect(sess.env_boundary([st], 128, "f64", 4))[0]
+        e_ref = energy(ref)
+        rows = {}
+        for chi in (4, 8, 16, 32, 64):
+            for cols in (False, True):
+                envs = sess.env_boundary([st], chi, "f64", 4, columns=cols)
+                r = sess.expect(envs)[0]
+                for e in envs:
+                    e.free()
+                rows[f"chi{chi}" + ("_columns" if cols else "")] = {
+                    "rel_energy_err": abs(energy(r) - e_ref) / abs(e_ref),
+                    "max_bond_err": float(max(np.max(np.abs(r["bond_h"] - ref["bond_h"])),
+                                              np.max(np.abs(r["bond_v"] - ref["bond_v"])))),
+                    "log_norm_err": abs(r["log_norm"] - ref["log_norm"])}
+        clusters = {}
+        for n in (2, 3, 4, 6, 8):
+            note(f"convergence {dist}: clusters n={n}")
+            wins = []
+            for i in range(L):
+                for j in range(L):
+                    r0, r1 = max(0, i - (n + 1) // 2 + 1), min(L - 1, i + n // 2)
+                    c0, c1 = max(0, j - (n + 1) // 2 + 1), min(L - 1, j + n // 2)
+                    wins.append((0, r0, r1, c0, c1, i, j))
+            envs = sess.cluster_env([st], wins, 32, "f64", 4)
+            res = sess.expect(envs)
+            for e in envs:
+                e.free()
+            e_cl = float(sum(np.nansum([r["right"], r["down"]]) for r in res))
+            clusters[f"n{n}"] = {"rel_energy_err": abs(e_cl - e_ref) / abs(e_ref)}
+        out[dist] = {"energy_ref": e_ref, "environment_vs_chi": rows, "clusters_chi32_vs_n": clusters}
+    out["workload"] = ("8x8 OBC PEPS, d=2, D=4, near-product (seed 1002) and N(0,1) unit-norm (seed 1003) "
+                       "sites, 4 ALS half-sweeps; reference: full environment at chi=128")
+    return out
+
+
+SIDE = {"precision": side_precision, "clusters": side_clusters, "instances": side_instances,
+        "convergence": side_convergence}
 
 
 def main():
@@ -196,7 +244,8 @@ def main():
                     help="lattices per call of the batched side measurement (1 = skip)")
     ap.add_argument("--workloads", default="",
                     help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
-                         "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices)")
+                         "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices), "
+                         "convergence (energy error against chi and cluster size n)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the contraction launch shapes on one untimed environment first")
     ap.add_argument("--graphs", action="store_true",
