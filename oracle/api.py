@@ -128,6 +128,17 @@ def bond_env(env, r, c, G):
     return bond_gate_environment(T, lat.A[r], B, lat.lam[r], lat.rho[r], c, G)
 
 
+def boundary_fidelity(env_a, env_b, side, k):
+    """Fidelity of two environments' boundaries of one lattice after k
+    absorbed rows: side 0 from the top (T(k-1)), side 1 from the bottom
+    (B(Lr-k))."""
+    from .boundary import boundary_fidelity as fid
+    Lr = env_a.lat.rows
+    X = env_a.T(k - 1)[0] if side == 0 else env_a.B(Lr - k)[0]
+    Y = env_b.T(k - 1)[0] if side == 0 else env_b.B(Lr - k)[0]
+    return fid(X, Y)
+
+
 def energy(res):
     """Total Heisenberg energy sum of bond terms (eq. HeisenbergH)."""
     return float(np.nansum(res["bond_h"]) + np.nansum(res["bond_v"]))

@@ -245,6 +245,21 @@ def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row):
     return X, 0.5 * np.log(omegas[-1]), AbsorbInfo(False, omegas, list(caps))
 
 
+def mps_overlap(X, Y):
+    """<X|Y> of two boundaries of one lattice row, each tensor [a, k, b, a']
+    with (k, b) taken as one physical index: the trace tr(X^T Y) of the two
+    boundary MPOs (Sec. 6 measures boundary fidelity with it)."""
+    E = np.ones((1, 1))
+    for x, y in zip(X, Y):
+        E = np.einsum("xy,xkbz,ykbw->zw", E, x, y, **EIN)
+    return float(E[0, 0])
+
+
+def boundary_fidelity(X, Y):
+    """|<X|Y>| / sqrt(<X|X> <Y|Y>)."""
+    return abs(mps_overlap(X, Y)) / np.sqrt(mps_overlap(X, X) * mps_overlap(Y, Y))
+
+
 def trivial_boundary(closing_list):
     """The bond-1 product MPS made of the closing matrices of one side."""
     return [np.asarray(s, dtype=np.float64).reshape(1, s.shape[0], s.shape[1], 1)

@@ -439,6 +439,42 @@ def test_bond_env_identity_gate_is_N_times_A():
             assert np.abs(b - a @ Nm).max() < 1e-12 * np.abs(b).max()
 
 
+# --- boundary fidelity ---------------------------------------------------------
+
+def _dense_mps(T):
+    x = T[0]
+    for t in T[1:]:
+        x = np.tensordot(x, t, axes=([-1], [0]))
+    return x.reshape(-1)
+
+
+def test_boundary_overlap_is_dense_inner_product_and_unit_norm():
+    """The overlap chain equals the inner product of the fully contracted
+    boundaries, and every stored boundary has unit norm."""
+    A = make_peps(4, 4, 2, "normal_unit", 95)
+    e1, e2 = api.env_boundary(A, 6, seed=5), api.env_boundary(A, 3, seed=6)
+    for k in range(1, 4):
+        X, Y = e1.T(k - 1)[0], e2.T(k - 1)[0]
+        assert abs(boundary.mps_overlap(X, Y) - _dense_mps(X) @ _dense_mps(Y)) < 1e-13
+        assert abs(boundary.mps_overlap(X, X) - 1.0) < 1e-13
+        X, Y = e1.B(4 - k)[0], e2.B(4 - k)[0]
+        assert abs(boundary.mps_overlap(X, Y) - _dense_mps(X) @ _dense_mps(Y)) < 1e-13
+
+
+def test_boundary_fidelity_one_at_lossless_chi_below_one_truncated():
+    """Lossless chi from two different ALS starts: the same boundary in
+    another gauge, f = 1; truncated boundaries have f < 1, closer to 1 at
+    larger chi."""
+    A = make_peps(5, 5, 2, "normal_unit", 97)
+    e1, e2 = api.env_boundary(A, 1024, seed=1), api.env_boundary(A, 1024, seed=2)
+    for side in (0, 1):
+        for k in range(1, 5):
+            assert abs(1.0 - api.boundary_fidelity(e1, e2, side, k)) < 1e-12
+    worst = [max(1.0 - api.boundary_fidelity(e1, api.env_boundary(A, chi), 0, k) for k in range(1, 5))
+             for chi in (2, 4, 8)]
+    assert worst[0] > worst[1] > worst[2] > 0.0
+
+
 # --- P12/P13 ------------------------------------------------------------------
 
 def test_bounds_at_exact_chi():
