@@ -181,24 +181,32 @@ def side_convergence(sess, binding, torch):
     """Convergence on synthetic states (the analogue of the paper's boundary
     and cluster studies, Sec. 6): 8x8, D=4, near-product and N(0,1)
     unit-norm sites.  Energy error of the full environment against chi (two-
-    row and column sandwiches), and of n x n cluster windows against n, both
-    relative to the full environment at chi = 128."""
+    row and column sandwiches) with the boundary infidelity 1 - f of every
+    row's boundaries, and of n x n cluster windows against n, all relative
+    to the full environment at chi = 128."""
     from paper_1311_6696_amd.inputs import make_peps
     L, D = 8, 4
     out = {}
     for dist, seed in (("near_product", 1002), ("normal_unit", 1003)):
         st = binding.to_device(make_peps(L, L, D, dist, seed))
         note(f"convergence {dist}: reference chi=128")
-        ref = sess.expect(sess.env_boundary([st], 128, "f64", 4))[0]
+        ref_env = sess.env_boundary([st], 128, "f64", 4)[0]
+        ref = sess.expect([ref_env])[0]
         e_ref = energy(ref)
         rows = {}
         for chi in (4, 8, 16, 32, 64):
             for cols in (False, True):
                 envs = sess.env_boundary([st], chi, "f64", 4, columns=cols)
                 r = sess.expect(envs)[0]
+                fid = {}
+                if not cols:
+                    # boundary fidelity against the chi = 128 boundaries, every row from both sides
+                    ov = sess.ctx.boundary_overlap([(envs[0], ref_env, s, k) for s in (0, 1) for k in range(1, L)])
+                    inf = [1.0 - abs(xy) / np.sqrt(xx * yy) for xy, xx, yy in ov]
+                    fid = {"max_boundary_infidelity": float(max(inf)), "mean_boundary_infidelity": float(np.mean(inf))}
                 for e in envs:
                     e.free()
-                rows[f"chi{chi}" + ("_columns" if cols else "")] = {
+                rows[f"chi{chi}" + ("_columns" if cols else "")] = {**fid,
                     "rel_energy_err": abs(energy(r) - e_ref) / abs(e_ref),
                     "max_bond_err": float(max(np.max(np.abs(r["bond_h"] - ref["bond_h"])),
                                               np.max(np.abs(r["bond_v"] - ref["bond_v"])))),
@@ -218,6 +226,7 @@ def side_convergence(sess, binding, torch):
                 e.free()
             e_cl = float(sum(np.nansum([r["right"], r["down"]]) for r in res))
             clusters[f"n{n}"] = {"rel_energy_err": abs(e_cl - e_ref) / abs(e_ref)}
+        ref_env.free()
         out[dist] = {"energy_ref": e_ref, "environment_vs_chi": rows, "clusters_chi32_vs_n": clusters}
     out["workload"] = ("8x8 OBC PEPS, d=2, D=4, near-product (seed 1002) and N(0,1) unit-norm (seed 1003) "
                        "sites, 4 ALS half-sweeps; reference: full environment at chi=128")

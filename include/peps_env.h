@@ -189,6 +189,21 @@ typedef struct {
 } peps_bond_req;
 peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req, double* flops);
 
+/* Overlaps of stored boundaries, for the boundary fidelity of Sec. 6
+ * (f = |tr(X^T Y)| of boundary MPOs scaled to tr(X^T X) = 1): per request
+ * the boundaries of env_a and env_b (environments of one lattice, any chi
+ * and precision; their float64 tensors are used) after k absorbed rows,
+ * side 0 from the top, 1 from the bottom, 2 from the left and 3 from the
+ * right (2 and 3 need PEPS_OPTS_COLUMNS), 1 <= k < number of rows (columns
+ * for sides 2, 3).  Outputs <X|Y>, <X|X>, <Y|Y>; one batched run. */
+typedef struct {
+  peps_env* env_a;
+  peps_env* env_b;
+  int32_t side, k;
+  double xy, xx, yy;   /* out */
+} peps_overlap_req;
+peps_status peps_boundary_overlap(peps_ctx* ctx, peps_overlap_req* req, int32_t n_req);
+
 /* Thin QR of n_blocks float64 blocks, the gauge step of the truncation
  * (Sec. 2: the ALS sweep keeps every tensor but the centre isometric):
  * A = Q R with A m x n (m >= n >= 1, n <= 1024), Q m x n with orthonormal

@@ -73,6 +73,11 @@ class BondReq(C.Structure):
                 ("b_left", C.c_void_p), ("b_right", C.c_void_p)]
 
 
+class OverlapReq(C.Structure):
+    _fields_ = [("env_a", C.c_void_p), ("env_b", C.c_void_p), ("side", C.c_int32), ("k", C.c_int32),
+                ("xy", C.c_double), ("xx", C.c_double), ("yy", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("log_norm", C.c_double), ("norm_sign", C.c_double), ("sz", C.POINTER(C.c_double)),
                 ("bond", C.POINTER(C.c_double)), ("flops", C.c_double)]
@@ -81,7 +86,7 @@ class Result(C.Structure):
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
            "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
-           "peps_bond_env", "peps_last_error")
+           "peps_bond_env", "peps_boundary_overlap", "peps_last_error")
 
 _lib = None
 
@@ -114,11 +119,13 @@ def load(path=None):
     lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
     lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
     lib.peps_bond_env.argtypes = [vp, C.POINTER(BondReq), i32, C.POINTER(C.c_double)]
+    lib.peps_boundary_overlap.argtypes = [vp, C.POINTER(OverlapReq), i32]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
-                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env", "peps_bond_env"):
+                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env", "peps_bond_env",
+                 "peps_boundary_overlap"):
         getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -304,6 +311,14 @@ class Context:
         fl = C.c_double()
         _check(self.lib, self.lib.peps_bond_env(self.handle, arr, len(reqs), C.byref(fl)))
         return fl.value
+
+    def boundary_overlap(self, reqs):
+        """reqs: sequence of (env_a, env_b, side, k).  Returns [(xy, xx, yy)];
+        the boundary fidelity is |xy| / sqrt(xx * yy)."""
+        arr = (OverlapReq * len(reqs))(*[OverlapReq(a.handle, b.handle, int(s), int(k), 0.0, 0.0, 0.0)
+                                         for a, b, s, k in reqs])
+        _check(self.lib, self.lib.peps_boundary_overlap(self.handle, arr, len(reqs)))
+        return [(arr[i].xy, arr[i].xx, arr[i].yy) for i in range(len(reqs))]
 
     def qr_raw(self, blocks):
         """blocks: sequence of (a, a_rs, a_cs, q, q_rs, q_cs, r, r_rs, r_cs, m, n)

@@ -309,6 +309,41 @@ peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req
   });
 }
 
+peps_status peps_boundary_overlap(peps_ctx* ctx, peps_overlap_req* req, int32_t n_req) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && req, "ctx and req must not be NULL");
+    PE_REQUIRE(n_req >= 1, "n_req must be >= 1");
+    std::vector<OvReq> rs;
+    for (int i = 0; i < n_req; ++i) {
+      const peps_overlap_req& q = req[i];
+      const std::string w = "request " + std::to_string(i) + ": ";
+      PE_REQUIRE(q.env_a && q.env_b, w + "environments must not be NULL");
+      PE_REQUIRE(q.env_a->ctx == ctx->c.get() && q.env_b->ctx == ctx->c.get(), w + "environment of another context");
+      PE_REQUIRE(q.side >= 0 && q.side <= 3, w + "side must be 0..3");
+      const Mps* m[2];
+      for (int t = 0; t < 2; ++t) {
+        peps_env* e = t == 0 ? q.env_a : q.env_b;
+        if (q.side >= 2) {
+          PE_REQUIRE(e->col != nullptr, w + "sides 2 and 3 need an environment built with PEPS_OPTS_COLUMNS");
+          e = e->col.get();
+        }
+        const std::vector<Mps>& v = (q.side & 1) == 0 ? e->top : e->bot;
+        PE_REQUIRE(q.k >= 1 && q.k < (int)v.size(), w + "k must be in [1, rows)");
+        m[t] = &v[q.k];
+      }
+      PE_REQUIRE(m[0]->leg == m[1]->leg, w + "boundaries of different lattices");
+      rs.push_back(OvReq{m[0], m[1], {0.0, 0.0, 0.0}});
+    }
+    dev::set_device(ctx->c->device);
+    plan_overlap(*ctx->c, rs);
+    for (int i = 0; i < n_req; ++i) {
+      req[i].xy = rs[i].out[0];
+      req[i].xx = rs[i].out[1];
+      req[i].yy = rs[i].out[2];
+    }
+  });
+}
+
 peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops) {
   return guarded([&] {
     PE_REQUIRE(ctx && req, "ctx and req must not be NULL");

@@ -939,3 +939,68 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
 }
 
 }  // namespace pe
+
+namespace pe {
+
+void plan_overlap(Ctx& ctx, std::vector<OvReq>& req) {
+  Arena call(&ctx.pool);
+  Rec rec(&ctx, &call);
+  // three chains per request: <X|Y>, <X|X>, <Y|Y>; E_{c+1}[z,w] = E_c[x,y] X_c[x,k,b,z] Y_c[y,k,b,w]
+  struct Chain {
+    const Mps* x;
+    const Mps* y;
+    double* e[2];
+    double* tmp;
+  };
+  std::vector<Chain> ch;
+  int maxLc = 0;
+  std::vector<EwDesc> init;
+  for (const OvReq& q : req)
+    for (int t = 0; t < 3; ++t) {
+      Chain c;
+      c.x = t == 2 ? q.y : q.x;
+      c.y = t == 1 ? q.x : q.y;
+      const int Lc = (int)c.x->leg.size();
+      maxLc = std::max(maxLc, Lc);
+      int64_t me = 1, mt = 1;
+      for (int k = 0; k <= Lc; ++k) me = std::max(me, (int64_t)c.x->bond[k] * c.y->bond[k]);
+      for (int k = 0; k < Lc; ++k)
+        mt = std::max(mt, (int64_t)c.y->bond[k] * c.x->leg[k] * c.x->leg[k] * c.x->bond[k + 1]);
+      c.e[0] = (double*)call.alloc(sizeof(double) * me);
+      c.e[1] = (double*)call.alloc(sizeof(double) * me);
+      c.tmp = (double*)call.alloc(sizeof(double) * mt);
+      EwDesc f = ew_desc(EW_FILL, nullptr, DT_F64, c.e[0], DT_F64, 1);
+      f.a = 1.0;
+      init.push_back(f);
+      ch.push_back(c);
+    }
+  rec.ew(init);
+  for (int s = 0; s < maxLc; ++s) {
+    std::vector<TcDesc> st1, st2;
+    for (Chain& c : ch) {
+      if (s >= (int)c.x->leg.size()) continue;
+      const int64_t bx = c.x->bond[s], by = c.y->bond[s], bx1 = c.x->bond[s + 1], by1 = c.y->bond[s + 1];
+      const int64_t l = c.x->leg[s];
+      TV E = dense(c.e[s & 1], DT_F64, "xy", {bx, by});
+      TV X = dense(c.x->t64[s], DT_F64, "xkbz", {bx, l, l, bx1});
+      TV Y = dense(c.y->t64[s], DT_F64, "ykbw", {by, l, l, by1});
+      TV y1 = dense(c.tmp, DT_F64, "ykbz", {by, l, l, bx1});
+      st1.push_back(tc_build(y1, E, X));
+      st2.push_back(tc_build(dense(c.e[(s + 1) & 1], DT_F64, "zw", {bx1, by1}), y1, Y));
+    }
+    rec.tc(TP_F64, DT_F64, st1);
+    rec.tc(TP_F64, DT_F64, st2);
+    rec.flush(call);
+  }
+  rec.run(call);
+  for (size_t i = 0; i < req.size(); ++i)
+    for (int t = 0; t < 3; ++t) {
+      const Chain& c = ch[3 * i + t];
+      double v = 0.0;
+      dev::d2h(&v, c.e[c.x->leg.size() & 1], sizeof(double), ctx.stream);
+      dev::sync(ctx.stream);
+      req[i].out[t] = v;
+    }
+}
+
+}  // namespace pe

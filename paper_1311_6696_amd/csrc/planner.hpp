@@ -57,4 +57,13 @@ struct BondReq {
 };
 void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops);
 
+// <X|Y>, <X|X>, <Y|Y> of pairs of stored boundaries of one row (float64
+// tensors, (ket, bra) taken as one physical index), one batched run.
+struct OvReq {
+  const Mps* x;
+  const Mps* y;
+  double out[3];
+};
+void plan_overlap(Ctx& ctx, std::vector<OvReq>& req);
+
 }  // namespace pe

@@ -205,6 +205,46 @@ def test_columns_rejected_for_clusters(sess):
     assert b"flags" in ctx.lib.peps_last_error()
 
 
+# --- boundary overlaps (boundary fidelity) -------------------------------------
+
+def test_boundary_overlap_parity(sess):
+    """<X|Y>, <X|X>, <Y|Y> of stored boundaries from all four sides, between
+    a lossless and a truncated environment (different seeds), against the
+    oracle; lossless boundaries from two seeds have fidelity 1."""
+    say("boundary overlaps")
+    A = make_peps(5, 4, 2, "normal_unit", 401)
+    dev = binding.to_device(A)
+    ea = sess.env_boundary([dev], 1024, "f64", 4, 1, columns=True)[0]
+    ea2 = sess.env_boundary([dev], 1024, "f64", 4, 2, columns=True)[0]
+    eb = sess.env_boundary([dev], 3, "f64", 4, 2, columns=True)[0]
+    reqs = [(ea, x, s, k) for x in (ea2, eb) for s in range(4) for k in range(1, 5 if s < 2 else 4)]
+    res = sess.ctx.boundary_overlap(reqs)
+    for e in (ea, ea2, eb):
+        e.free()
+    ref = {1024: (api.env_boundary(A, 1024, 4, 1), api.env_columns(A, 1024, 4, 1)),
+           3: (api.env_boundary(A, 3, 4, 2), api.env_columns(A, 3, 4, 2))}
+    for (a, x, s, k), (xy, xx, yy) in zip(reqs, res):
+        f = abs(xy) / np.sqrt(xx * yy)
+        if x is ea2:
+            assert abs(1.0 - f) < 1e-12
+            continue
+        ra, rb = (ref[1024][0], ref[3][0]) if s < 2 else (ref[1024][1], ref[3][1])
+        assert abs(f - api.boundary_fidelity(ra, rb, s % 2, k)) < TOL64
+        assert abs(xx - 1.0) < 1e-12 and abs(yy - 1.0) < 1e-12
+
+
+def test_boundary_overlap_rejects_bad_requests(sess):
+    A = make_peps(3, 3, 2, "uniform", 5)
+    e = sess.env_boundary([binding.to_device(A)], 4)[0]
+    with pytest.raises(binding.PepsError):   # no column boundaries
+        sess.ctx.boundary_overlap([(e, e, 2, 1)])
+    with pytest.raises(binding.PepsError):   # k out of range
+        sess.ctx.boundary_overlap([(e, e, 0, 3)])
+    with pytest.raises(binding.PepsError):   # closing boundary
+        sess.ctx.boundary_overlap([(e, e, 1, 0)])
+    e.free()
+
+
 @pytest.mark.parametrize("L,D,chi,dist,seed", [
     (4, 3, 72, "normal_unit", 61),   # 81 x 72 QR blocks: five columns per wave
     (4, 5, 30, "uniform", 52),       # 625 x 30 and 625 x 25 blocks: tree QR over row blocks
