@@ -139,6 +139,30 @@ def boundary_fidelity(env_a, env_b, side, k):
     return fid(X, Y)
 
 
+def _from_transposed(x, shape, matrix):
+    """A site quantity computed on the transposed lattice (legs l, u, r, d of
+    the transpose = u, l, d, r of the site) back in the site's own order."""
+    d, Dl, Du, Dr, Dd = shape
+    if matrix:
+        return x.reshape(Du, Dl, Dd, Dr, Du, Dl, Dd, Dr).transpose(1, 0, 3, 2, 5, 4, 7, 6).reshape(x.shape)
+    return x.reshape(d, Du, Dl, Dd, Dr).transpose(0, 2, 1, 4, 3).reshape(x.shape)
+
+
+def site_env_columns(columns, A, r, c):
+    """``site_env`` of site (r, c) from the column sandwich of column c
+    (``columns`` from ``env_columns``), in the site's own leg order."""
+    N, lz, sgn = site_env(columns, c, r)
+    return _from_transposed(N, A[r][c].shape, True), lz, sgn
+
+
+def bond_env_vertical(columns, A, r, c, G):
+    """``bond_env`` of the vertical bond (r, c)-(r+1, c) from the column
+    sandwich of column c: (b of (r, c), b of (r+1, c)), G's first index pair
+    on (r, c), each in the site's own leg order."""
+    bl, br = bond_env(columns, c, r, G)
+    return _from_transposed(bl, A[r][c].shape, False), _from_transposed(br, A[r + 1][c].shape, False)
+
+
 def energy(res):
     """Total Heisenberg energy sum of bond terms (eq. HeisenbergH)."""
     return float(np.nansum(res["bond_h"]) + np.nansum(res["bond_v"]))

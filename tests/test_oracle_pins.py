@@ -423,6 +423,41 @@ def test_bond_env_matches_brute_force(case):
                 assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+def test_vertical_bond_env_and_column_site_env_match_brute_force():
+    """Lossless chi: b of both sites of every vertical bond and N of every
+    site, both from the column sandwiches, equal brute force (anisotropic
+    bonds, so that a leg-order slip in the transposition fails)."""
+    Lr, Lc = 3, 3
+    A = _anisotropic_peps(Lr, Lc, 2, 3, 99)
+    G = np.random.default_rng(7).standard_normal((2, 2, 2, 2))
+    psi = exact.statevector(A)
+    Z = float(psi @ psi)
+    N = Lr * Lc
+    cols = api.env_columns(A, 4096)
+
+    def open_M(rr, cc):
+        K = int(np.prod(A[rr][cc].shape[1:]))
+        O = np.eye(K).reshape((K,) + A[rr][cc].shape[1:])
+        Bt = [[O if (x, y) == (rr, cc) else A[x][y] for y in range(Lc)] for x in range(Lr)]
+        return exact.statevector(Bt).reshape(2 ** (rr * Lc + cc), K, -1)
+
+    for r in range(Lr):
+        for c in range(Lc):
+            M = open_M(r, c)
+            Mm = M.transpose(0, 2, 1).reshape(-1, M.shape[1])
+            Nc, _, _ = api.site_env_columns(cols, A, r, c)
+            assert np.abs(Nc - Mm.T @ Mm / Z).max() <= 1e-12 * np.abs(Nc).max()
+    for r in range(Lr - 1):
+        for c in range(Lc):
+            i, j = r * Lc + c, (r + 1) * Lc + c
+            phi = _gate_applied(psi, N, i, j, G)
+            bl, br = api.bond_env_vertical(cols, A, r, c, G)
+            for site, b in ((i, bl), (j, br)):
+                M = open_M(*divmod(site, Lc))
+                ref = np.einsum("akb,apb->pk", M, phi.reshape(2 ** site, 2, -1)) / Z
+                assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_bond_env_identity_gate_is_N_times_A():
     """Truncated chi: for the identity gate b[p, k'] = sum_k A[p, k] N[k, k']
     for both sites (the scalings of the bond and site environments agree;
