@@ -154,13 +154,18 @@ void peps_env_free(peps_env* env);
  * log_z (out): log|<psi|psi>| as this row's sandwich estimates it, so the
  * unscaled environment is sign * exp(log_z) * N.  (r, c) are window
  * coordinates for a cluster environment (its cut legs closed by the CU_0
- * boundaries: the environment of the cluster update).  N is symmetric and
+ * boundaries: the environment of the cluster update).  dir 0 takes N from
+ * the row sandwich of row r; dir 1 (an environment built with
+ * PEPS_OPTS_COLUMNS) from the column sandwich of column c, the one that
+ * matches the vertical bonds of peps_bond_env; N is in the site's own leg
+ * order either way.  N is symmetric and
  * positive semidefinite at lossless chi; truncated boundaries need not be
  * symmetric under ket <-> bra.  All requests share one precision; *flops
  * (may be NULL) receives the algorithmic flops. */
 typedef struct {
   peps_env* env;
   int32_t r, c;
+  int32_t dir;    /* 0: row sandwich, 1: column sandwich */
   double* n;
   double log_z;   /* out */
   double sign;    /* out */
@@ -179,10 +184,15 @@ peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, doub
  * scaling of that site's peps_site_env matrix: for the identity gate
  * b[p][k'] = sum_k A[p][k] N[k][k'].  (At truncated chi the boundaries need
  * not be symmetric under ket <-> bra, so neither need N.)  All requests
- * share one precision; *flops (may be NULL) receives the algorithmic flops. */
+ * share one precision; *flops (may be NULL) receives the algorithmic flops.
+ * dir 1 (an environment built with PEPS_OPTS_COLUMNS): the vertical bond
+ * (r,c)-(r+1,c) from the column sandwich of column c, b_left for (r,c) and
+ * b_right for (r+1,c), G's first index pair on (r,c), b in each site's own
+ * leg order, scaled like peps_site_env with dir 1. */
 typedef struct {
   peps_env* env;
-  int32_t r, c;           /* bond (r,c)-(r,c+1), window coordinates for a cluster environment */
+  int32_t r, c;           /* bond (r,c)-(r,c+1) (dir 0) or (r,c)-(r+1,c) (dir 1); window coordinates for a window */
+  int32_t dir;
   const double* gate;
   double* b_left;
   double* b_right;

@@ -64,12 +64,12 @@ class QrBlock(C.Structure):
 
 
 class SiteReq(C.Structure):
-    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("n", C.c_void_p),
+    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("dir", C.c_int32), ("n", C.c_void_p),
                 ("log_z", C.c_double), ("sign", C.c_double)]
 
 
 class BondReq(C.Structure):
-    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("gate", C.c_void_p),
+    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("dir", C.c_int32), ("gate", C.c_void_p),
                 ("b_left", C.c_void_p), ("b_right", C.c_void_p)]
 
 
@@ -296,18 +296,19 @@ class Context:
         _check(self.lib, self.lib.peps_ctx_set_workspace(self.handle, int(nbytes)))
 
     def site_env_raw(self, reqs):
-        """reqs: sequence of (env, r, c, device address of K*K doubles).
+        """reqs: sequence of (env, r, c, device address of K*K doubles[, dir]).
         Returns ([(log_z, sign)], flops)."""
-        arr = (SiteReq * len(reqs))(*[SiteReq(e.handle, int(r), int(c), int(p), 0.0, 0.0) for e, r, c, p in reqs])
+        arr = (SiteReq * len(reqs))(*[SiteReq(q[0].handle, int(q[1]), int(q[2]), int(q[4]) if len(q) > 4 else 0,
+                                              int(q[3]), 0.0, 0.0) for q in reqs])
         fl = C.c_double()
         _check(self.lib, self.lib.peps_site_env(self.handle, arr, len(reqs), C.byref(fl)))
         return [(arr[i].log_z, arr[i].sign) for i in range(len(reqs))], fl.value
 
     def bond_env_raw(self, reqs):
-        """reqs: sequence of (env, r, c, gate, b_left, b_right) with device
-        addresses (0 for an output not wanted).  Returns the flops."""
-        arr = (BondReq * len(reqs))(*[BondReq(e.handle, int(r), int(c), int(g), int(bl) or None, int(br) or None)
-                                      for e, r, c, g, bl, br in reqs])
+        """reqs: sequence of (env, r, c, gate, b_left, b_right[, dir]) with
+        device addresses (0 for an output not wanted).  Returns the flops."""
+        arr = (BondReq * len(reqs))(*[BondReq(q[0].handle, int(q[1]), int(q[2]), int(q[6]) if len(q) > 6 else 0,
+                                              int(q[3]), int(q[4]) or None, int(q[5]) or None) for q in reqs])
         fl = C.c_double()
         _check(self.lib, self.lib.peps_bond_env(self.handle, arr, len(reqs), C.byref(fl)))
         return fl.value
@@ -370,28 +371,34 @@ class Session:
         return self.ctx.expect(envs)
 
     def site_env(self, reqs):
-        """reqs: sequence of (env, r, c).  Returns ([(N, log_z, sign)], flops)
-        with N a K x K float64 GPU tensor (ket legs (l, u, r, d) as rows)
-        scaled so that sum_p A N A = sign."""
+        """reqs: sequence of (env, r, c[, dir]).  Returns ([(N, log_z, sign)],
+        flops) with N a K x K float64 GPU tensor (ket legs (l, u, r, d) as
+        rows) scaled so that sum_p A N A = sign; dir 1 takes it from the
+        column sandwich."""
         torch = self.torch
-        outs = [torch.empty((e.site_dim(r, c),) * 2, dtype=torch.float64, device="cuda") for e, r, c in reqs]
-        res, fl = self.ctx.site_env_raw([(e, r, c, n.data_ptr()) for (e, r, c), n in zip(reqs, outs)])
+        outs = [torch.empty((q[0].site_dim(q[1], q[2]),) * 2, dtype=torch.float64, device="cuda") for q in reqs]
+        res, fl = self.ctx.site_env_raw([(q[0], q[1], q[2], n.data_ptr(), q[3] if len(q) > 3 else 0)
+                                         for q, n in zip(reqs, outs)])
         return [(n, lz, sg) for n, (lz, sg) in zip(outs, res)], fl
 
     def bond_env(self, reqs):
-        """reqs: sequence of (env, r, c, gate) with gate a (d, d, d, d)
-        float64 GPU tensor G[p, P, q, Q].  Returns ([(b_left, b_right)], flops),
-        each b a (d, K) float64 GPU tensor of that site."""
+        """reqs: sequence of (env, r, c, gate[, dir]) with gate a (d, d, d, d)
+        float64 GPU tensor G[p, P, q, Q]; dir 0 the bond (r,c)-(r,c+1), dir 1
+        the bond (r,c)-(r+1,c).  Returns ([(b_left, b_right)], flops), each b
+        a (d, K) float64 GPU tensor of that site."""
         torch = self.torch
         outs, raw = [], []
-        for e, r, c, g in reqs:
+        for q in reqs:
+            e, r, c, g = q[:4]
+            dr = q[4] if len(q) > 4 else 0
             if not g.is_cuda or g.dtype != torch.float64 or not g.is_contiguous():
                 raise ValueError("the gate must be a contiguous float64 GPU tensor")
             d = int(e.shapes[r][c][0])
+            r2, c2 = (r + 1, c) if dr == 1 else (r, c + 1)
             bl = torch.empty((d, e.site_dim(r, c)), dtype=torch.float64, device="cuda")
-            br = torch.empty((d, e.site_dim(r, c + 1)), dtype=torch.float64, device="cuda")
+            br = torch.empty((d, e.site_dim(r2, c2)), dtype=torch.float64, device="cuda")
             outs.append((bl, br))
-            raw.append((e, r, c, g.data_ptr(), bl.data_ptr(), br.data_ptr()))
+            raw.append((e, r, c, g.data_ptr(), bl.data_ptr(), br.data_ptr(), dr))
         fl = self.ctx.bond_env_raw(raw)
         return outs, fl
 

@@ -282,9 +282,18 @@ peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req
       PE_REQUIRE(q.env != nullptr && q.gate != nullptr, w + "env and gate must not be NULL");
       PE_REQUIRE(q.b_left != nullptr || q.b_right != nullptr, w + "no output requested");
       PE_REQUIRE(q.env->ctx == ctx->c.get(), w + "environment belongs to another context");
-      PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c + 1 < q.env->lat.Lc,
-                 w + "bond outside the lattice");
-      rs.push_back(BondReq{q.env, q.r, q.c, q.gate, q.b_left, q.b_right});
+      PE_REQUIRE(q.dir == 0 || q.dir == 1, w + "dir must be 0 or 1");
+      if (q.dir == 0) {
+        PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c + 1 < q.env->lat.Lc,
+                   w + "bond outside the lattice");
+        rs.push_back(BondReq{q.env, q.r, q.c, q.gate, q.b_left, q.b_right, false});
+      } else {
+        PE_REQUIRE(q.env->col != nullptr, w + "dir 1 needs an environment built with PEPS_OPTS_COLUMNS");
+        PE_REQUIRE(q.r >= 0 && q.r + 1 < q.env->lat.Lr && q.c >= 0 && q.c < q.env->lat.Lc,
+                   w + "bond outside the lattice");
+        // row c of the transposed lattice, bond (r, r+1) along it
+        rs.push_back(BondReq{q.env->col.get(), q.c, q.r, q.gate, q.b_left, q.b_right, true});
+      }
     }
     dev::set_device(ctx->c->device);
     std::vector<peps_env*> es;
@@ -355,7 +364,13 @@ peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, doub
       PE_REQUIRE(q.env != nullptr && q.n != nullptr, w + "env and n must not be NULL");
       PE_REQUIRE(q.env->ctx == ctx->c.get(), w + "environment belongs to another context");
       PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c < q.env->lat.Lc, w + "site outside the lattice");
-      rs.push_back(SiteReq{q.env, q.r, q.c, q.n});
+      PE_REQUIRE(q.dir == 0 || q.dir == 1, w + "dir must be 0 or 1");
+      if (q.dir == 0) {
+        rs.push_back(SiteReq{q.env, q.r, q.c, q.n, false});
+      } else {
+        PE_REQUIRE(q.env->col != nullptr, w + "dir 1 needs an environment built with PEPS_OPTS_COLUMNS");
+        rs.push_back(SiteReq{q.env->col.get(), q.c, q.r, q.n, true});   // column c of the lattice
+      }
     }
     dev::set_device(ctx->c->device);
     std::vector<peps_env*> es;

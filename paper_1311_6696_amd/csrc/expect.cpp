@@ -670,10 +670,16 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
       TV B = dense(j.B->tc[c], cdt, "xdgy", {d.x, d.Dd, d.Dd, d.y});
       TV R = envv(j, j.R[c + 1], c + 1, "yrse", cdt);
       // intermediate leg orders chosen so that every index group of each
-      // contraction merges into at most four strided sub-dimensions
-      TV y1 = dense(p, cdt, "xlumve", {d.x, d.Dl, d.Du, d.Dl, d.Du, d.e});
-      TV y2 = dense(q, cdt, "ludmvgye", {d.Dl, d.Du, d.Dd, d.Dl, d.Du, d.Dd, d.y, d.e});
-      TV n = dense(raw[i], cdt, "lurdmvsg", {d.Dl, d.Du, d.Dr, d.Dd, d.Dl, d.Du, d.Dr, d.Dd});
+      // contraction merges into at most four strided sub-dimensions; on a
+      // transposed lattice N is written in the original site's leg order
+      // (l, u, r, d) = (u, l, d, r) of the transpose
+      const bool tr = req[i].tr;
+      TV y1 = tr ? dense(p, cdt, "xulvme", {d.x, d.Du, d.Dl, d.Du, d.Dl, d.e})
+                 : dense(p, cdt, "xlumve", {d.x, d.Dl, d.Du, d.Dl, d.Du, d.e});
+      TV y2 = tr ? dense(q, cdt, "uldvmgye", {d.Du, d.Dl, d.Dd, d.Du, d.Dl, d.Dd, d.y, d.e})
+                 : dense(q, cdt, "ludmvgye", {d.Dl, d.Du, d.Dd, d.Dl, d.Du, d.Dd, d.y, d.e});
+      TV n = tr ? dense(raw[i], cdt, "uldrvmgs", {d.Du, d.Dl, d.Dd, d.Dr, d.Du, d.Dl, d.Dd, d.Dr})
+                : dense(raw[i], cdt, "lurdmvsg", {d.Dl, d.Du, d.Dr, d.Dd, d.Dl, d.Du, d.Dr, d.Dd});
       s1.push_back(tc_build(y1, L, T));
       s2.push_back(tc_build(y2, y1, B));
       s3.push_back(tc_build(n, y2, R));
@@ -865,12 +871,17 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
       add(1, tc_build(th, G, aa));
       add(2, tc_build(W, Z, th));
       add(3, tc_build(E, X, W));
+      // on a transposed lattice b is written in the original site's leg
+      // order (l, u, r, d) = (u, l, d, r) of the transpose
+      const bool tr = req[i].tr;
       if (rawl[i])
-        add(4, tc_build(dense(rawl[i], cdt, "pmvsg", {q.d, q.Dl, q.Du, h, q.Dd}), E,
-                        site_tv(s2, OP_ID, false, cdt, "PsVSG")));
+        add(4, tc_build(tr ? dense(rawl[i], cdt, "pvmgs", {q.d, q.Du, q.Dl, q.Dd, h})
+                           : dense(rawl[i], cdt, "pmvsg", {q.d, q.Dl, q.Du, h, q.Dd}),
+                        E, site_tv(s2, OP_ID, false, cdt, "PsVSG")));
       if (rawr[i])
-        add(4, tc_build(dense(rawr[i], cdt, "PsVSG", {q.d, h, q.U, q.R, q.D}), E,
-                        site_tv(s1, OP_ID, false, cdt, "pmvsg")));
+        add(4, tc_build(tr ? dense(rawr[i], cdt, "PVsGS", {q.d, q.U, h, q.D, q.R})
+                           : dense(rawr[i], cdt, "PsVSG", {q.d, h, q.U, q.R, q.D}),
+                        E, site_tv(s1, OP_ID, false, cdt, "pmvsg")));
     }
     for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
     for (void* p : tmp) scr.put(p);

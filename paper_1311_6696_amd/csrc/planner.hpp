@@ -40,6 +40,7 @@ struct SiteReq {
   peps_env* e;
   int r, c;
   double* out;
+  bool tr = false;   // e is a transposed lattice: write N in the original site's leg order
 };
 void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log_z, std::vector<double>& sign,
                    double& flops);
@@ -54,6 +55,7 @@ struct BondReq {
   const double* gate;   // device, d^2 x d^2 float64
   double* bl;
   double* br;
+  bool tr = false;   // e is a transposed lattice (a vertical bond): b in the original leg order
 };
 void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops);
 

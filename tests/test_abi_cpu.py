@@ -61,8 +61,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(binding.Opts) == 4 * 4 + 8
     assert C.sizeof(binding.Window) == 7 * 4
     assert C.sizeof(binding.Result) == 5 * 8
-    assert C.sizeof(binding.SiteReq) == 8 + 2 * 4 + 3 * 8
-    assert C.sizeof(binding.BondReq) == 8 + 2 * 4 + 3 * 8
+    assert C.sizeof(binding.SiteReq) == 8 + 4 * 4 + 3 * 8   # r, c, dir and padding
+    assert C.sizeof(binding.BondReq) == 8 + 4 * 4 + 3 * 8
     assert C.sizeof(binding.OverlapReq) == 2 * 8 + 2 * 4 + 3 * 8
 
 

@@ -319,3 +319,46 @@ def test_bond_env_rejects_bad_requests(sess):
     with pytest.raises(binding.PepsError):   # no gate
         sess.ctx.bond_env_raw([(env, 0, 0, 0, 1 << 20, 0)])
     env.free()
+
+
+# --- vertical bonds: the column sandwiches (environments with columns) ------
+
+@pytest.mark.parametrize("case", [("aniso", 4, 3, 5, 3), ("normal_unit", 3, 4, 3, 4), ("normal_unit", 4, 4, 4096, 4)])
+def test_vertical_site_and_bond_env_parity(sess, case):
+    """dir 1: N of every site and b of both sites of every vertical bond from
+    the column sandwich of the site's column, in the site's own leg order."""
+    dist, Lr, Lc, chi, H = case
+    say(f"vertical site/bond environments {case}")
+    if dist == "aniso":
+        rng = np.random.default_rng(410)
+        A = [[rng.standard_normal((2, 1 if c == 0 else 2, 1 if r == 0 else 3, 1 if c == Lc - 1 else 2,
+                                   1 if r == Lr - 1 else 3)) for c in range(Lc)] for r in range(Lr)]
+    else:
+        A = make_peps(Lr, Lc, 2, dist, 411 + Lr * Lc)
+    G = _gate(Lr + Lc)
+    env = sess.env_boundary([binding.to_device(A)], chi, "f64", H, columns=True)[0]
+    sites = [(r, c) for r in range(Lr) for c in range(Lc)]
+    Ns, _ = sess.site_env([(env, r, c, 1) for r, c in sites])
+    bonds = [(r, c) for r in range(Lr - 1) for c in range(Lc)]
+    bs, _ = sess.bond_env([(env, r, c, _dev(G), 1) for r, c in bonds])
+    env.free()
+    cols = api.env_columns(A, chi, H)
+    for (r, c), g in zip(sites, Ns):
+        check(g, api.site_env_columns(cols, A, r, c), TOL64)
+    for (r, c), b in zip(bonds, bs):
+        check_b(b, api.bond_env_vertical(cols, A, r, c, G), TOL64)
+
+
+def test_vertical_needs_column_environment(sess):
+    A = make_peps(3, 3, 2, "uniform", 5)
+    env = sess.env_boundary([binding.to_device(A)], 4)[0]
+    with pytest.raises(binding.PepsError):
+        sess.ctx.site_env_raw([(env, 0, 0, 1 << 20, 1)])
+    g = _dev(np.eye(4))
+    with pytest.raises(binding.PepsError):
+        sess.ctx.bond_env_raw([(env, 0, 0, g.data_ptr(), 1 << 20, 0, 1)])
+    env.free()
+    env = sess.env_boundary([binding.to_device(A)], 4, columns=True)[0]
+    with pytest.raises(binding.PepsError):   # bond (2,0)-(3,0) leaves the lattice
+        sess.ctx.bond_env_raw([(env, 2, 0, g.data_ptr(), 1 << 20, 0, 1)])
+    env.free()
