@@ -179,7 +179,7 @@ def side_instances(sess, binding, torch):
 
 def side_convergence(sess, binding, torch):
     """Convergence on synthetic states (the analogue of the paper's boundary
-    and cluster studies, Sec. 6): 8x8, D=4, near-product and N(0,1)
+    and cluster studies, Secs. 5.2 and 5.3): 8x8, D=4, near-product and N(0,1)
     unit-norm sites.  Energy error of the full environment against chi (two-
     row and column sandwiches) with the boundary infidelity 1 - f of every
     row's boundaries, and of n x n cluster windows against n, all relative

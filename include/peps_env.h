@@ -144,7 +144,7 @@ peps_status peps_expect(peps_ctx* ctx, peps_env* const* env, int32_t n_env, peps
 
 void peps_env_free(peps_env* env);
 
-/* Norm environment N_l of single sites (Sec. 3: the network of <psi|psi>
+/* Norm environment N_l of single sites (Sec. 2: the network of <psi|psi>
  * with the ket and bra tensors of site l taken out, the matrix of the ALS
  * tensor update N_l A_l = b_l), from the single-row sandwich of the site's
  * row between the stored boundaries; one batched run over all requests.
@@ -172,7 +172,7 @@ typedef struct {
 } peps_site_req;
 peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, double* flops);
 
-/* Right-hand sides b_l of the ALS update of a horizontal bond (Sec. 3,
+/* Right-hand sides b_l of the ALS update of a horizontal bond (Sec. 2,
  * N_l A_l = b_l) under a two-site gate: the overlap <psi|G psi> of the
  * stored state with the gated one, differentiated by the bra tensor of the
  * left site (r,c) and of the right site (r,c+1), from the row sandwich of
@@ -199,7 +199,7 @@ typedef struct {
 } peps_bond_req;
 peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req, double* flops);
 
-/* Overlaps of stored boundaries, for the boundary fidelity of Sec. 6
+/* Overlaps of stored boundaries, for the boundary fidelity of Sec. 5.2
  * (f = |tr(X^T Y)| of boundary MPOs scaled to tr(X^T X) = 1): per request
  * the boundaries of env_a and env_b (environments of one lattice, any chi
  * and precision; their float64 tensors are used) after k absorbed rows,

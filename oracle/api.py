@@ -12,11 +12,11 @@ and cluster windows.  Test infrastructure only (see the package docstring).
   run along the other lattice direction, Sec. 2).  Passed to ``expect``, they
   give the vertical bond energies from single-column sandwiches instead of
   two-row sandwiches.
-* ``site_env`` - norm environment N_l of one site (Sec. 3, the matrix of
+* ``site_env`` - norm environment N_l of one site (Sec. 2, the matrix of
   the ALS tensor update) from its row sandwich, scaled to A N A = +-1, with
   the log of the scale.
 * ``bond_env`` - right-hand sides b_l of the ALS update of a horizontal
-  bond under a two-site gate (Sec. 3), in the scaling of ``site_env``.
+  bond under a two-site gate (Sec. 2), in the scaling of ``site_env``.
 * ``cluster_env`` - per-site n x n windows closed by CU_0 separable
   boundaries (``cluster``), Sec. 5.3.
 """

@@ -248,7 +248,7 @@ def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row):
 def mps_overlap(X, Y):
     """<X|Y> of two boundaries of one lattice row, each tensor [a, k, b, a']
     with (k, b) taken as one physical index: the trace tr(X^T Y) of the two
-    boundary MPOs (Sec. 6 measures boundary fidelity with it)."""
+    boundary MPOs (Sec. 5.2 measures boundary fidelity with it)."""
     E = np.ones((1, 1))
     for x, y in zip(X, Y):
         E = np.einsum("xy,xkbz,ykbw->zw", E, x, y, **EIN)

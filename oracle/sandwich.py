@@ -121,7 +121,7 @@ def row_observables(T, Arow, B, lam, rho):
 def site_environment(T, Arow, B, lam, rho, c):
     """Norm environment of site c of one row: the network of <psi|psi> with
     the ket and bra tensors of that site taken out, the matrix N_l of the
-    ALS tensor update N_l A_l = b_l (Sec. 3).
+    ALS tensor update N_l A_l = b_l (Sec. 2).
 
     N[l,u,r,d,m,v,s,g] = sum L[o,l,m,a] T[a,u,v,e] R[o',r,s,e] B[o,d,g,o']
     with the normalised environments L = Lenv[c], R = Renv[c+1] of the row,
@@ -143,7 +143,7 @@ def site_environment(T, Arow, B, lam, rho, c):
 
 def bond_gate_environment(T, Arow, B, lam, rho, c, G):
     """Right-hand sides b of the ALS update of the horizontal bond (c, c+1)
-    under a two-site gate (Sec. 3, N_l A_l = b_l): the overlap <psi'|G psi>
+    under a two-site gate (Sec. 2, N_l A_l = b_l): the overlap <psi'|G psi>
     with psi' = psi, differentiated by the bra tensor of site c (b_left) or
     of site c+1 (b_right).
 

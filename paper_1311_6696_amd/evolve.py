@@ -1,4 +1,4 @@
-"""Imaginary-time evolution of a PEPS by full updates (Secs. 3 and 5.2), a
+"""Imaginary-time evolution of a PEPS by full updates (Secs. 2 and 5.2), a
 consumer of the library's environments.
 
 Each Trotter step applies exp(-tau S_l.S_m) on every nearest-neighbour bond
