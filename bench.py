@@ -233,8 +233,30 @@ def side_convergence(sess, binding, torch):
     return out
 
 
+def side_evolution(sess, binding, torch):
+    """Imaginary-time full updates of the 4x4 Heisenberg model from a Neel
+    start (the driver over the site and bond environments), D = 2, 3, 4 at
+    lossless chi: energy per site against the exact -0.57432544 and time per
+    Trotter step (eight environments plus their site and bond environments)."""
+    from paper_1311_6696_amd import evolve
+    out = {}
+    for D, chi, steps in ((2, 16, 40), (3, 81, 40), (4, 256, 30)):
+        note(f"evolution 4x4 D={D}")
+        A = evolve.neel_start(4, 4, D, 1e-1, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, trace = evolve.full_update(sess, A, 0.05, steps, chi, cutoff=1e-8, every=10)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[f"D{D}"] = {"chi": chi, "tau": 0.05, "steps": steps, "energy_per_site": [e for _, e in trace],
+                        "best": min(e for _, e in trace), "exact": -0.57432544,
+                        "ms_per_step_incl_energy_checks": 1000.0 * t / steps}
+    out["workload"] = "4x4 OBC Heisenberg, Neel start with 0.1 noise, exp(-0.05 S.S) gates, one-site refits"
+    return out
+
+
 SIDE = {"precision": side_precision, "clusters": side_clusters, "instances": side_instances,
-        "convergence": side_convergence}
+        "convergence": side_convergence, "evolution": side_evolution}
 
 
 def main():
@@ -254,7 +276,8 @@ def main():
     ap.add_argument("--workloads", default="",
                     help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
                          "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices), "
-                         "convergence (energy error against chi and cluster size n)")
+                         "convergence (energy error against chi and cluster size n), evolution "
+                         "(4x4 imaginary-time full updates)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the contraction launch shapes on one untimed environment first")
     ap.add_argument("--graphs", action="store_true",
