@@ -163,6 +163,16 @@ def bond_env_vertical(columns, A, r, c, G):
     return _from_transposed(bl, A[r][c].shape, False), _from_transposed(br, A[r + 1][c].shape, False)
 
 
+def bond_fit(env, r, c, G, S1, S2):
+    """(N1, b1, N2, b2) of fitting G psi on the horizontal bond (r, c)-(r, c+1)
+    with the sites replaced by S1, S2 (``bond_fit_environments``)."""
+    lat = env.lat
+    T, _, _ = env.T(r - 1)
+    B, _, _ = env.B(r + 1)
+    from .sandwich import bond_fit_environments
+    return bond_fit_environments(T, lat.A[r], B, lat.lam[r], lat.rho[r], c, G, S1, S2)
+
+
 def energy(res):
     """Total Heisenberg energy sum of bond terms (eq. HeisenbergH)."""
     return float(np.nansum(res["bond_h"]) + np.nansum(res["bond_v"]))

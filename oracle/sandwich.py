@@ -141,6 +141,52 @@ def site_environment(T, Arow, B, lam, rho, c):
     return N / abs(w), np.log(abs(w)) + sL[c] + sR[c + 1], (1.0 if w >= 0 else -1.0)
 
 
+def bond_fit_environments(T, Arow, B, lam, rho, c, G, S1, S2):
+    """The two local problems of fitting G psi on the bond (c, c+1) with the
+    new state psi' = psi except S1, S2 at sites c, c+1 (the alternating
+    least-squares solve of the bond update, Sec. 2 and Sec. 5.2):
+
+    N1 (S2): norm environment of site c in <psi'|psi'>,  b1 (S2) = d<psi'|G psi>/d S1,
+    N2 (S1): norm environment of site c+1,                b2 (S1) = d<psi'|G psi>/d S2,
+
+    every quantity from the normalised Lenv[c], Renv[c+2] of the row and
+    divided by one number per site (the scaling of ``bond_gate_environment``),
+    so that S1 = b1 N1^-1 and S2 = b2 N2^-1 solve the two problems; with
+    S = A they reduce to ``site_environment`` and ``bond_gate_environment``.
+    """
+    Lenv, Renv, sL, sR = row_environments(T, Arow, B, lam, rho)
+    bl, br = bond_gate_environment(T, Arow, B, lam, rho, c, G)   # for the scale factors below
+    A1, A2 = Arow[c], Arow[c + 1]
+    Theta = np.einsum("pPqQ,qQludURD->pPludURD", G, np.einsum("qlurd,QrURD->qQludURD", A1, A2, **EIN), **EIN)
+    X = np.einsum("olmuve,odgy->lumvdgye", np.einsum("olma,auve->olmuve", Lenv[c], T[c], **EIN), B[c], **EIN)
+    Z = np.einsum("zRSeUV,yDGz->RSeUVyDG", np.einsum("zRSf,eUVf->zRSeUV", Renv[c + 2], T[c + 1], **EIN),
+                  B[c + 1], **EIN)
+    E = np.einsum("lumvdgye,SeVyGpPlud->pPmvgVSG", X,
+                  np.einsum("RSeUVyDG,pPludURD->SeVyGpPlud", Z, Theta, **EIN), **EIN)
+    # raw environments with the substitutes in place of the other site
+    R1 = row_step_right(Renv[c + 2], T[c + 1], S2, S2, B[c + 1])
+    L2 = row_step(Lenv[c], T[c], S1, S1, B[c])
+
+    def norm_env(L, k, R):
+        Y = np.einsum("olma,auve->olmuve", L, T[k], **EIN)
+        Y = np.einsum("olmuve,odgy->lmuvedgy", Y, B[k], **EIN)
+        K = int(np.prod(Arow[k].shape[1:]))
+        return np.einsum("lmuvedgy,yrse->lurdmvsg", Y, R, **EIN).reshape(K, K)
+
+    def absw(k):
+        N = norm_env(Lenv[k], k, Renv[k + 1])
+        a = Arow[k].reshape(Arow[k].shape[0], -1)
+        return abs(float(np.einsum("pk,kj,pj->", a, N, a)))
+
+    sc1 = np.exp(sR[c + 1] - sR[c + 2]) * absw(c)
+    sc2 = np.exp(sL[c + 1] - sL[c]) * absw(c + 1)
+    N1 = norm_env(Lenv[c], c, R1) / sc1
+    N2 = norm_env(L2, c + 1, Renv[c + 2]) / sc2
+    b1 = np.einsum("pPmvgVSG,PsVSG->pmvsg", E, S2, **EIN).reshape(A1.shape[0], -1) / sc1
+    b2 = np.einsum("pPmvgVSG,pmvsg->PsVSG", E, S1, **EIN).reshape(A2.shape[0], -1) / sc2
+    return N1, b1, N2, b2
+
+
 def bond_gate_environment(T, Arow, B, lam, rho, c, G):
     """Right-hand sides b of the ALS update of the horizontal bond (c, c+1)
     under a two-site gate (Sec. 2, N_l A_l = b_l): the overlap <psi'|G psi>

@@ -474,6 +474,44 @@ def test_bond_env_identity_gate_is_N_times_A():
             assert np.abs(b - a @ Nm).max() < 1e-12 * np.abs(b).max()
 
 
+def test_bond_fit_with_substitutes_matches_brute_force():
+    """The bond update's two local problems with the sites replaced by
+    random S1, S2: N and b of each site equal the brute-force norm
+    environment of psi' and d<psi'|G psi>/dS up to one common factor per
+    site (the factor the solve S = b N^-1 does not see); with S = A they
+    equal the site and bond environments."""
+    Lr, Lc = 3, 4
+    A = make_peps(Lr, Lc, 2, "normal_unit", 101)
+    G = np.random.default_rng(3).standard_normal((2, 2, 2, 2))
+    env = api.env_boundary(A, 4096)
+    r, c = 1, 1
+    N1, b1, N2, b2 = api.bond_fit(env, r, c, G, A[r][c], A[r][c + 1])
+    bl, br = api.bond_env(env, r, c, G)
+    assert np.abs(N1 - api.site_env(env, r, c)[0]).max() < 1e-13
+    assert np.abs(N2 - api.site_env(env, r, c + 1)[0]).max() < 1e-13
+    assert np.abs(b1 - bl).max() < 1e-13 and np.abs(b2 - br).max() < 1e-13
+    rng = np.random.default_rng(4)
+    S1, S2 = rng.standard_normal(A[r][c].shape), rng.standard_normal(A[r][c + 1].shape)
+    N1, b1, N2, b2 = api.bond_fit(env, r, c, G, S1, S2)
+    psi = exact.statevector(A)
+    i, j = r * Lc + c, r * Lc + c + 1
+    phi = _gate_applied(psi, Lr * Lc, i, j, G)
+    for site, other, Sother, N, b in ((i, (r, c + 1), S2, N1, b1), (j, (r, c), S1, N2, b2)):
+        Ap = [list(row) for row in A]
+        Ap[other[0]][other[1]] = Sother
+        rr, cc = divmod(site, Lc)
+        K = int(np.prod(A[rr][cc].shape[1:]))
+        O = np.eye(K).reshape((K,) + A[rr][cc].shape[1:])
+        Bt = [[O if (x, y) == (rr, cc) else Ap[x][y] for y in range(Lc)] for x in range(Lr)]
+        M = exact.statevector(Bt).reshape(2 ** site, K, -1)
+        Mm = M.transpose(0, 2, 1).reshape(-1, K)
+        Nex = Mm.T @ Mm
+        bex = np.einsum("akb,apb->pk", M, phi.reshape(2 ** site, 2, -1))
+        f = np.sum(Nex * N) / np.sum(N * N)
+        assert np.abs(N * f - Nex).max() <= 1e-12 * np.abs(Nex).max()
+        assert np.abs(b * f - bex).max() <= 1e-12 * np.abs(bex).max()
+
+
 # --- boundary fidelity ---------------------------------------------------------
 
 def _dense_mps(T):
