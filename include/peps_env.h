@@ -199,6 +199,32 @@ typedef struct {
 } peps_bond_req;
 peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req, double* flops);
 
+/* The two local problems of the alternating least-squares bond update
+ * (Sec. 2; the full update of Sec. 5.2): fitting G psi on the bond of
+ * peps_bond_env (same r, c, dir, gate) by psi', the stored state with the
+ * bond's two sites replaced by s1 (first site) and s2 (second site).  n1, b1:
+ * norm environment of the first site in <psi'|psi'> (its second site s2)
+ * and d<psi'|G psi>/d s1; n2, b2 the same for the second site with s1.
+ * s1, s2 (device, float64, each site's own shape and leg order) may be the
+ * stored tensors.  Outputs (device, caller-allocated, K*K and d*K doubles as
+ * in peps_site_env / peps_bond_env) are divided by one positive number per
+ * site, that of peps_bond_env, so that s1 = b1 n1^-1 and s2 = b2 n2^-1 solve
+ * the two problems; with s = A they equal the site and bond environments.
+ * Needs float64 environments. */
+typedef struct {
+  peps_env* env;
+  int32_t r, c;
+  int32_t dir;
+  const double* gate;
+  const double* s1;
+  const double* s2;
+  double* n1;
+  double* b1;
+  double* n2;
+  double* b2;
+} peps_fit_req;
+peps_status peps_bond_fit(peps_ctx* ctx, const peps_fit_req* req, int32_t n_req, double* flops);
+
 /* Overlaps of stored boundaries, for the boundary fidelity of Sec. 5.2
  * (f = |tr(X^T Y)| of boundary MPOs scaled to tr(X^T X) = 1): per request
  * the boundaries of env_a and env_b (environments of one lattice, any chi

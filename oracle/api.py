@@ -173,6 +173,14 @@ def bond_fit(env, r, c, G, S1, S2):
     return bond_fit_environments(T, lat.A[r], B, lat.lam[r], lat.rho[r], c, G, S1, S2)
 
 
+def bond_fit_vertical(columns, r, c, G, S1, S2):
+    """``bond_fit`` of the vertical bond (r, c)-(r+1, c) from the column
+    sandwich of column c; S1, S2 and the results in the sites' own order."""
+    N1, b1, N2, b2 = bond_fit(columns, c, r, G, S1.transpose(0, 2, 1, 4, 3), S2.transpose(0, 2, 1, 4, 3))
+    return (_from_transposed(N1, S1.shape, True), _from_transposed(b1, S1.shape, False),
+            _from_transposed(N2, S2.shape, True), _from_transposed(b2, S2.shape, False))
+
+
 def energy(res):
     """Total Heisenberg energy sum of bond terms (eq. HeisenbergH)."""
     return float(np.nansum(res["bond_h"]) + np.nansum(res["bond_v"]))

@@ -73,6 +73,12 @@ class BondReq(C.Structure):
                 ("b_left", C.c_void_p), ("b_right", C.c_void_p)]
 
 
+class FitReq(C.Structure):
+    _fields_ = [("env", C.c_void_p), ("r", C.c_int32), ("c", C.c_int32), ("dir", C.c_int32), ("gate", C.c_void_p),
+                ("s1", C.c_void_p), ("s2", C.c_void_p), ("n1", C.c_void_p), ("b1", C.c_void_p),
+                ("n2", C.c_void_p), ("b2", C.c_void_p)]
+
+
 class OverlapReq(C.Structure):
     _fields_ = [("env_a", C.c_void_p), ("env_b", C.c_void_p), ("side", C.c_int32), ("k", C.c_int32),
                 ("xy", C.c_double), ("xx", C.c_double), ("yy", C.c_double)]
@@ -86,7 +92,7 @@ class Result(C.Structure):
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
            "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
-           "peps_bond_env", "peps_boundary_overlap", "peps_last_error")
+           "peps_bond_env", "peps_bond_fit", "peps_boundary_overlap", "peps_last_error")
 
 _lib = None
 
@@ -120,12 +126,13 @@ def load(path=None):
     lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
     lib.peps_bond_env.argtypes = [vp, C.POINTER(BondReq), i32, C.POINTER(C.c_double)]
     lib.peps_boundary_overlap.argtypes = [vp, C.POINTER(OverlapReq), i32]
+    lib.peps_bond_fit.argtypes = [vp, C.POINTER(FitReq), i32, C.POINTER(C.c_double)]
     lib.peps_last_error.argtypes = []
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
                  "peps_ctx_set_workspace", "peps_qr", "peps_site_env", "peps_bond_env",
-                 "peps_boundary_overlap"):
+                 "peps_boundary_overlap", "peps_bond_fit"):
         getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -313,6 +320,15 @@ class Context:
         _check(self.lib, self.lib.peps_bond_env(self.handle, arr, len(reqs), C.byref(fl)))
         return fl.value
 
+    def bond_fit_raw(self, reqs):
+        """reqs: sequence of (env, r, c, dir, gate, s1, s2, n1, b1, n2, b2)
+        with device addresses.  Returns the flops."""
+        arr = (FitReq * len(reqs))(*[FitReq(q[0].handle, int(q[1]), int(q[2]), int(q[3]), *[int(p) for p in q[4:]])
+                                     for q in reqs])
+        fl = C.c_double()
+        _check(self.lib, self.lib.peps_bond_fit(self.handle, arr, len(reqs), C.byref(fl)))
+        return fl.value
+
     def boundary_overlap(self, reqs):
         """reqs: sequence of (env_a, env_b, side, k).  Returns [(xy, xx, yy)];
         the boundary fidelity is |xy| / sqrt(xx * yy)."""
@@ -400,6 +416,31 @@ class Session:
             outs.append((bl, br))
             raw.append((e, r, c, g.data_ptr(), bl.data_ptr(), br.data_ptr(), dr))
         fl = self.ctx.bond_env_raw(raw)
+        return outs, fl
+
+    def bond_fit(self, reqs):
+        """reqs: sequence of (env, r, c, dir, gate, s1, s2) with float64 GPU
+        tensors (s1, s2 shaped like the bond's sites).  Returns
+        ([(n1, b1, n2, b2)], flops): the two local problems of fitting
+        gate psi with the bond's sites replaced by s1, s2."""
+        torch = self.torch
+        outs, raw = [], []
+        for e, r, c, dr, g, s1, s2 in reqs:
+            for t in (g, s1, s2):
+                if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+                    raise ValueError("gate and substitutes must be contiguous float64 GPU tensors")
+            r2, c2 = (r + 1, c) if dr == 1 else (r, c + 1)
+            if tuple(s1.shape) != tuple(e.shapes[r][c]) or tuple(s2.shape) != tuple(e.shapes[r2][c2]):
+                raise ValueError("substitutes must have the shapes of the bond's sites")
+            d = int(e.shapes[r][c][0])
+            K1, K2 = e.site_dim(r, c), e.site_dim(r2, c2)
+            o = (torch.empty((K1, K1), dtype=torch.float64, device="cuda"),
+                 torch.empty((d, K1), dtype=torch.float64, device="cuda"),
+                 torch.empty((K2, K2), dtype=torch.float64, device="cuda"),
+                 torch.empty((d, K2), dtype=torch.float64, device="cuda"))
+            outs.append(o)
+            raw.append((e, r, c, dr, g.data_ptr(), s1.data_ptr(), s2.data_ptr()) + tuple(t.data_ptr() for t in o))
+        fl = self.ctx.bond_fit_raw(raw)
         return outs, fl
 
     def qr(self, mats, inplace=False):

@@ -318,6 +318,56 @@ peps_status peps_bond_env(peps_ctx* ctx, const peps_bond_req* req, int32_t n_req
   });
 }
 
+peps_status peps_bond_fit(peps_ctx* ctx, const peps_fit_req* req, int32_t n_req, double* flops) {
+  return guarded([&] {
+    PE_REQUIRE(ctx && req, "ctx and req must not be NULL");
+    PE_REQUIRE(n_req >= 1, "n_req must be >= 1");
+    std::vector<FitReq> rs;
+    for (int i = 0; i < n_req; ++i) {
+      const peps_fit_req& q = req[i];
+      const std::string w = "request " + std::to_string(i) + ": ";
+      PE_REQUIRE(q.env && q.gate && q.s1 && q.s2, w + "env, gate, s1 and s2 must not be NULL");
+      PE_REQUIRE(q.n1 && q.b1 && q.n2 && q.b2, w + "n1, b1, n2 and b2 must not be NULL");
+      PE_REQUIRE(q.env->ctx == ctx->c.get(), w + "environment belongs to another context");
+      PE_REQUIRE(q.dir == 0 || q.dir == 1, w + "dir must be 0 or 1");
+      FitReq f{q.env, q.r, q.c, q.gate, q.s1, q.s2, q.n1, q.b1, q.n2, q.b2, false};
+      if (q.dir == 0) {
+        PE_REQUIRE(q.r >= 0 && q.r < q.env->lat.Lr && q.c >= 0 && q.c + 1 < q.env->lat.Lc,
+                   w + "bond outside the lattice");
+      } else {
+        PE_REQUIRE(q.env->col != nullptr, w + "dir 1 needs an environment built with PEPS_OPTS_COLUMNS");
+        PE_REQUIRE(q.r >= 0 && q.r + 1 < q.env->lat.Lr && q.c >= 0 && q.c < q.env->lat.Lc,
+                   w + "bond outside the lattice");
+        f.e = q.env->col.get();
+        f.r = q.c;
+        f.c = q.r;
+        f.tr = true;
+      }
+      rs.push_back(f);
+    }
+    dev::set_device(ctx->c->device);
+    std::vector<peps_env*> es;
+    std::vector<double> f0;
+    for (const FitReq& q : rs)
+      if (std::find(es.begin(), es.end(), q.e) == es.end()) {
+        es.push_back(q.e);
+        f0.push_back(q.e->flops);
+      }
+    double fl = 0.0;
+    try {
+      plan_bond_fit(*ctx->c, rs, fl);
+    } catch (...) {
+      for (size_t k = 0; k < es.size(); ++k) es[k]->flops = f0[k];
+      throw;
+    }
+    for (size_t k = 0; k < es.size(); ++k) {
+      fl += es[k]->flops - f0[k];
+      es[k]->flops = f0[k];
+    }
+    if (flops) *flops = fl;
+  });
+}
+
 peps_status peps_boundary_overlap(peps_ctx* ctx, peps_overlap_req* req, int32_t n_req) {
   return guarded([&] {
     PE_REQUIRE(ctx && req, "ctx and req must not be NULL");

@@ -1015,3 +1015,232 @@ void plan_overlap(Ctx& ctx, std::vector<OvReq>& req) {
 }
 
 }  // namespace pe
+
+namespace pe {
+
+namespace {
+
+// One raw column step with explicit ket and bra views (no normalisation).
+void step_tv(St& st, std::vector<TcDesc>& fin, const RJob& j, int c, bool left, const TV& in, const TV& ket,
+             const TV& bra, void* out, void* P, void* Q, int cdt) {
+  TV T = dense(j.T->tc[c], cdt, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV B = dense(j.B->tc[c], cdt, "xdgy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  if (left) {
+    TV y3 = chain_left(st, in, T, ket, bra, P, Q, cdt);
+    fin.push_back(tc_build(envv(j, out, c + 1, "yrse", cdt), y3, B));
+  } else {
+    TV y3 = chain_right(st, in, T, ket, bra, P, Q, cdt);
+    fin.push_back(tc_build(envv(j, out, c, "xlma", cdt), y3, B));
+  }
+  st.flops += tc_flops(fin.back());
+}
+
+}  // namespace
+
+void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
+  Arena call(&ctx.pool);
+  Rec rec(&ctx, &call);
+  Scratch scr(call);
+  const Opts& o = req[0].e->opts;
+  for (const FitReq& q : req) PE_REQUIRE(q.e->opts.dtype == o.dtype, "one precision per bond-fit call");
+  PE_REQUIRE(o.cdt() == DT_F64, "the bond fit takes float64 substitutes: it needs a float64 environment");
+  const int prec = o.prec(), cdt = DT_F64;
+  const size_t esz = sizeof(double);
+
+  std::vector<RJob> rj;
+  std::vector<R2Job> r2;
+  std::map<std::pair<peps_env*, int>, size_t> job_of;
+  std::vector<size_t> jid(req.size());
+  for (size_t i = 0; i < req.size(); ++i) {
+    const auto key = std::make_pair(req[i].e, req[i].r);
+    auto it = job_of.find(key);
+    if (it == job_of.end()) {
+      it = job_of.emplace(key, rj.size()).first;
+      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
+    }
+    jid[i] = it->second;
+  }
+  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
+  flops = 0.0;
+
+  // the substitutes as site views (same shape and storage order as the sites)
+  std::vector<Site> v1(req.size()), v2(req.size());
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    v1[i] = *j.s[req[i].c];
+    v2[i] = *j.s[req[i].c + 1];
+    v1[i].op[0] = const_cast<double*>(req[i].s1);
+    v2[i].op[0] = const_cast<double*>(req[i].s2);
+  }
+  // raw environments with the substitutes: R1 = step(R[c+2]; S2), L2 = step(L[c]; S1)
+  std::vector<void*> R1(req.size()), L2(req.size());
+  {
+    St st(3, prec);
+    std::vector<TcDesc> fin;
+    std::vector<void*> tmp;
+    for (size_t i = 0; i < req.size(); ++i) {
+      const RJob& j = rj[jid[i]];
+      const int c = req[i].c;
+      R1[i] = call.alloc(esz * env_elems(j, c + 1));
+      L2[i] = call.alloc(esz * env_elems(j, c + 1));
+      for (int k = 0; k < 2; ++k) {
+        const int cc = k == 0 ? c + 1 : c;
+        auto pq = step_scratch(j, cc);
+        void* P = scr.get(esz * pq.first);
+        void* Q = scr.get(esz * pq.second);
+        tmp.push_back(P);
+        tmp.push_back(Q);
+        const Site& v = k == 0 ? v2[i] : v1[i];
+        if (k == 0)
+          step_tv(st, fin, j, cc, false, envv(j, j.R[c + 2], c + 2, "yrse", cdt), site_tv(v, OP_ID, false, cdt, "plurd"),
+                  site_tv(v, OP_ID, false, cdt, "pmvsg"), R1[i], P, Q, cdt);
+        else
+          step_tv(st, fin, j, cc, true, envv(j, j.L[c], c, "xlma", cdt), site_tv(v, OP_ID, false, cdt, "plurd"),
+                  site_tv(v, OP_ID, false, cdt, "pmvsg"), L2[i], P, Q, cdt);
+      }
+    }
+    st.record(rec, prec, cdt);
+    rec.tc(prec, cdt, fin);
+    flops += st.flops;
+    for (void* p : tmp) scr.put(p);
+    rec.flush(call);
+  }
+
+  // pair environment E (as for the gated bond), b1 = E . S2, b2 = E . S1,
+  // N1 = L[c] T B R1, N2 = L2 T B R[c+2]; leg orders as in the site and bond
+  // environments (the transposed forms write the sites' own order)
+  for (size_t i = 0; i < req.size(); ++i) {
+    const RJob& j = rj[jid[i]];
+    const int c = req[i].c;
+    const bool tr = req[i].tr;
+    const int64_t d = j.s[c]->d;
+    const int64_t x = j.bB[c], y = j.bB[c + 1], z = j.bB[c + 2], a = j.bT[c], e = j.bT[c + 1], f = j.bT[c + 2];
+    const int64_t Dl = j.Dl[c], Du = j.T->leg[c], Dd = j.B->leg[c], h = j.Dl[c + 1];
+    const int64_t R = j.Dl[c + 2], U = j.T->leg[c + 1], D = j.B->leg[c + 1];
+    std::vector<TcDesc> st[5];
+    std::vector<void*> tmp;
+    auto add = [&](int k, const TcDesc& t) {
+      st[k].push_back(t);
+      flops += tc_flops(t);
+    };
+    auto get = [&](int64_t n) {
+      void* p = scr.get(esz * n);
+      tmp.push_back(p);
+      return p;
+    };
+    TV L = envv(j, j.L[c], c, "xlma", cdt);
+    TV T1 = dense(j.T->tc[c], cdt, "auve", {a, Du, Du, e});
+    TV B1 = dense(j.B->tc[c], cdt, "xdgy", {x, Dd, Dd, y});
+    TV T2 = dense(j.T->tc[c + 1], cdt, "eUVf", {e, U, U, f});
+    TV B2 = dense(j.B->tc[c + 1], cdt, "yDGz", {y, D, D, z});
+    TV Rr = envv(j, j.R[c + 2], c + 2, "zRSf", cdt);
+    TV G = dense(req[i].gate, cdt, "pPqQ", {d, d, d, d});
+    TV x1 = dense(get(x * Dl * Du * Dl * Du * e), cdt, "xlumve", {x, Dl, Du, Dl, Du, e});
+    TV X = dense(get(Dl * Du * Dd * Dl * Du * Dd * y * e), cdt, "ludmvgye", {Dl, Du, Dd, Dl, Du, Dd, y, e});
+    TV z1 = dense(get(z * R * R * e * U * U), cdt, "zRSeUV", {z, R, R, e, U, U});
+    TV Z = dense(get(R * R * e * U * U * y * D * D), cdt, "RSeUVyDG", {R, R, e, U, U, y, D, D});
+    TV aa = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "qQludURD", {d, d, Dl, Du, Dd, U, R, D});
+    TV th = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "pPludURD", {d, d, Dl, Du, Dd, U, R, D});
+    TV W = dense(get(R * e * U * y * D * d * d * Dl * Du * Dd), cdt, "SeVyGpPlud", {R, e, U, y, D, d, d, Dl, Du, Dd});
+    TV E = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "pPmvgVSG", {d, d, Dl, Du, Dd, U, R, D});
+    add(0, tc_build(x1, L, T1));
+    add(0, tc_build(z1, Rr, T2));
+    add(0, tc_build(aa, site_tv(*j.s[c], OP_ID, false, cdt, "qlurd"), site_tv(*j.s[c + 1], OP_ID, false, cdt, "QrURD")));
+    add(1, tc_build(X, x1, B1));
+    add(1, tc_build(Z, z1, B2));
+    add(1, tc_build(th, G, aa));
+    add(2, tc_build(W, Z, th));
+    add(3, tc_build(E, X, W));
+    add(4, tc_build(tr ? dense(req[i].b1, cdt, "pvmgs", {d, Du, Dl, Dd, h}) : dense(req[i].b1, cdt, "pmvsg", {d, Dl, Du, h, Dd}),
+                    E, site_tv(v2[i], OP_ID, false, cdt, "PsVSG")));
+    add(4, tc_build(tr ? dense(req[i].b2, cdt, "PVsGS", {d, U, h, D, R}) : dense(req[i].b2, cdt, "PsVSG", {d, h, U, R, D}),
+                    E, site_tv(v1[i], OP_ID, false, cdt, "pmvsg")));
+    // N1 from L[c], T[c], B[c], R1; N2 from L2, T[c+1], B[c+1], R[c+2]
+    for (int k = 0; k < 2; ++k) {
+      const int cc = c + k;
+      const int64_t xx = j.bB[cc], yy = j.bB[cc + 1], ee = j.bT[cc + 1];
+      const int64_t dl = j.Dl[cc], du = j.T->leg[cc], dr = j.Dl[cc + 1], dd = j.B->leg[cc];
+      TV Lk = k == 0 ? L : envv(j, L2[i], c + 1, "xlma", cdt);
+      TV Tk = dense(j.T->tc[cc], cdt, "auve", {j.bT[cc], du, du, ee});
+      TV Bk = dense(j.B->tc[cc], cdt, "xdgy", {xx, dd, dd, yy});
+      TV Rk = k == 0 ? envv(j, R1[i], c + 1, "yrse", cdt) : envv(j, j.R[c + 2], c + 2, "yrse", cdt);
+      TV y1 = tr ? dense(get(xx * du * dl * du * dl * ee), cdt, "xulvme", {xx, du, dl, du, dl, ee})
+                 : dense(get(xx * dl * du * dl * du * ee), cdt, "xlumve", {xx, dl, du, dl, du, ee});
+      TV y2 = tr ? dense(get(du * dl * dd * du * dl * dd * yy * ee), cdt, "uldvmgye", {du, dl, dd, du, dl, dd, yy, ee})
+                 : dense(get(dl * du * dd * dl * du * dd * yy * ee), cdt, "ludmvgye", {dl, du, dd, dl, du, dd, yy, ee});
+      double* out = k == 0 ? req[i].n1 : req[i].n2;
+      TV n = tr ? dense(out, cdt, "uldrvmgs", {du, dl, dd, dr, du, dl, dd, dr})
+                : dense(out, cdt, "lurdmvsg", {dl, du, dr, dd, dl, du, dr, dd});
+      add(0, tc_build(y1, Lk, Tk));
+      add(1, tc_build(y2, y1, Bk));
+      add(2, tc_build(n, y2, Rk));
+    }
+    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
+    for (void* p : tmp) scr.put(p);
+    rec.flush(call);
+  }
+  // <L[k], R[k]> at k = c+1, c+2 (once per job and column)
+  {
+    std::vector<RedDesc> rd;
+    std::vector<std::vector<char>> done(rj.size());
+    for (size_t k = 0; k < rj.size(); ++k) done[k].assign(rj[k].Lc + 1, 0);
+    for (size_t i = 0; i < req.size(); ++i) {
+      const RJob& j = rj[jid[i]];
+      for (int k = req[i].c + 1; k <= req[i].c + 2; ++k) {
+        if (done[jid[i]][k]) continue;
+        done[jid[i]][k] = 1;
+        rd.push_back(red_desc(j.L[k], j.R[k], env_elems(j, k), j.dots + k, cdt));
+      }
+    }
+    rec.reduce(rd);
+  }
+  rec.run(call);
+
+  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
+  for (size_t k = 0; k < rj.size(); ++k) {
+    const int Lc = rj[k].Lc;
+    hd[k].resize(Lc + 1);
+    hl[k].resize(Lc + 1);
+    hr[k].resize(Lc + 1);
+    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
+    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
+  }
+  dev::sync(ctx.stream);
+  // the gated bond's scale factors of the two sites (the stored state's)
+  double* s2 = (double*)call.alloc(sizeof(double) * 2 * req.size());
+  std::vector<EwDesc> fill, scale;
+  for (size_t i = 0; i < req.size(); ++i) {
+    const size_t k = jid[i];
+    const int c = req[i].c;
+    const double w0 = std::sqrt(hl[k][c + 1]) * hd[k][c + 1], w1 = std::sqrt(hl[k][c + 2]) * hd[k][c + 2];
+    const double sl = std::sqrt(hr[k][c + 1]) * std::fabs(w0), sr = std::sqrt(hl[k][c + 1]) * std::fabs(w1);
+    if (!(std::isfinite(sl) && sl > 0.0 && std::isfinite(sr) && sr > 0.0))
+      throw Error(ST_NONFINITE, "bond fit (" + std::to_string(req[i].r) + "," + std::to_string(c) +
+                                    ") has a zero or non-finite scale");
+    const RJob& j = rj[k];
+    const int64_t d = j.s[c]->d;
+    const int64_t K1 = j.Dl[c] * j.T->leg[c] * j.Dl[c + 1] * j.B->leg[c];
+    const int64_t K2 = j.Dl[c + 1] * j.T->leg[c + 1] * j.Dl[c + 2] * j.B->leg[c + 1];
+    for (int side = 0; side < 2; ++side) {
+      EwDesc fl = ew_desc(EW_FILL, nullptr, DT_F64, s2 + 2 * i + side, DT_F64, 1);
+      fl.a = side == 0 ? sl * sl : sr * sr;
+      fill.push_back(fl);
+      const int64_t K = side == 0 ? K1 : K2;
+      double* outs[2] = {side == 0 ? req[i].n1 : req[i].n2, side == 0 ? req[i].b1 : req[i].b2};
+      const int64_t ns[2] = {K * K, d * K};
+      for (int t = 0; t < 2; ++t) {
+        EwDesc e = ew_desc(EW_RSQRT, outs[t], DT_F64, outs[t], DT_F64, ns[t]);
+        e.sptr = s2 + 2 * i + side;
+        scale.push_back(e);
+      }
+    }
+  }
+  Rec rec2(&ctx, &call);
+  rec2.ew(fill);
+  rec2.ew(scale);
+  rec2.run(call);
+  dev::sync(ctx.stream);
+}
+
+}  // namespace pe

@@ -59,6 +59,24 @@ struct BondReq {
 };
 void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops);
 
+// The bond update's two local problems with substitute site tensors (one
+// batched run, float64 environments): N1, b1 of the first site with the
+// second replaced by s2, N2, b2 of the second with the first replaced by s1,
+// in the gated bond's scaling (device float64 outputs, sites' own order).
+struct FitReq {
+  peps_env* e;
+  int r, c;
+  const double* gate;
+  const double* s1;
+  const double* s2;
+  double* n1;
+  double* b1;
+  double* n2;
+  double* b2;
+  bool tr = false;
+};
+void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops);
+
 // <X|Y>, <X|X>, <Y|Y> of pairs of stored boundaries of one row (float64
 // tensors, (ket, bra) taken as one physical index), one batched run.
 struct OvReq {

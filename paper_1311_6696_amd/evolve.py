@@ -3,22 +3,18 @@ consumer of the library's environments.
 
 Each Trotter step applies exp(-tau S_l.S_m) on every nearest-neighbour bond
 in four sets of disjoint bonds (horizontal with even / odd left column,
-vertical with even / odd upper row), each set in two passes: the first pass
-refits the first site of every bond, the second the other site.  In a pass,
-one environment of the current state gives, through the C ABI, the norm
-environment N and the right-hand side b of the refitted site of every bond
-(the row sandwiches for horizontal bonds, the column sandwiches for
-vertical ones); the site is replaced by the solution of A' N = b, the ALS
-local problem of fitting G psi with only that site free (computed here on the
-host from the K x K matrices with a relative eigenvalue cutoff), rescaled
-to unit largest entry.  Refitting one site of a bond at a time keeps each
-update an exact least-squares fit; refitting both from one environment would
-let each site take up the whole change of the bond.  The second pass fits
-the gate applied to the state after the first pass, so each bond sees the
-gate twice per step (an effective step of 2 tau).  The bond dimension D stays fixed: the truncation of
-the evolved state is the optimisation itself.  With boundaries at lossless
-chi the energies are exact expectation values of the evolved PEPS, so they
-are bounded below by the exact ground-state energy.
+vertical with even / odd upper row).  For one set, one environment of the
+current state is built (with column boundaries for the vertical sets), and
+for every bond of the set the two new site tensors are found by alternating
+least squares on the fit of G psi (Sec. 2): with the second site held at S2,
+S1 solves S1 N1 = b1, then S2 solves S2 N2 = b2 with the new S1; N and b
+come from the library (``peps_bond_fit``: the bond's pair environment from
+the fixed boundaries, the substitutes in place of the sites), the K x K
+solves run here on the host with a relative eigenvalue cutoff, and the new
+tensors are rescaled to unit largest entry.  The bond dimension D stays
+fixed: the truncation of the evolved state is the fit itself.  With
+boundaries at lossless chi the energies are exact expectation values of the
+evolved PEPS, so they are bounded below by the exact ground-state energy.
 """
 import numpy as np
 
@@ -50,13 +46,15 @@ def energy_per_site(sess, A, chi):
     return float(np.sum(r["bond_h"]) + np.sum(r["bond_v"])) / (len(A) * len(A[0]))
 
 
-def full_update(sess, A, tau, steps, chi, cutoff=1e-12, every=1, log=None):
+def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None):
     """Evolve the site list A (numpy, (d, Dl, Du, Dr, Dd) each) for `steps`
-    Trotter steps of size tau; returns (A, [(step, energy per site)])."""
+    Trotter steps of size tau with `als` alternating sweeps per bond;
+    returns (A, [(step, energy per site)])."""
     import torch
     A = [[np.array(t, dtype=np.float64) for t in row] for row in A]
     Lr, Lc = len(A), len(A[0])
     g = torch.as_tensor(heisenberg_gate(tau), device="cuda")
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     trace = []
     for step in range(steps):
         for direction, parity in ((0, 0), (0, 1), (1, 0), (1, 1)):
@@ -67,17 +65,21 @@ def full_update(sess, A, tau, steps, chi, cutoff=1e-12, every=1, log=None):
             if not bonds:
                 continue
             other = [(r, c + 1) if direction == 0 else (r + 1, c) for r, c in bonds]
-            for side in (0, 1):
-                env = sess.env_boundary([binding.to_device(A)], chi, columns=direction == 1)[0]
-                sites = bonds if side == 0 else other
-                Ns, _ = sess.site_env([(env, r, c, direction) for r, c in sites])
-                bs, _ = sess.bond_env([(env, r, c, g, direction) for r, c in bonds])
-                env.free()
-                for k, (rr, cc) in enumerate(sites):
-                    N = Ns[k][0].cpu().numpy()
-                    b = bs[k][side].cpu().numpy()
-                    new = _solve(N, b, cutoff).reshape(A[rr][cc].shape)
-                    A[rr][cc] = new / np.abs(new).max()
+            env = sess.env_boundary([binding.to_device(A)], chi, columns=direction == 1)[0]
+            S1 = [A[r][c].copy() for r, c in bonds]
+            S2 = [A[r][c].copy() for r, c in other]
+            for _ in range(als):
+                for side in (0, 1):
+                    got, _ = sess.bond_fit([(env, r, c, direction, g, dev(s1), dev(s2))
+                                            for (r, c), s1, s2 in zip(bonds, S1, S2)])
+                    for k, (n1, b1, n2, b2) in enumerate(got):
+                        N, b = (n1, b1) if side == 0 else (n2, b2)
+                        S = S1 if side == 0 else S2
+                        new = _solve(N.cpu().numpy(), b.cpu().numpy(), cutoff).reshape(S[k].shape)
+                        S[k] = new / np.abs(new).max()
+            env.free()
+            for k, ((r, c), (r2, c2)) in enumerate(zip(bonds, other)):
+                A[r][c], A[r2][c2] = S1[k], S2[k]
         if (step + 1) % every == 0 or step + 1 == steps:
             e = energy_per_site(sess, A, chi)
             trace.append((step + 1, e))

@@ -48,6 +48,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.peps_site_env(None, None, 0, None) == -1
     assert lib.peps_bond_env(None, None, 0, None) == -1
     assert lib.peps_boundary_overlap(None, None, 0) == -1
+    assert lib.peps_bond_fit(None, None, 0, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -64,6 +65,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(binding.SiteReq) == 8 + 4 * 4 + 3 * 8   # r, c, dir and padding
     assert C.sizeof(binding.BondReq) == 8 + 4 * 4 + 3 * 8
     assert C.sizeof(binding.OverlapReq) == 2 * 8 + 2 * 4 + 3 * 8
+    assert C.sizeof(binding.FitReq) == 8 + 4 * 4 + 7 * 8
 
 
 def test_statistics_table_size_matches_header():

@@ -362,3 +362,51 @@ def test_vertical_needs_column_environment(sess):
     with pytest.raises(binding.PepsError):   # bond (2,0)-(3,0) leaves the lattice
         sess.ctx.bond_env_raw([(env, 2, 0, g.data_ptr(), 1 << 20, 0, 1)])
     env.free()
+
+
+# --- the bond update's local problems with substitute tensors ----------------
+
+@pytest.mark.parametrize("case", [("normal_unit", 3, 4, 4, 4), ("aniso", 4, 3, 5, 3)])
+def test_bond_fit_parity_both_directions(sess, case):
+    """N and b of both sites of every bond, with the sites replaced by
+    random substitutes, from the row (dir 0) and column (dir 1) sandwiches."""
+    dist, Lr, Lc, chi, H = case
+    say(f"bond fit {case}")
+    if dist == "aniso":
+        rng = np.random.default_rng(420)
+        A = [[rng.standard_normal((2, 1 if c == 0 else 2, 1 if r == 0 else 3, 1 if c == Lc - 1 else 2,
+                                   1 if r == Lr - 1 else 3)) for c in range(Lc)] for r in range(Lr)]
+    else:
+        A = make_peps(Lr, Lc, 2, dist, 421 + Lr * Lc)
+    G = _gate(11)
+    env = sess.env_boundary([binding.to_device(A)], chi, "f64", H, columns=True)[0]
+    ref, cols = api.env_boundary(A, chi, H), api.env_columns(A, chi, H)
+    rng = np.random.default_rng(7)
+    for dr in (0, 1):
+        bonds = ([(r, c) for r in range(Lr) for c in range(Lc - 1)] if dr == 0
+                 else [(r, c) for r in range(Lr - 1) for c in range(Lc)])
+        subs = []
+        for r, c in bonds:
+            r2, c2 = (r, c + 1) if dr == 0 else (r + 1, c)
+            subs.append((rng.standard_normal(A[r][c].shape), rng.standard_normal(A[r2][c2].shape)))
+        got, _ = sess.bond_fit([(env, r, c, dr, _dev(G), _dev(s1), _dev(s2)) for (r, c), (s1, s2) in zip(bonds, subs)])
+        for (r, c), (s1, s2), g in zip(bonds, subs, got):
+            want = (api.bond_fit(ref, r, c, G, s1, s2) if dr == 0 else api.bond_fit_vertical(cols, r, c, G, s1, s2))
+            check_b(g, want, TOL64)
+    env.free()
+
+
+def test_bond_fit_with_stored_tensors_equals_site_and_bond_env(sess):
+    """Substitutes equal to the stored tensors: the site and bond
+    environments (GPU against GPU)."""
+    say("bond fit with the stored tensors")
+    A = make_peps(4, 4, 2, "near_product", 431)
+    env = sess.env_boundary([binding.to_device(A)], 4, "f64", 4)[0]
+    G = _dev(_heisenberg_gate(0.1))
+    (n1, b1, n2, b2), = sess.bond_fit([(env, 2, 1, 0, G, _dev(A[2][1]), _dev(A[2][2]))])[0]
+    (bl, br), = sess.bond_env([(env, 2, 1, G)])[0]
+    Ns, _ = sess.site_env([(env, 2, 1), (env, 2, 2)])
+    env.free()
+    for x, y in ((n1, Ns[0][0]), (n2, Ns[1][0]), (b1, bl), (b2, br)):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.abs(x - y).max() < 1e-12 * np.abs(y).max()
