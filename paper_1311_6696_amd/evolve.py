@@ -46,10 +46,11 @@ def energy_per_site(sess, A, chi):
     return float(np.sum(r["bond_h"]) + np.sum(r["bond_v"])) / (len(A) * len(A[0]))
 
 
-def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None):
+def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None, sequential=False):
     """Evolve the site list A (numpy, (d, Dl, Du, Dr, Dd) each) for `steps`
     Trotter steps of size tau with `als` alternating sweeps per bond;
-    returns (A, [(step, energy per site)])."""
+    sequential: a new environment for every bond instead of one per bond set.
+    Returns (A, [(step, energy per site)])."""
     import torch
     A = [[np.array(t, dtype=np.float64) for t in row] for row in A]
     Lr, Lc = len(A), len(A[0])
@@ -62,30 +63,34 @@ def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None
                 bonds = [(r, c) for r in range(Lr) for c in range(parity, Lc - 1, 2)]
             else:
                 bonds = [(r, c) for r in range(parity, Lr - 1, 2) for c in range(Lc)]
-            if not bonds:
-                continue
-            other = [(r, c + 1) if direction == 0 else (r + 1, c) for r, c in bonds]
-            env = sess.env_boundary([binding.to_device(A)], chi, columns=direction == 1)[0]
-            S1 = [A[r][c].copy() for r, c in bonds]
-            S2 = [A[r][c].copy() for r, c in other]
-            for _ in range(als):
-                for side in (0, 1):
-                    got, _ = sess.bond_fit([(env, r, c, direction, g, dev(s1), dev(s2))
-                                            for (r, c), s1, s2 in zip(bonds, S1, S2)])
-                    for k, (n1, b1, n2, b2) in enumerate(got):
-                        N, b = (n1, b1) if side == 0 else (n2, b2)
-                        S = S1 if side == 0 else S2
-                        new = _solve(N.cpu().numpy(), b.cpu().numpy(), cutoff).reshape(S[k].shape)
-                        S[k] = new / np.abs(new).max()
-            env.free()
-            for k, ((r, c), (r2, c2)) in enumerate(zip(bonds, other)):
-                A[r][c], A[r2][c2] = S1[k], S2[k]
+            for group in ([[b] for b in bonds] if sequential else [bonds]):
+                _update_bonds(sess, A, group, direction, g, chi, als, cutoff, dev)
         if (step + 1) % every == 0 or step + 1 == steps:
             e = energy_per_site(sess, A, chi)
             trace.append((step + 1, e))
             if log:
                 log(f"step {step + 1}: energy per site {e:.8f}")
     return A, trace
+
+
+def _update_bonds(sess, A, bonds, direction, g, chi, als, cutoff, dev):
+    """Alternating fits of the disjoint bonds `bonds` from one environment."""
+    other = [(r, c + 1) if direction == 0 else (r + 1, c) for r, c in bonds]
+    env = sess.env_boundary([binding.to_device(A)], chi, columns=direction == 1)[0]
+    S1 = [A[r][c].copy() for r, c in bonds]
+    S2 = [A[r][c].copy() for r, c in other]
+    for _ in range(als):
+        for side in (0, 1):
+            got, _ = sess.bond_fit([(env, r, c, direction, g, dev(s1), dev(s2))
+                                    for (r, c), s1, s2 in zip(bonds, S1, S2)])
+            for k, (n1, b1, n2, b2) in enumerate(got):
+                N, b = (n1, b1) if side == 0 else (n2, b2)
+                S = S1 if side == 0 else S2
+                new = _solve(N.cpu().numpy(), b.cpu().numpy(), cutoff).reshape(S[k].shape)
+                S[k] = new / np.abs(new).max()
+    env.free()
+    for k, ((r, c), (r2, c2)) in enumerate(zip(bonds, other)):
+        A[r][c], A[r2][c2] = S1[k], S2[k]
 
 
 def neel_start(Lr, Lc, D, noise=1e-2, seed=0):
