@@ -10,8 +10,11 @@ least squares on the fit of G psi (Sec. 2): with the second site held at S2,
 S1 solves S1 N1 = b1, then S2 solves S2 N2 = b2 with the new S1; N and b
 come from the library (``peps_bond_fit``: the bond's pair environment from
 the fixed boundaries, the substitutes in place of the sites), the K x K
-solves run here on the host with a relative eigenvalue cutoff, and the new
-tensors are rescaled to unit largest entry.  The bond dimension D stays
+solves run here on the host with a relative eigenvalue cutoff; the two new
+tensors are then split symmetrically over their shared bond (SVD of their
+product, the square root of the singular values to each side: the bond's
+gauge, which the fit leaves free, would otherwise drift and spoil the
+conditioning of later fits) and rescaled to unit largest entry.  The bond dimension D stays
 fixed: the truncation of the evolved state is the fit itself.  With
 boundaries at lossless chi the energies are exact expectation values of the
 evolved PEPS, so they are bounded below by the exact ground-state energy.
@@ -46,10 +49,13 @@ def energy_per_site(sess, A, chi):
     return float(np.sum(r["bond_h"]) + np.sum(r["bond_v"])) / (len(A) * len(A[0]))
 
 
-def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None, sequential=False):
+def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None, sequential=False,
+                balance=True):
     """Evolve the site list A (numpy, (d, Dl, Du, Dr, Dd) each) for `steps`
     Trotter steps of size tau with `als` alternating sweeps per bond;
-    sequential: a new environment for every bond instead of one per bond set.
+    sequential: a new environment for every bond instead of one per bond set;
+    balance: after each bond's fit, split the product of its two tensors over
+    the shared bond symmetrically (SVD, same product).
     Returns (A, [(step, energy per site)])."""
     import torch
     A = [[np.array(t, dtype=np.float64) for t in row] for row in A]
@@ -64,7 +70,7 @@ def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None
             else:
                 bonds = [(r, c) for r in range(parity, Lr - 1, 2) for c in range(Lc)]
             for group in ([[b] for b in bonds] if sequential else [bonds]):
-                _update_bonds(sess, A, group, direction, g, chi, als, cutoff, dev)
+                _update_bonds(sess, A, group, direction, g, chi, als, cutoff, dev, balance)
         if (step + 1) % every == 0 or step + 1 == steps:
             e = energy_per_site(sess, A, chi)
             trace.append((step + 1, e))
@@ -73,7 +79,23 @@ def full_update(sess, A, tau, steps, chi, cutoff=1e-12, als=3, every=1, log=None
     return A, trace
 
 
-def _update_bonds(sess, A, bonds, direction, g, chi, als, cutoff, dev):
+def _balance(S1, S2, direction):
+    """Rebalance the shared bond of S1 (left or upper) and S2 without changing
+    their product: SVD of the product over the bond, sqrt(s) to each side."""
+    ax1, ax2 = (3, 1) if direction == 0 else (4, 2)    # S1's right/down leg, S2's left/up leg
+    t1 = np.moveaxis(S1, ax1, -1)
+    t2 = np.moveaxis(S2, ax2, 0)
+    D = t1.shape[-1]
+    M = t1.reshape(-1, D) @ t2.reshape(D, -1)
+    U, s, Vh = np.linalg.svd(M, full_matrices=False)
+    U, s, Vh = U[:, :D], s[:D], Vh[:D]
+    r = np.sqrt(s)
+    n1 = np.moveaxis((U * r).reshape(t1.shape), -1, ax1)
+    n2 = np.moveaxis((r[:, None] * Vh).reshape(t2.shape), 0, ax2)
+    return n1, n2
+
+
+def _update_bonds(sess, A, bonds, direction, g, chi, als, cutoff, dev, balance=False):
     """Alternating fits of the disjoint bonds `bonds` from one environment."""
     other = [(r, c + 1) if direction == 0 else (r + 1, c) for r, c in bonds]
     env = sess.env_boundary([binding.to_device(A)], chi, columns=direction == 1)[0]
@@ -90,7 +112,8 @@ def _update_bonds(sess, A, bonds, direction, g, chi, als, cutoff, dev):
                 S[k] = new / np.abs(new).max()
     env.free()
     for k, ((r, c), (r2, c2)) in enumerate(zip(bonds, other)):
-        A[r][c], A[r2][c2] = S1[k], S2[k]
+        s1, s2 = _balance(S1[k], S2[k], direction) if balance else (S1[k], S2[k])
+        A[r][c], A[r2][c2] = s1 / np.abs(s1).max(), s2 / np.abs(s2).max()
 
 
 def neel_start(Lr, Lc, D, noise=1e-2, seed=0):
