@@ -233,6 +233,9 @@ def side_convergence(sess, binding, torch):
     return out
 
 
+EVOLUTION = {"steps": 20, "taus": (0.1, 0.05, 0.02)}
+
+
 def side_evolution(sess, binding, torch):
     """Imaginary-time full updates of the 4x4 Heisenberg model from a Neel
     start (the driver over the site and bond environments), D = 2, 3, 4 at
@@ -240,8 +243,8 @@ def side_evolution(sess, binding, torch):
     Trotter step (four environments plus six bond fits per bond set)."""
     from paper_1311_6696_amd import evolve
     out = {}
-    taus = (0.1, 0.05, 0.02)
-    for D, chi, steps in ((2, 16, 20), (3, 81, 20), (4, 256, 20)):
+    taus, n = EVOLUTION["taus"], EVOLUTION["steps"]
+    for D, chi, steps in ((2, 16, n), (3, 81, n), (4, 256, n)):
         note(f"evolution 4x4 D={D}")
         A = evolve.neel_start(4, 4, D, 1e-1, 0)
         torch.cuda.synchronize()
@@ -255,7 +258,7 @@ def side_evolution(sess, binding, torch):
         out[f"D{D}"] = {"chi": chi, "tau": list(taus), "steps": len(taus) * steps, "energy_per_site": [e for _, e in trace],
                         "best": min(e for _, e in trace), "exact": -0.57432544,
                         "ms_per_step_incl_energy_checks": 1000.0 * t / (len(taus) * steps)}
-    out["workload"] = ("4x4 OBC Heisenberg, Neel start with 0.1 noise, exp(-tau S.S) gates (tau 0.1, 0.05, 0.02), "
+    out["workload"] = ("4x4 OBC Heisenberg, Neel start with 0.1 noise, exp(-tau S.S) gates (tau " + ", ".join(map(str, taus)) + "), "
                        "3 alternating fits per bond, bond rebalancing")
     return out
 
@@ -283,6 +286,8 @@ def main():
                          "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices), "
                          "convergence (energy error against chi and cluster size n), evolution "
                          "(4x4 imaginary-time full updates)")
+    ap.add_argument("--evolution-steps", type=int, default=20, help="Trotter steps per tau of the evolution workload")
+    ap.add_argument("--evolution-taus", default="0.1,0.05,0.02", help="tau schedule of the evolution workload")
     ap.add_argument("--autotune", action="store_true",
                     help="time the contraction launch shapes on one untimed environment first")
     ap.add_argument("--graphs", action="store_true",
@@ -291,6 +296,8 @@ def main():
                     help="one device-to-device copy of this many MiB before the run: a plain copy kernel of "
                          "known size against which hardware byte counters are scaled")
     args = ap.parse_args()
+    EVOLUTION["steps"] = args.evolution_steps
+    EVOLUTION["taus"] = tuple(float(x) for x in args.evolution_taus.split(","))
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path has no multi-GPU component); got --gpus {args.gpus}",
               file=sys.stderr)
