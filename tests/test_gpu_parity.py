@@ -343,6 +343,47 @@ def test_8x8_D4_chi32_columns_full_parity(sess):
     assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
 
 
+def test_10x10_D6_chi72_properties(sess):
+    """10x10, D=6, N(0,1) unit-norm sites, chi=72 (the precision workload's
+    size, too large for the oracle): properties that hold at any size.
+    Bounds of <S^z> and <S.S>; the site environments reproduce <S^z> of the
+    row sandwich (A N A = sign, (S^z A) N A = <S^z> sign); FP32 agrees with
+    FP64; boundaries have unit norm and the FP32 ones fidelity ~1."""
+    from oracle import spin
+    say("10x10 D=6 chi=72 properties")
+    A = workload_peps("10x10_D6_chi72")
+    c = WORKLOADS["10x10_D6_chi72"]
+    dev = binding.to_device(A)
+    e64 = sess.env_boundary([dev], c["chi"], "f64", 4)[0]
+    e32 = sess.env_boundary([dev], c["chi"], "f32", 4)[0]
+    r64, = sess.expect([e64])
+    r32, = sess.expect([e32])
+    assert np.all(np.abs(r64["sz"]) <= 0.5 + 1e-9)
+    for k in ("bond_h", "bond_v"):
+        assert np.all(r64[k] >= -0.75 - 1e-9) and np.all(r64[k] <= 0.25 + 1e-9)
+        assert np.abs(r32[k] - r64[k]).max() < 1e-4
+    sites = [(0, 0), (0, 5), (4, 4), (9, 9)]
+    got, _ = sess.site_env([(e64, r, q) for r, q in sites])
+    for (r, q), (N, _, sign) in zip(sites, got):
+        N = N.cpu().numpy()
+        a = A[r][q].reshape(2, -1)
+        sa = sandwich_apply(spin.SZ, A[r][q]).reshape(2, -1)
+        assert abs(np.einsum("pk,kj,pj->", a, N, a) - sign) < 1e-9
+        assert abs(np.einsum("pk,kj,pj->", sa, N, a) * sign - r64["sz"][r, q]) < 1e-9
+    ov = sess.ctx.boundary_overlap([(e64, e32, side, k) for side in (0, 1) for k in (1, 5, 9)])
+    for xy, xx, yy in ov:
+        assert abs(xx - 1.0) < 1e-10
+        assert 1.0 - abs(xy) / np.sqrt(xx * yy) < 1e-6
+    e64.free()
+    e32.free()
+
+
+def sandwich_apply(O, A):
+    """O on the physical leg of a site tensor (the operator convention of the
+    sandwich: sum_q O[p, q] A[q, ...])."""
+    return np.tensordot(O, A, axes=([1], [0]))
+
+
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 5e-2)])
 def test_precision_forms_error(sess, dtype, tol):
     """FP32 / BF16 bulk contractions (FP64 QR and norms): error vs the FP64 oracle."""
