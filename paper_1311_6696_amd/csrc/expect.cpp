@@ -787,14 +787,16 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
     if (!cv.empty()) rec.ew(cv);
   }
 
-  // Per bond (c, c+1) of row r, with both bra tensors taken out:
+  // Per bond (c, c+1) of row r:
   //   X[l,u,d,m,v,g,y,e]  = L[c] T[c] B[c]
   //   Z[R,S,e,U,V,y,D,G]  = R[c+2] T[c+1] B[c+1]
   //   Th[p,P,l,u,d,U,R,D] = gate[p,P,q,Q] A_c[q,l,u,r,d] A_c+1[Q,r,U,R,D]
-  //   W[S,e,V,y,G,p,P,l,u,d] = Z Th,   E[p,P,m,v,g,V,S,G] = X W,
-  //   b_left = E . A_c+1 (bra),  b_right = E . A_c (bra).
-  // Leg orders are chosen so that every index group of each contraction
-  // merges into at most four strided sub-dimensions.
+  //   b_left  = X . ((Z . A_c+1 bra) . Th)   (the right block takes its bra first)
+  //   b_right = ((X . A_c bra) . Th) . Z     (the left block takes its bra first)
+  // so that no intermediate carries both bra tensors' open legs (the pair
+  // environment would cost D^6 chi^2 d^2 entries per bond).  Leg orders are
+  // chosen so that every index group of each contraction merges into at
+  // most four strided sub-dimensions.
   struct Dims {
     int64_t d, x, y, z, a, e, f, Dl, Du, Dd, R, U, D;
   };
@@ -818,8 +820,8 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
                       + q.z * q.R * q.R * q.e * q.U * q.U                     // Z1
                       + q.R * q.R * q.e * q.U * q.U * q.y * q.D * q.D         // Z
                       + 2 * q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D   // A_c A_c+1, Th
-                      + q.R * q.e * q.U * q.y * q.D * q.d * q.d * q.Dl * q.Du * q.Dd   // W
-                      + q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D;     // E
+                      + 2 * q.R * q.e * q.U * q.y * q.D * q.d * j.Dl[c + 1]   // Zb, Wr
+                      + 2 * q.Dl * q.Du * q.Dd * q.y * q.e * q.d * j.Dl[c + 1];   // Xb, Wl
     sz[i] = esz * (size_t)n;
   }
   flops = 0.0;
@@ -857,10 +859,6 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
                     {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
       TV th = dense(get(q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D), cdt, "pPludURD",
                     {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
-      TV W = dense(get(q.R * q.e * q.U * q.y * q.D * q.d * q.d * q.Dl * q.Du * q.Dd), cdt, "SeVyGpPlud",
-                   {q.R, q.e, q.U, q.y, q.D, q.d, q.d, q.Dl, q.Du, q.Dd});
-      TV E = dense(get(q.d * q.d * q.Dl * q.Du * q.Dd * q.U * q.R * q.D), cdt, "pPmvgVSG",
-                   {q.d, q.d, q.Dl, q.Du, q.Dd, q.U, q.R, q.D});
       const Site& s1 = *j.s[c];
       const Site& s2 = *j.s[c + 1];
       add(0, tc_build(x1, L, T1));
@@ -869,19 +867,27 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
       add(1, tc_build(X, x1, B1));
       add(1, tc_build(Z, z1, B2));
       add(1, tc_build(th, G, aa));
-      add(2, tc_build(W, Z, th));
-      add(3, tc_build(E, X, W));
       // on a transposed lattice b is written in the original site's leg
       // order (l, u, r, d) = (u, l, d, r) of the transpose
       const bool tr = req[i].tr;
-      if (rawl[i])
+      if (rawl[i]) {
+        TV zb = dense(get(q.R * q.e * q.U * q.y * q.D * q.d * h), cdt, "ReUyDPs", {q.R, q.e, q.U, q.y, q.D, q.d, h});
+        TV wl = dense(get(q.e * q.y * h * q.d * q.Dl * q.Du * q.Dd), cdt, "eysplud", {q.e, q.y, h, q.d, q.Dl, q.Du, q.Dd});
+        add(2, tc_build(zb, Z, site_tv(s2, OP_ID, false, cdt, "PsVSG")));
+        add(3, tc_build(wl, zb, th));
         add(4, tc_build(tr ? dense(rawl[i], cdt, "pvmgs", {q.d, q.Du, q.Dl, q.Dd, h})
                            : dense(rawl[i], cdt, "pmvsg", {q.d, q.Dl, q.Du, h, q.Dd}),
-                        E, site_tv(s2, OP_ID, false, cdt, "PsVSG")));
-      if (rawr[i])
+                        X, wl));
+      }
+      if (rawr[i]) {
+        TV xb = dense(get(q.Dl * q.Du * q.Dd * q.y * q.e * q.d * h), cdt, "ludyeps", {q.Dl, q.Du, q.Dd, q.y, q.e, q.d, h});
+        TV wr = dense(get(h * q.d * q.R * q.e * q.U * q.y * q.D), cdt, "sPReUyD", {h, q.d, q.R, q.e, q.U, q.y, q.D});
+        add(2, tc_build(xb, X, site_tv(s1, OP_ID, false, cdt, "pmvsg")));
+        add(3, tc_build(wr, xb, th));
         add(4, tc_build(tr ? dense(rawr[i], cdt, "PVsGS", {q.d, q.U, h, q.D, q.R})
                            : dense(rawr[i], cdt, "PsVSG", {q.d, h, q.U, q.R, q.D}),
-                        E, site_tv(s1, OP_ID, false, cdt, "pmvsg")));
+                        wr, Z));
+      }
     }
     for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
     for (void* p : tmp) scr.put(p);
@@ -1106,7 +1112,7 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
     rec.flush(call);
   }
 
-  // pair environment E (as for the gated bond), b1 = E . S2, b2 = E . S1,
+  // b1 and b2 (as for the gated bond, the substitutes as the bras),
   // N1 = L[c] T B R1, N2 = L2 T B R[c+2]; leg orders as in the site and bond
   // environments (the transposed forms write the sites' own order)
   for (size_t i = 0; i < req.size(); ++i) {
@@ -1141,20 +1147,25 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
     TV Z = dense(get(R * R * e * U * U * y * D * D), cdt, "RSeUVyDG", {R, R, e, U, U, y, D, D});
     TV aa = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "qQludURD", {d, d, Dl, Du, Dd, U, R, D});
     TV th = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "pPludURD", {d, d, Dl, Du, Dd, U, R, D});
-    TV W = dense(get(R * e * U * y * D * d * d * Dl * Du * Dd), cdt, "SeVyGpPlud", {R, e, U, y, D, d, d, Dl, Du, Dd});
-    TV E = dense(get(d * d * Dl * Du * Dd * U * R * D), cdt, "pPmvgVSG", {d, d, Dl, Du, Dd, U, R, D});
+    TV zb = dense(get(R * e * U * y * D * d * h), cdt, "ReUyDPs", {R, e, U, y, D, d, h});
+    TV wl = dense(get(e * y * h * d * Dl * Du * Dd), cdt, "eysplud", {e, y, h, d, Dl, Du, Dd});
+    TV xb = dense(get(Dl * Du * Dd * y * e * d * h), cdt, "ludyeps", {Dl, Du, Dd, y, e, d, h});
+    TV wr = dense(get(h * d * R * e * U * y * D), cdt, "sPReUyD", {h, d, R, e, U, y, D});
     add(0, tc_build(x1, L, T1));
     add(0, tc_build(z1, Rr, T2));
     add(0, tc_build(aa, site_tv(*j.s[c], OP_ID, false, cdt, "qlurd"), site_tv(*j.s[c + 1], OP_ID, false, cdt, "QrURD")));
     add(1, tc_build(X, x1, B1));
     add(1, tc_build(Z, z1, B2));
     add(1, tc_build(th, G, aa));
-    add(2, tc_build(W, Z, th));
-    add(3, tc_build(E, X, W));
+    // b1 = X . ((Z . S2 bra) . Th), b2 = ((X . S1 bra) . Th) . Z (as for the gated bond)
+    add(2, tc_build(zb, Z, site_tv(v2[i], OP_ID, false, cdt, "PsVSG")));
+    add(2, tc_build(xb, X, site_tv(v1[i], OP_ID, false, cdt, "pmvsg")));
+    add(3, tc_build(wl, zb, th));
+    add(3, tc_build(wr, xb, th));
     add(4, tc_build(tr ? dense(req[i].b1, cdt, "pvmgs", {d, Du, Dl, Dd, h}) : dense(req[i].b1, cdt, "pmvsg", {d, Dl, Du, h, Dd}),
-                    E, site_tv(v2[i], OP_ID, false, cdt, "PsVSG")));
+                    X, wl));
     add(4, tc_build(tr ? dense(req[i].b2, cdt, "PVsGS", {d, U, h, D, R}) : dense(req[i].b2, cdt, "PsVSG", {d, h, U, R, D}),
-                    E, site_tv(v1[i], OP_ID, false, cdt, "pmvsg")));
+                    wr, Z));
     // N1 from L[c], T[c], B[c], R1; N2 from L2, T[c+1], B[c+1], R[c+2]
     for (int k = 0; k < 2; ++k) {
       const int cc = c + k;
