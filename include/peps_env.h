@@ -75,7 +75,7 @@ typedef struct {
   int32_t chi;          /* boundary bond dimension D' >= 1 */
   int32_t dtype;        /* peps_dtype */
   int32_t halfsweeps;   /* ALS half-sweeps per truncated row, >= 1 (default 4 if 0) */
-  int32_t flags;        /* 0, or PEPS_OPTS_PER_STATE | PEPS_OPTS_COLUMNS (peps_env_boundary only) */
+  int32_t flags;        /* 0, PEPS_OPTS_PER_STATE (peps_env_boundary only), PEPS_OPTS_COLUMNS */
   uint64_t seed;        /* SplitMix64 key of the ALS start tensors */
 } peps_env_opts;
 
@@ -92,7 +92,10 @@ typedef struct {
  * single-column sandwich of column c instead of the two-row sandwich of
  * rows r and r+1: a different approximation at truncated chi, the same
  * values at lossless chi.  The transposed sites are strided views of the
- * packed sites, not copies.  Rejected by peps_cluster_env. */
+ * packed sites, not copies.  With peps_cluster_env every window also gets
+ * the boundaries of its transpose (closed by the same CU_0 matrices), and
+ * its bond downwards comes from the single-column sandwich of the centre's
+ * column. */
 #define PEPS_OPTS_COLUMNS 2
 
 /* Cluster window around the centre site (ci, cj) of state `state`,

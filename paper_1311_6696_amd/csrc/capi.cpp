@@ -149,7 +149,8 @@ void* make_one(Rec& rec, Arena& arena, int cdt) {
 }  // namespace
 
 void validate_state_public(const peps_state& s, int idx) { validate_state(s, idx); }
-Opts make_opts_public(const peps_env_opts* o) { return make_opts(o); }
+Opts make_opts_public(const peps_env_opts* o) { return make_opts(o, PEPS_OPTS_COLUMNS); }
+std::unique_ptr<peps_env> transposed_env_public(const peps_env& e) { return transposed_env(e); }
 void pack_state_public(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out) {
   pack_state(rec, arena, s, cdt, out);
 }

@@ -74,6 +74,7 @@ using namespace pe;
 namespace pe {
 void validate_state_public(const peps_state& s, int idx);
 Opts make_opts_public(const peps_env_opts* o);
+std::unique_ptr<peps_env> transposed_env_public(const peps_env& e);
 void pack_state_public(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out);
 void* make_one_public(Rec& rec, Arena& arena, int cdt);
 peps_status guarded_public(const std::function<void()>& f);
@@ -186,8 +187,17 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
         L.tau.push_back(x.r0 == 0 ? data->one : sigma(i, 0, x.r0 - 1, c));
         L.beta.push_back(x.r1 == s.rows - 1 ? data->one : sigma(i, 1, s.rows - 2 - x.r1, c));
       }
+      if (o.columns) {   // the transposed window: its centre row is the centre's column
+        e->col = transposed_env_public(*e);
+        e->col->window = true;
+        e->col->ci = e->cj;
+        e->col->cj = e->ci;
+      }
     }
-    plan_boundaries(C, made);
+    std::vector<peps_env*> all(made);
+    for (peps_env* e : made)
+      if (e->col) all.push_back(e->col.get());
+    plan_boundaries(C, all);
     for (int w = 0; w < n_win; ++w) out[w] = made[w];
   });
   if (status != PEPS_OK)

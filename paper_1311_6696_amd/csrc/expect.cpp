@@ -564,7 +564,10 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       double num = 0.0;
       for (int t = 0; t < 3; ++t) num += BOND_W[t] * D[2 * Lc + 1 + 3 * c + t];
       const double v = num / (std::sqrt(nu[c + 1] * nu[c + 2]) * D[c + 2]);
-      if (j.tr) {
+      if (j.tr && e->window) {
+        // the transposed window's centre bond to the right is the centre's bond downwards
+        if (c == e->cj && j.r == e->ci) eo.bond[1] = v;
+      } else if (j.tr) {
         // bond (j.r, c)-(j.r, c+1) of the transpose is the vertical bond (c, j.r)-(c+1, j.r)
         eo.bond[(size_t)Lc * (Lr - 1) + (size_t)c * Lr + j.r] = v;
       } else if (e->window) {

@@ -188,21 +188,45 @@ def test_columns_mixed_with_row_only_envs(sess):
     assert max_obs_diff(r2, api.expect(api.env_boundary(A2, 4, 3))) < TOL64
 
 
-def test_columns_rejected_for_clusters(sess):
-    """The column flag belongs to whole-lattice environments only."""
-    import ctypes as C
-    say("columns flag on a cluster call")
-    dev = binding.to_device(make_peps(3, 3, 2, "uniform", 5))
+def test_columns_for_cluster_windows(sess):
+    """Cluster windows with column boundaries: the bond downwards from the
+    single-column sandwich of the transposed window, against the oracle."""
+    from oracle import cluster
+    from oracle.boundary import whole_lattice
+    say("columns in cluster windows")
+    L, n, chi = 5, 3, 4
+    A = make_peps(L, L, 2, "near_product", 501)
+    wins = []
+    for (i, j) in [(0, 0), (2, 2), (3, 1), (1, 4)]:
+        r0, r1 = cluster.window_bounds(i, n, L)
+        c0, c1 = cluster.window_bounds(j, n, L)
+        wins.append((0, r0, r1, c0, c1, i, j))
+    dev = binding.to_device(A)
     st = binding.state_of(dev)
     ctx = sess.ctx
-    o = ctx.opts(4)
+    import ctypes as C
+    o = ctx.opts(chi)
     o.flags = binding.OPTS_COLUMNS
     arr = (binding.State * 1)(st.struct())
-    w = (binding.Window * 1)(binding.Window(0, 0, 2, 0, 2, 1, 1))
-    out = (C.c_void_p * 1)()
-    code = ctx.lib.peps_cluster_env(ctx.handle, arr, 1, w, 1, C.byref(o), out)
-    assert code != 0 and out[0] is None
-    assert b"flags" in ctx.lib.peps_last_error()
+    w = (binding.Window * len(wins))(*[binding.Window(*x) for x in wins])
+    out = (C.c_void_p * len(wins))()
+    binding._check(ctx.lib, ctx.lib.peps_cluster_env(ctx.handle, arr, 1, w, len(wins), C.byref(o), out))
+    envs = [binding.Env(ctx, out[k], x[2] - x[1] + 1, x[4] - x[3] + 1, window=True) for k, x in enumerate(wins)]
+    res = sess.expect(envs)
+    for e in envs:
+        e.free()
+    sep = cluster.SeparableEnv(whole_lattice(A))
+    for x, r in zip(wins, res):
+        _, r0, r1, c0, c1, i, j = x
+        win = cluster.window_lattice(sep, r0, r1, c0, c1)
+        ref = api.expect(api.env_boundary(win, chi), rows=[i - r0], columns=api.env_columns(win, chi))
+        assert abs(r["sz"] - ref["sz"][i - r0, j - c0]) < TOL64
+        if j < c1:
+            assert abs(r["right"] - ref["bond_h"][i - r0, j - c0]) < TOL64
+        if i < r1:
+            assert abs(r["down"] - ref["bond_v"][i - r0, j - c0]) < TOL64
+        else:
+            assert np.isnan(r["down"])
 
 
 # --- boundary overlaps (boundary fidelity) -------------------------------------
