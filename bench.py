@@ -125,8 +125,8 @@ def side_clusters(sess, binding, torch):
                 wins.append((0, r0, r1, c0, c1, i, j))
         note(f"cluster workload n={n}")
 
-        def run():
-            envs = sess.cluster_env([st], wins, cfg["chi"], "f32", 4)
+        def run(columns=False):
+            envs = sess.cluster_env([st], wins, cfg["chi"], "f32", 4, columns=columns)
             res = sess.expect(envs)
             for e in envs:
                 e.free()
@@ -137,6 +137,11 @@ def side_clusters(sess, binding, torch):
         out[f"n{n}"] = {"windows": len(wins), "windows_per_s": len(wins) / t, "s_per_call": t,
                         "tflops": fl / t / 1e12, "pct_f32_peak": 100.0 * fl / t / 1e12 / PEAK["f32"],
                         "tflop_per_call": fl / 1e12}
+        # the same windows with the bond downwards from the transposed window
+        run(True)
+        rc, tc = timed(torch, lambda: run(True), 1)
+        out[f"n{n}"]["columns"] = {"s_per_call": tc, "speedup": t / tc, "tflop_per_call": sum(r["flops"] for r in rc) / 1e12,
+                                   "max_down_gap": float(np.nanmax([abs(a["down"] - b["down"]) for a, b in zip(res, rc)]))}
     out["workload"] = "16x16 OBC PEPS, d=2, D=6, near-product, chi=36, all 256 windows per n, FP32 contractions"
     return out
 

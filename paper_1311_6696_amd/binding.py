@@ -240,12 +240,13 @@ class Context:
             _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, o, out))
         return [Env(self, out[i], s.rows, s.cols, shapes=s.shapes) for i, s in enumerate(states)]
 
-    def cluster_env_raw(self, states, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+    def cluster_env_raw(self, states, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
         n = len(states)
         arr = (State * n)(*[s.struct() for s in states])
         w = (Window * len(windows))(*[Window(*[int(x) for x in win]) for win in windows])
         out = (C.c_void_p * len(windows))()
         o = self.opts(chi, dtype, halfsweeps, seed)
+        o.flags = OPTS_COLUMNS if columns else 0
         _check(self.lib, self.lib.peps_cluster_env(self.handle, arr, n, w, len(windows), C.byref(o), out))
         return [Env(self, out[i], win[2] - win[1] + 1, win[4] - win[3] + 1, window=True,
                     shapes=[row[win[3]: win[4] + 1] for row in states[win[0]].shapes[win[1]: win[2] + 1]])
@@ -379,9 +380,9 @@ class Session:
         states = [state_of(t) for t in tensors_list]
         return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed, columns)
 
-    def cluster_env(self, tensors_list, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+    def cluster_env(self, tensors_list, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
         states = [state_of(t) for t in tensors_list]
-        return self.ctx.cluster_env_raw(states, windows, chi, dtype, halfsweeps, seed)
+        return self.ctx.cluster_env_raw(states, windows, chi, dtype, halfsweeps, seed, columns)
 
     def expect(self, envs):
         return self.ctx.expect(envs)
