@@ -104,6 +104,15 @@ def side_precision(sess, binding, torch):
                    "max_bond_err_vs_f64": float(max(np.max(np.abs(r["bond_h"] - ref["bond_h"])),
                                                     np.max(np.abs(r["bond_v"] - ref["bond_v"]))))}
         out[dt]["speedup_vs_f64"] = out["f64"]["s_per_env"] / t
+    # FP64 with the vertical bonds from the column boundaries
+    note("precision workload f64 with column boundaries")
+    run = lambda: run_steps(sess, st, cfg["chi"], "f64", 4, 1, columns=True)
+    run()
+    r, t = timed(torch, run, 1)
+    out["f64_columns"] = {"env_per_s": 1.0 / t, "s_per_env": t, "tflop_per_env": r["flops"] / 1e12,
+                          "speedup_vs_f64": out["f64"]["s_per_env"] / t,
+                          "max_bond_v_gap_vs_two_row": float(np.max(np.abs(r["bond_v"] - ref["bond_v"]))),
+                          "rel_energy_gap_vs_two_row": abs(energy(r) - energy(ref)) / abs(energy(ref))}
     out["workload"] = "10x10 OBC PEPS, d=2, D=6, N(0,1) unit-norm sites, chi=72, 4 half-sweeps"
     return out
 
