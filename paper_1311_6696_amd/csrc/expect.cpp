@@ -610,6 +610,46 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
 
 namespace pe {
 
+namespace {
+
+// The single-row sandwich jobs of (environment, row) pairs with their left
+// and right column environments.  An environment is immutable, so these
+// are computed once, in the environment's own memory, and kept with it for
+// later site, bond and fit calls; jid[i] indexes the job of keys[i].
+void row_sandwiches(Ctx& ctx, Rec& rec, Arena& call, Scratch& scr, const std::vector<std::pair<peps_env*, int>>& keys,
+                    std::vector<RJob>& rj, std::vector<size_t>& jid, int prec, int cdt) {
+  const size_t esz = dtype_size(cdt);
+  std::map<std::pair<peps_env*, int>, size_t> job_of;
+  std::vector<RJob> fresh;
+  std::vector<size_t> fresh_at;
+  for (size_t i = 0; i < keys.size(); ++i) {
+    auto it = job_of.find(keys[i]);
+    if (it == job_of.end()) {
+      it = job_of.emplace(keys[i], rj.size()).first;
+      peps_env* e = keys[i].first;
+      auto c = e->row_env.find(keys[i].second);
+      if (c != e->row_env.end()) {
+        rj.push_back(*static_cast<const RJob*>(c->second.get()));
+      } else {
+        fresh.push_back(make_row_job(e, e, false, keys[i].second, e->arena, esz));
+        fresh_at.push_back(rj.size());
+        rj.push_back(fresh.back());
+      }
+    }
+    jid[i] = it->second;
+  }
+  if (fresh.empty()) return;
+  std::vector<R2Job> r2;
+  column_envs(rec, call, scr, fresh, r2, prec, cdt, esz, ctx.scratch_budget);
+  for (size_t k = 0; k < fresh.size(); ++k) {
+    const RJob& j = fresh[k];
+    j.e->row_env[j.r] = std::make_shared<RJob>(j);
+    rj[fresh_at[k]] = j;
+  }
+}
+
+}  // namespace
+
 void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log_z, std::vector<double>& sign,
                    double& flops) {
   Arena call(&ctx.pool);
@@ -622,19 +662,12 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
 
   // one single-row sandwich per distinct (environment, row)
   std::vector<RJob> rj;
-  std::vector<R2Job> r2;
-  std::map<std::pair<peps_env*, int>, size_t> job_of;
   std::vector<size_t> jid(req.size());
-  for (size_t i = 0; i < req.size(); ++i) {
-    const auto key = std::make_pair(req[i].e, req[i].r);
-    auto it = job_of.find(key);
-    if (it == job_of.end()) {
-      it = job_of.emplace(key, rj.size()).first;
-      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
-    }
-    jid[i] = it->second;
+  {
+    std::vector<std::pair<peps_env*, int>> keys;
+    for (const auto& q : req) keys.push_back({q.e, q.r});
+    row_sandwiches(ctx, rec, call, scr, keys, rj, jid, prec, cdt);
   }
-  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
 
   // N[l,u,r,d,m,v,s,g] = L[c][x,l,m,a] T[c][a,u,v,e] B[c][x,d,g,y] R[c+1][y,r,s,e]
   // (the norm network of the row with site c's ket and bra taken out):
@@ -759,19 +792,12 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
   const size_t esz = dtype_size(cdt);
 
   std::vector<RJob> rj;
-  std::vector<R2Job> r2;
-  std::map<std::pair<peps_env*, int>, size_t> job_of;
   std::vector<size_t> jid(req.size());
-  for (size_t i = 0; i < req.size(); ++i) {
-    const auto key = std::make_pair(req[i].e, req[i].r);
-    auto it = job_of.find(key);
-    if (it == job_of.end()) {
-      it = job_of.emplace(key, rj.size()).first;
-      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
-    }
-    jid[i] = it->second;
+  {
+    std::vector<std::pair<peps_env*, int>> keys;
+    for (const auto& q : req) keys.push_back({q.e, q.r});
+    row_sandwiches(ctx, rec, call, scr, keys, rj, jid, prec, cdt);
   }
-  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
 
   // gates in the compute dtype
   std::vector<const void*> gate(req.size());
@@ -1057,19 +1083,12 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
   const size_t esz = sizeof(double);
 
   std::vector<RJob> rj;
-  std::vector<R2Job> r2;
-  std::map<std::pair<peps_env*, int>, size_t> job_of;
   std::vector<size_t> jid(req.size());
-  for (size_t i = 0; i < req.size(); ++i) {
-    const auto key = std::make_pair(req[i].e, req[i].r);
-    auto it = job_of.find(key);
-    if (it == job_of.end()) {
-      it = job_of.emplace(key, rj.size()).first;
-      rj.push_back(make_row_job(req[i].e, req[i].e, false, req[i].r, call, esz));
-    }
-    jid[i] = it->second;
+  {
+    std::vector<std::pair<peps_env*, int>> keys;
+    for (const auto& q : req) keys.push_back({q.e, q.r});
+    row_sandwiches(ctx, rec, call, scr, keys, rj, jid, prec, cdt);
   }
-  column_envs(rec, call, scr, rj, r2, prec, cdt, esz, ctx.scratch_budget);
   flops = 0.0;
 
   // the substitutes as site views (same shape and storage order as the sites)

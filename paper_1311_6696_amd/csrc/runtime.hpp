@@ -241,6 +241,9 @@ struct peps_env {
   // peps_expect then takes the vertical bonds from its single-row sandwiches.
   std::unique_ptr<peps_env> col;
   int side0 = 0;   // ALS start-stream side of the top boundaries (bottom: side0 + 1)
+  // Single-row sandwiches (column environments in this environment's
+  // memory) of rows already used by site, bond or fit calls, by row.
+  std::map<int, std::shared_ptr<void>> row_env;
   pe::Mps& T(int r) { return top[r + 1]; }
   pe::Mps& B(int r) { return bot[lat.Lr - r]; }
   double Tlog(int r) const { return top_log[r + 1]; }
