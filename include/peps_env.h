@@ -164,7 +164,10 @@ void peps_env_free(peps_env* env);
  * order either way.  N is symmetric and
  * positive semidefinite at lossless chi; truncated boundaries need not be
  * symmetric under ket <-> bra.  All requests share one precision; *flops
- * (may be NULL) receives the algorithmic flops. */
+ * (may be NULL) receives the algorithmic flops.  The row sandwich of each
+ * row used (its left and right column environments) is kept with the
+ * environment, in device memory it owns until peps_env_free, and reused by
+ * later peps_site_env, peps_bond_env and peps_bond_fit calls. */
 typedef struct {
   peps_env* env;
   int32_t r, c;
