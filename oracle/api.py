@@ -48,14 +48,17 @@ class Env:
         return self.bottom[self.lat.rows - r]
 
 
-def env_boundary(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED):
+def env_boundary(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED, tol=0.0, max_halfsweeps=None):
+    """Top and bottom boundaries.  ``halfsweeps`` ALS half-sweeps per
+    truncated row; with ``tol`` > 0 the sweeps go on until the squared centre
+    norm settles to ``tol`` (relative) or ``max_halfsweeps`` have run."""
     lat = lat_or_A if isinstance(lat_or_A, Lattice) else whole_lattice(lat_or_A)
-    top = top_boundaries(lat, chi, halfsweeps, seed, side=0)
-    bottom = top_boundaries(flip_vertical(lat), chi, halfsweeps, seed, side=1)
+    top = top_boundaries(lat, chi, halfsweeps, seed, 0, tol, max_halfsweeps)
+    bottom = top_boundaries(flip_vertical(lat), chi, halfsweeps, seed, 1, tol, max_halfsweeps)
     return Env(lat, top, bottom, chi)
 
 
-def env_columns(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED):
+def env_columns(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED, tol=0.0, max_halfsweeps=None):
     """Left and right boundaries of a lattice, as an ``Env`` of its transpose:
     its T(c) holds columns 0..c absorbed from the left, its B(c) columns
     c..Lc-1 absorbed from the right.  ALS start streams use side 2 (from the
@@ -63,8 +66,8 @@ def env_columns(lat_or_A, chi, halfsweeps=DEFAULT_HALFSWEEPS, seed=DEFAULT_SEED)
     of the row boundaries."""
     lat = lat_or_A if isinstance(lat_or_A, Lattice) else whole_lattice(lat_or_A)
     tl = transpose_lattice(lat)
-    top = top_boundaries(tl, chi, halfsweeps, seed, side=2)
-    bottom = top_boundaries(flip_vertical(tl), chi, halfsweeps, seed, side=3)
+    top = top_boundaries(tl, chi, halfsweeps, seed, 2, tol, max_halfsweeps)
+    bottom = top_boundaries(flip_vertical(tl), chi, halfsweeps, seed, 3, tol, max_halfsweeps)
     return Env(tl, top, bottom, chi)
 
 

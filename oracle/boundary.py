@@ -31,6 +31,14 @@ Conventions (readings of the paper, identical on the GPU side)
   gauge with non-negative R diagonal, then the centre tensor is normalised
   and 0.5*log(omega) is added to the boundary's log-scale, omega being the
   squared norm of the final centre tensor.
+* Stopping: with ``tol`` = 0 exactly ``halfsweeps`` half-sweeps run.  With
+  ``tol`` > 0 the sweep goes on past ``halfsweeps`` (at least 2) until the
+  squared centre norm settles, |omega_h - omega_(h-1)| <= tol * omega_h, or
+  ``max_halfsweeps`` have run (the row is then marked not converged).
+  omega is the squared overlap of the fit with the exact product, which is
+  stationary at the optimum: the rule fixes omega to about tol and the
+  tensors only to about sqrt(tol) (directions of tiny weight in the boundary
+  go on rotating long after omega and the observables have settled).
 """
 from dataclasses import dataclass, field
 from typing import List
@@ -157,9 +165,10 @@ class AbsorbInfo:
     exact: bool
     omegas: list
     bonds: list
+    converged: bool = True
 
 
-def absorb_row(T, Arow, lam, rho, chi, halfsweeps, seed, side, row):
+def absorb_row(T, Arow, lam, rho, chi, halfsweeps, seed, side, row, tol=0.0, max_halfsweeps=None):
     """T_new ~ T . row, returns (T_new, dlog, info); T_new has unit norm."""
     Lc = len(Arow)
     Dr = [t.shape[3] for t in Arow]
@@ -169,7 +178,7 @@ def absorb_row(T, Arow, lam, rho, chi, halfsweeps, seed, side, row):
     caps = bond_caps(chi, chi_prod, Dd)
     if caps == chi_prod:
         return _absorb_exact(T, Arow, lam, rho, Dd)
-    return _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row)
+    return _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row, tol, max_halfsweeps)
 
 
 def _absorb_exact(T, Arow, lam, rho, Dd):
@@ -196,7 +205,7 @@ def _absorb_exact(T, Arow, lam, rho, Dd):
     return X, 0.5 * np.log(omega), AbsorbInfo(True, [omega], [t.shape[3] for t in X[:-1]])
 
 
-def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row):
+def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row, tol=0.0, max_halfsweeps=None):
     Lc = len(Arow)
     bonds = [1] + list(caps) + [1]
     X = []
@@ -218,7 +227,11 @@ def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row):
     for c in range(Lc - 1, 0, -1):
         F[c] = env_right(F[c + 1], T[c], Arow[c], X[c])
     omegas = []
-    for h in range(halfsweeps):
+    adaptive = tol > 0.0
+    h_min = max(halfsweeps, 2) if adaptive else halfsweeps
+    h_max = max(max_halfsweeps or h_min, h_min) if adaptive else halfsweeps
+    converged = not adaptive
+    for h in range(h_max):
         if h % 2 == 0:                       # left to right
             for c in range(Lc):
                 N = site_tensor(E[c], T[c], Arow[c], F[c + 1])
@@ -240,9 +253,12 @@ def _absorb_als(T, Arow, lam, rho, caps, Dd, halfsweeps, seed, side, row):
                 else:
                     X[c] = N
         omegas.append(float(np.sum(N ** 2)))
-    centre = Lc - 1 if halfsweeps % 2 == 1 else 0
+        if adaptive and h + 1 >= h_min and abs(omegas[-1] - omegas[-2]) <= tol * omegas[-1]:
+            converged = True
+            break
+    centre = Lc - 1 if len(omegas) % 2 == 1 else 0
     X[centre] = X[centre] / np.sqrt(omegas[-1])
-    return X, 0.5 * np.log(omegas[-1]), AbsorbInfo(False, omegas, list(caps))
+    return X, 0.5 * np.log(omegas[-1]), AbsorbInfo(False, omegas, list(caps), converged)
 
 
 def mps_overlap(X, Y):
@@ -266,7 +282,7 @@ def trivial_boundary(closing_list):
             for s in closing_list]
 
 
-def top_boundaries(lat, chi, halfsweeps=4, seed=0, side=0):
+def top_boundaries(lat, chi, halfsweeps=4, seed=0, side=0, tol=0.0, max_halfsweeps=None):
     """Boundaries T_r (rows 0..r absorbed) for r = -1 .. Lr-2.
 
     Returns a list ``out`` with out[r+1] = (tensors, log_scale, info).
@@ -275,7 +291,7 @@ def top_boundaries(lat, chi, halfsweeps=4, seed=0, side=0):
     T, s = out[0][0], 0.0
     for r in range(lat.rows - 1):
         T, dlog, info = absorb_row(T, lat.A[r], lat.lam[r], lat.rho[r], chi,
-                                   halfsweeps, seed, side, r)
+                                   halfsweeps, seed, side, r, tol, max_halfsweeps)
         s += dlog
         out.append((T, s, info))
     return out

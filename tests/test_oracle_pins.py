@@ -229,6 +229,10 @@ def test_gauge_invariance_truncated():
 # --- P10/P11: ALS ------------------------------------------------------------
 
 def test_als_omega_monotone_and_start_independent():
+    """P10: omega never decreases over the half-sweeps, and two random starts
+    reach the same fixed point: after 64 half-sweeps the observables of two
+    seeds agree to 1e-11 on a strongly truncated product bond (81 -> 9) and on
+    two smaller cases."""
     A = make_peps(5, 5, 3, "uniform", 7)
     lat = whole_lattice(A)
     outs = [boundary.top_boundaries(lat, 9, 16, seed) for seed in (1, 2)]
@@ -236,9 +240,34 @@ def test_als_omega_monotone_and_start_independent():
         for _, _, info in out[2:]:
             w = np.array(info.omegas)
             assert np.all(np.diff(w) >= -1e-12 * w[-1])
-    # ALS converges linearly; after 16 half-sweeps two starts agree to ~1e-8
-    r = [api.expect(api.env_boundary(lat, 9, 16, seed)) for seed in (1, 2)]
-    _obs_close(r[0], r[1], 5e-8)
+    for (L, D, dist, chi, s) in [(5, 3, "uniform", 9, 7), (4, 3, "near_product", 6, 8), (4, 2, "uniform", 3, 9)]:
+        A = make_peps(L, L, D, dist, s)
+        r = [api.expect(api.env_boundary(A, chi, 64, seed)) for seed in (1, 2)]
+        _obs_close(r[0], r[1], 1e-11)
+
+
+def test_als_tolerance_rule():
+    """The omega stopping rule: every truncated row stops at the first
+    half-sweep h >= 2 with |omega_h - omega_(h-1)| <= tol omega_h, or is
+    marked not converged at the cap; with tol = 1e-15 two starts agree to
+    2e-9 (omega is stationary at the fixed point, so the observables settle
+    only to about sqrt(tol) times a state-dependent factor)."""
+    A = make_peps(4, 4, 3, "near_product", 8)
+    envs = [api.env_boundary(A, 6, 2, seed, tol=1e-15, max_halfsweeps=200) for seed in (1, 2)]
+    for env in envs:
+        for out in (env.top, env.bottom):
+            for _, _, info in out[1:]:
+                if info.exact:
+                    continue
+                w = info.omegas
+                assert info.converged and len(w) < 200
+                assert abs(w[-1] - w[-2]) <= 1e-15 * w[-1]
+                assert all(abs(w[h] - w[h - 1]) > 1e-15 * w[h] for h in range(1, len(w) - 1))
+    r = [api.expect(e) for e in envs]
+    _obs_close(r[0], r[1], 2e-9)
+    capped = api.env_boundary(A, 6, 2, 1, tol=1e-15, max_halfsweeps=5)
+    infos = [x[2] for x in capped.top[1:] if not x[2].exact]
+    assert infos and all(len(i.omegas) == 5 and not i.converged for i in infos)
 
 
 def test_als_stationary_at_convergence():
@@ -510,6 +539,46 @@ def test_bond_fit_with_substitutes_matches_brute_force():
         f = np.sum(Nex * N) / np.sum(N * N)
         assert np.abs(N * f - Nex).max() <= 1e-12 * np.abs(Nex).max()
         assert np.abs(b * f - bex).max() <= 1e-12 * np.abs(bex).max()
+
+
+def test_bond_fit_vertical_with_substitutes_matches_brute_force():
+    """The vertical bond's two local problems from the column sandwiches
+    (anisotropic bonds, so a swapped leg pair in the transposition fails):
+    with S = A they equal the column site and bond environments; with random
+    S1 on (r, c) and S2 on (r+1, c) N and b of each site equal the brute-force
+    norm environment of psi' and d<psi'|G psi>/dS up to one common factor per
+    site."""
+    Lr, Lc = 3, 3
+    A = _anisotropic_peps(Lr, Lc, 2, 3, 103)
+    G = np.random.default_rng(5).standard_normal((2, 2, 2, 2))
+    cols = api.env_columns(A, 4096)
+    psi = exact.statevector(A)
+    for (r, c) in [(0, 1), (1, 0), (1, 2)]:
+        N1, b1, N2, b2 = api.bond_fit_vertical(cols, r, c, G, A[r][c], A[r + 1][c])
+        bl, br = api.bond_env_vertical(cols, A, r, c, G)
+        assert np.abs(N1 - api.site_env_columns(cols, A, r, c)[0]).max() < 1e-13
+        assert np.abs(N2 - api.site_env_columns(cols, A, r + 1, c)[0]).max() < 1e-13
+        assert np.abs(b1 - bl).max() < 1e-13 and np.abs(b2 - br).max() < 1e-13
+        rng = np.random.default_rng(10 + r * Lc + c)
+        S1, S2 = rng.standard_normal(A[r][c].shape), rng.standard_normal(A[r + 1][c].shape)
+        N1, b1, N2, b2 = api.bond_fit_vertical(cols, r, c, G, S1, S2)
+        i, j = r * Lc + c, (r + 1) * Lc + c
+        phi = _gate_applied(psi, Lr * Lc, i, j, G)
+        for site, other, Sother, N, b in ((i, (r + 1, c), S2, N1, b1), (j, (r, c), S1, N2, b2)):
+            Ap = [list(row) for row in A]
+            Ap[other[0]][other[1]] = Sother
+            rr, cc = divmod(site, Lc)
+            K = int(np.prod(A[rr][cc].shape[1:]))
+            O = np.eye(K).reshape((K,) + A[rr][cc].shape[1:])
+            Bt = [[O if (x, y) == (rr, cc) else Ap[x][y] for y in range(Lc)] for x in range(Lr)]
+            M = exact.statevector(Bt).reshape(2 ** site, K, -1)
+            Mm = M.transpose(0, 2, 1).reshape(-1, K)
+            Nex = Mm.T @ Mm
+            bex = np.einsum("akb,apb->pk", M, phi.reshape(2 ** site, 2, -1))
+            f = np.sum(Nex * N) / np.sum(N * N)
+            assert f > 0
+            assert np.abs(N * f - Nex).max() <= 1e-12 * np.abs(Nex).max()
+            assert np.abs(b * f - bex).max() <= 1e-12 * np.abs(bex).max()
 
 
 # --- boundary fidelity ---------------------------------------------------------
