@@ -28,11 +28,14 @@
  *   - All work is enqueued on the context's stream; every entry point
  *     returns only after the results it writes are complete.
  *
- * Errors: every entry point returns peps_status.  On error nothing is
- * written to *out and peps_last_error() describes the failure (thread-local
- * string valid until the next call on the thread).  Arguments are validated
- * on the host before any launch.  No C++ exception crosses the ABI.  A
- * context must be used by one thread at a time.
+ * Errors: every entry point returns peps_status.  On error the handles in
+ * out[] are set to NULL, no result is written and peps_last_error()
+ * describes the failure (thread-local string valid until the next call on
+ * the thread).  Shapes, bonds, windows and options are validated on the host
+ * before any launch; the input tensors are then checked for NaN/Inf by a
+ * read-only pass (PEPS_ERR_NONFINITE, naming a site) before anything is
+ * computed.  No C++ exception crosses the ABI.  A context must be used by
+ * one thread at a time.
  */
 #ifndef PEPS_ENV_H
 #define PEPS_ENV_H
@@ -48,6 +51,7 @@ typedef enum {
   PEPS_ERR_INVALID = -1,      /* bad shape, bond mismatch, chi < 1, bad window, NULL pointer */
   PEPS_ERR_OOM = -2,          /* device allocation failed or workspace cap exceeded */
   PEPS_ERR_HIP = -3,          /* a HIP runtime call failed */
+  PEPS_ERR_NOT_CONVERGED = -4, /* PEPS_OPTS_STRICT: an ALS row reached max_halfsweeps before tol */
   PEPS_ERR_NONFINITE = -5,    /* NaN/Inf in an input tensor or in a computed norm */
   PEPS_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
 } peps_status;
@@ -71,12 +75,28 @@ typedef struct {
   const double* const* site;   /* host array of rows*cols device pointers */
 } peps_state;
 
+/* ALS truncation of a row (Sec. 2: the MPS-MPO product is replaced by the
+ * best MPS of bond chi, found by alternating least squares).  With tol == 0
+ * every truncated row runs exactly `halfsweeps` half-sweeps (a launch
+ * sequence that does not depend on the data).  With tol > 0 it runs at least
+ * max(halfsweeps, 2) and at most max_halfsweeps, stopping after the first
+ * half-sweep h with |omega_h - omega_(h-1)| <= tol * omega_h, omega being the
+ * squared norm of the ALS centre tensor (the squared overlap of the fit with
+ * the exact product).  omega is stationary at the optimum, so the rule fixes
+ * it to about tol and the boundary tensors only to about sqrt(tol).  Each
+ * extra half-sweep waits for the GPU once (the decision is taken on the
+ * host).  A row that reaches max_halfsweeps first is marked not converged
+ * (peps_env_info); with PEPS_OPTS_STRICT the call then fails with
+ * PEPS_ERR_NOT_CONVERGED and returns no environment. */
 typedef struct {
-  int32_t chi;          /* boundary bond dimension D' >= 1 */
-  int32_t dtype;        /* peps_dtype */
-  int32_t halfsweeps;   /* ALS half-sweeps per truncated row, >= 1 (default 4 if 0) */
-  int32_t flags;        /* 0, PEPS_OPTS_PER_STATE (peps_env_boundary only), PEPS_OPTS_COLUMNS */
-  uint64_t seed;        /* SplitMix64 key of the ALS start tensors */
+  int32_t chi;             /* boundary bond dimension D' >= 1 */
+  int32_t dtype;           /* peps_dtype */
+  int32_t halfsweeps;      /* ALS half-sweeps per truncated row (the minimum with tol > 0), default 4 if 0 */
+  int32_t flags;           /* 0 or PEPS_OPTS_PER_STATE (peps_env_boundary only), PEPS_OPTS_COLUMNS, PEPS_OPTS_STRICT */
+  uint64_t seed;           /* SplitMix64 key of the ALS start tensors */
+  int32_t max_halfsweeps;  /* with tol > 0: the cap, >= halfsweeps, <= 256 (0: 40) */
+  int32_t reserved;        /* must be 0 */
+  double tol;              /* 0 (fixed half-sweep count) or the relative omega tolerance, in (0, 1) */
 } peps_env_opts;
 
 /* opts.flags: the options argument of peps_env_boundary points to one
@@ -97,6 +117,11 @@ typedef struct {
  * its bond downwards comes from the single-column sandwich of the centre's
  * column. */
 #define PEPS_OPTS_COLUMNS 2
+
+/* opts.flags: with tol > 0, fail with PEPS_ERR_NOT_CONVERGED (no
+ * environment returned) if any truncated row reaches max_halfsweeps before
+ * the tolerance. */
+#define PEPS_OPTS_STRICT 4
 
 /* Cluster window around the centre site (ci, cj) of state `state`,
  * rows r0..r1 and columns c0..c1 inclusive, centre inside the window. */
@@ -269,10 +294,16 @@ typedef struct {
 peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
 
 /* Diagnostics of an environment's row boundaries (the column boundaries of
- * PEPS_OPTS_COLUMNS are not included): number of truncated rows, and the squared
- * norm of the ALS centre tensor after each half-sweep of each truncated row
- * (host buffer of at least n_rows*halfsweeps doubles; may be NULL). */
-peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas);
+ * PEPS_OPTS_COLUMNS are not included), truncated rows in order (top
+ * boundaries T_0, T_1, ..., then bottom ones), any pointer may be NULL:
+ * n_rows the number of truncated rows; max_halfsweeps the most half-sweeps
+ * any of them ran; omegas (n_rows * max_halfsweeps doubles) the squared norm
+ * of the ALS centre tensor after each half-sweep, NaN past a row's last;
+ * sweeps (n_rows) the half-sweeps each row ran; n_unconverged the rows that
+ * stopped at the cap before the tolerance (always 0 with tol == 0).  Waits
+ * for the context's stream. */
+peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* max_halfsweeps, double* omegas, int32_t* sweeps,
+                          int32_t* n_unconverged);
 
 /* Launch-shape autotuning of the contractions.  mode 1: every grouped
  * contraction (with beta = 0) whose signature - precision, output type,
@@ -313,7 +344,9 @@ peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
 #define PEPS_N_STATS 90
 peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches, double* bytes);
 /* Upper bound (bytes) of the transient workspace one call may hold for the
- * chain intermediates of a batch; larger batches run in several groups. */
+ * chain intermediates of a batch (default 48 GiB, at least 1 MiB); larger
+ * batches run in several groups, and a call in which one sandwich alone
+ * needs more fails with PEPS_ERR_OOM before any launch of its sandwiches. */
 peps_status peps_ctx_set_workspace(peps_ctx* ctx, uint64_t bytes);
 
 const char* peps_last_error(void);

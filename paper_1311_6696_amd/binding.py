@@ -14,9 +14,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpepsenv.
 
 PEPS_F64, PEPS_F32, PEPS_BF16 = 0, 1, 2
 DTYPES = {"f64": PEPS_F64, "f32": PEPS_F32, "bf16": PEPS_BF16}
-STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -5: "NONFINITE", -6: "UNSUPPORTED"}
+STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NOT_CONVERGED", -5: "NONFINITE", -6: "UNSUPPORTED"}
 OPTS_PER_STATE = 1   # peps_env_opts.flags: one options record per state
 OPTS_COLUMNS = 2     # peps_env_opts.flags: also the left/right boundaries (vertical bonds from column sandwiches)
+OPTS_STRICT = 4      # peps_env_opts.flags: an ALS row that reaches max_halfsweeps before tol fails the call
 DEFAULT_SEED = 0x13116696
 TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16", "128x48", "64x80",
          "skinny16", "skinny32", "skinny48", "skinny64", "skinny80", "ketbra16", "ketbra32")
@@ -48,7 +49,8 @@ class State(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("dtype", C.c_int32), ("halfsweeps", C.c_int32),
-                ("flags", C.c_int32), ("seed", C.c_uint64)]
+                ("flags", C.c_int32), ("seed", C.c_uint64), ("max_halfsweeps", C.c_int32),
+                ("reserved", C.c_int32), ("tol", C.c_double)]
 
 
 class Window(C.Structure):
@@ -115,7 +117,8 @@ def load(path=None):
     lib.peps_expect.argtypes = [vp, pp, i32, C.POINTER(Result)]
     lib.peps_env_free.argtypes = [vp]
     lib.peps_env_free.restype = None
-    lib.peps_env_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]
+    lib.peps_env_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32),
+                                  C.POINTER(i32)]
     lib.peps_ctx_profile.argtypes = [vp, i32]
     lib.peps_ctx_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
@@ -171,13 +174,21 @@ class Env:
         _, Dl, Du, Dr, Dd = self.shapes[r][c]
         return int(Dl * Du * Dr * Dd)
 
-    def info(self):
+    def info(self, full=False):
+        """Squared ALS centre norms per truncated row (top rows, then bottom
+        rows) and half-sweep, NaN past a row's last; with full=True also the
+        half-sweeps each row ran and the number of rows that stopped at the
+        cap before the tolerance."""
         lib = self.ctx.lib
-        n, h = C.c_int32(), C.c_int32()
-        _check(lib, lib.peps_env_info(self.handle, C.byref(n), C.byref(h), None))
+        n, h, u = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib, lib.peps_env_info(self.handle, C.byref(n), C.byref(h), None, None, C.byref(u)))
         om = (C.c_double * max(1, n.value * h.value))()
-        _check(lib, lib.peps_env_info(self.handle, None, None, om))
-        return np.array(om[: n.value * h.value]).reshape(n.value, h.value)
+        sw = (C.c_int32 * max(1, n.value))()
+        _check(lib, lib.peps_env_info(self.handle, None, None, om, sw, None))
+        w = np.array(om[: n.value * h.value]).reshape(n.value, h.value)
+        if full:
+            return w, np.array(sw[: n.value]), u.value
+        return w
 
     def free(self):
         if self.handle:
@@ -212,28 +223,31 @@ class Context:
             pass
 
     @staticmethod
-    def opts(chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED):
+    def opts(chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, tol=0.0, max_halfsweeps=0):
         return Opts(int(chi), DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(halfsweeps), 0,
-                    int(seed) & ((1 << 64) - 1))
+                    int(seed) & ((1 << 64) - 1), int(max_halfsweeps), 0, float(tol))
 
-    def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
+    def env_boundary_raw(self, states, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False,
+                         tol=0.0, max_halfsweeps=0, strict=False):
         """chi, halfsweeps, seed: one value for all states, or a sequence with
         one per state (passed as per-state options records).  columns: also
-        the left and right boundaries (OPTS_COLUMNS)."""
+        the left and right boundaries (OPTS_COLUMNS).  tol > 0: ALS sweeps
+        until the squared centre norm settles (at most max_halfsweeps; strict
+        makes an unconverged row an error)."""
         n = len(states)
         arr = (State * n)(*[s.struct() for s in states])
         out = (C.c_void_p * n)()
-        flags = OPTS_COLUMNS if columns else 0
+        flags = (OPTS_COLUMNS if columns else 0) | (OPTS_STRICT if strict else 0)
         per = [np.ndim(x) != 0 for x in (chi, halfsweeps, seed)]
         if not any(per):
-            o = self.opts(chi, dtype, halfsweeps, seed)
+            o = self.opts(chi, dtype, halfsweeps, seed, tol, max_halfsweeps)
             o.flags = flags
             _check(self.lib, self.lib.peps_env_boundary(self.handle, arr, n, C.byref(o), out))
         else:
             vals = [list(x) if p else [x] * n for x, p in zip((chi, halfsweeps, seed), per)]
             if any(len(v) != n for v in vals):
                 raise ValueError("one chi, halfsweeps or seed per state")
-            recs = [self.opts(c, dtype, h, s) for c, h, s in zip(*vals)]
+            recs = [self.opts(c, dtype, h, s, tol, max_halfsweeps) for c, h, s in zip(*vals)]
             for r in recs:
                 r.flags = OPTS_PER_STATE | flags
             o = (Opts * n)(*recs)
@@ -376,9 +390,10 @@ class Session:
         self.stream = torch.cuda.current_stream(dev)
         self.ctx = Context(dev, self.stream.cuda_stream)
 
-    def env_boundary(self, tensors_list, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
+    def env_boundary(self, tensors_list, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False,
+                     tol=0.0, max_halfsweeps=0, strict=False):
         states = [state_of(t) for t in tensors_list]
-        return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed, columns)
+        return self.ctx.env_boundary_raw(states, chi, dtype, halfsweeps, seed, columns, tol, max_halfsweeps, strict)
 
     def cluster_env(self, tensors_list, windows, chi, dtype="f64", halfsweeps=4, seed=DEFAULT_SEED, columns=False):
         states = [state_of(t) for t in tensors_list]

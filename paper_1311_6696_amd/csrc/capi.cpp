@@ -66,15 +66,64 @@ Opts make_opts(const peps_env_opts* o, int32_t allowed_flags = 0) {
   PE_REQUIRE(o != nullptr, "opts must not be NULL");
   PE_REQUIRE(o->chi >= 1, "chi must be >= 1");
   PE_REQUIRE(o->dtype >= PEPS_F64 && o->dtype <= PEPS_BF16, "unknown dtype");
-  PE_REQUIRE(o->halfsweeps >= 0 && o->halfsweeps <= 64, "halfsweeps must be in [0, 64]");
-  PE_REQUIRE((o->flags & ~allowed_flags) == 0, "unsupported flags");
+  PE_REQUIRE(o->halfsweeps >= 0 && o->halfsweeps <= 256, "halfsweeps must be in [0, 256]");
+  PE_REQUIRE((o->flags & ~(allowed_flags | PEPS_OPTS_STRICT)) == 0, "unsupported flags");
+  PE_REQUIRE(o->reserved == 0, "reserved must be 0");
+  PE_REQUIRE(std::isfinite(o->tol) && o->tol >= 0.0 && o->tol < 1.0, "tol must be in [0, 1)");
   Opts r;
   r.chi = o->chi;
   r.dtype = o->dtype;
   r.halfsweeps = o->halfsweeps == 0 ? 4 : o->halfsweeps;
   r.seed = o->seed;
   r.columns = (o->flags & PEPS_OPTS_COLUMNS) != 0;
+  r.strict = (o->flags & PEPS_OPTS_STRICT) != 0;
+  r.tol = o->tol;
+  if (r.tol > 0.0) {
+    r.halfsweeps = std::max(r.halfsweeps, 2);
+    const int cap = o->max_halfsweeps == 0 ? std::max(40, r.halfsweeps) : o->max_halfsweeps;
+    PE_REQUIRE(cap >= r.halfsweeps && cap <= 256, "max_halfsweeps must be in [halfsweeps, 256]");
+    r.max_halfsweeps = cap;
+  } else {
+    PE_REQUIRE(o->max_halfsweeps == 0 || o->max_halfsweeps >= r.halfsweeps,
+               "max_halfsweeps must be 0 or >= halfsweeps");
+    r.max_halfsweeps = r.halfsweeps;
+  }
   return r;
+}
+
+// Read-only pass over every input tensor of the used states: fails with
+// NONFINITE, naming a site, if any entry is NaN or Inf.  Nothing is written
+// but one flag in scratch memory.
+void check_finite(Ctx& C, const peps_state* st, int n_states, const std::vector<char>* used = nullptr) {
+  Arena tmp(&C.pool);
+  Rec rec(&C);
+  double* flag = (double*)tmp.alloc(sizeof(double));
+  std::vector<EwDesc> clear{ew_desc(EW_FILL, nullptr, DT_F64, flag, DT_F64, 1)};
+  std::vector<EwDesc> chk;
+  std::vector<std::pair<int, int>> who;
+  for (int i = 0; i < n_states; ++i) {
+    if (used && !(*used)[i]) continue;
+    for (int k = 0; k < st[i].rows * st[i].cols; ++k) {
+      const int32_t* d = st[i].dims + 5 * k;
+      const int64_t n = (int64_t)d[0] * d[1] * d[2] * d[3] * d[4];
+      EwDesc e = ew_desc(EW_NONFINITE, st[i].site[k], DT_F64, flag, DT_F64, n);
+      e.a = (double)(who.size() + 1);
+      who.push_back({i, k});
+      chk.push_back(e);
+    }
+  }
+  rec.ew(clear);
+  rec.ew(chk);
+  rec.run(tmp);
+  double f = 0.0;
+  dev::d2h(&f, flag, sizeof(double), C.stream);
+  dev::sync(C.stream);
+  if (f != 0.0) {
+    const auto& w = who[(size_t)f - 1];
+    const int cols = st[w.first].cols;
+    throw Error(ST_NONFINITE, "state " + std::to_string(w.first) + ": site (" + std::to_string(w.second / cols) + "," +
+                                  std::to_string(w.second % cols) + ") has a NaN or Inf entry");
+  }
 }
 
 // Packs the caller's float64 sites into `owner`'s arena: identity, S^z, S^+,
@@ -149,6 +198,9 @@ void* make_one(Rec& rec, Arena& arena, int cdt) {
 }  // namespace
 
 void validate_state_public(const peps_state& s, int idx) { validate_state(s, idx); }
+void check_finite_public(Ctx& C, const peps_state* st, int n_states, const std::vector<char>& used) {
+  check_finite(C, st, n_states, &used);
+}
 Opts make_opts_public(const peps_env_opts* o) { return make_opts(o, PEPS_OPTS_COLUMNS); }
 std::unique_ptr<peps_env> transposed_env_public(const peps_env& e) { return transposed_env(e); }
 void pack_state_public(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out) {
@@ -205,6 +257,7 @@ peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_sta
     }
     for (int i = 0; i < n_states; ++i) validate_state(st[i], i);
     dev::set_device(ctx->c->device);
+    check_finite(*ctx->c, st, n_states);
     Arena tmp(&ctx->c->pool);
     Rec rec(ctx->c.get());
     for (int i = 0; i < n_states; ++i) {
@@ -231,8 +284,11 @@ peps_status peps_env_boundary(peps_ctx* ctx, const peps_state* st, int32_t n_sta
     plan_boundaries(*ctx->c, all);   // row and column boundaries in one batched run
     for (int i = 0; i < n_states; ++i) out[i] = made[i];
   });
-  if (s != PEPS_OK)
+  if (s != PEPS_OK) {
     for (peps_env* e : made) delete e;
+    if (out && n_states > 0)
+      for (int i = 0; i < n_states; ++i) out[i] = nullptr;
+  }
   return s;
 }
 
@@ -451,12 +507,32 @@ peps_status peps_site_env(peps_ctx* ctx, peps_site_req* req, int32_t n_req, doub
   });
 }
 
-peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* halfsweeps, double* omegas) {
+peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* max_halfsweeps, double* omegas, int32_t* sweeps,
+                          int32_t* n_unconverged) {
   return guarded([&] {
     PE_REQUIRE(env != nullptr, "env must not be NULL");
-    if (n_rows) *n_rows = env->n_trunc;
-    if (halfsweeps) *halfsweeps = env->opts.halfsweeps;
-    if (omegas) std::memcpy(omegas, env->omegas.data(), sizeof(double) * env->omegas.size());
+    std::vector<const Mps*> rows;
+    for (const std::vector<Mps>* v : {&env->top, &env->bot})
+      for (size_t k = 1; k < v->size(); ++k)
+        if ((*v)[k].truncated) rows.push_back(&(*v)[k]);
+    int hmax = 0, unconv = 0;
+    for (const Mps* m : rows) {
+      hmax = std::max(hmax, m->n_omega);
+      unconv += m->converged ? 0 : 1;
+    }
+    if (n_rows) *n_rows = (int32_t)rows.size();
+    if (max_halfsweeps) *max_halfsweeps = hmax;
+    if (n_unconverged) *n_unconverged = unconv;
+    for (size_t i = 0; i < rows.size(); ++i) {
+      if (sweeps) sweeps[i] = rows[i]->n_omega;
+      if (omegas) {
+        double* o = omegas + i * (size_t)hmax;
+        for (int h = 0; h < hmax; ++h) o[h] = std::nan("");
+        dev::set_device(env->ctx->device);
+        dev::d2h(o, rows[i]->omega, sizeof(double) * rows[i]->n_omega, env->ctx->stream);
+      }
+    }
+    if (omegas && !rows.empty()) dev::sync(env->ctx->stream);
   });
 }
 

@@ -73,6 +73,7 @@ using namespace pe;
 // Defined in capi.cpp.
 namespace pe {
 void validate_state_public(const peps_state& s, int idx);
+void check_finite_public(Ctx& C, const peps_state* st, int n_states, const std::vector<char>& used);
 Opts make_opts_public(const peps_env_opts* o);
 std::unique_ptr<peps_env> transposed_env_public(const peps_env& e);
 void pack_state_public(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vector<std::unique_ptr<Site>>& out);
@@ -106,6 +107,7 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
     }
     dev::set_device(ctx->c->device);
     Ctx& C = *ctx->c;
+    check_finite_public(C, st, n_states, used);
     auto data = std::make_shared<ClusterData>(&C);
     Arena tmp(&C.pool);
     Rec rec(&C);
@@ -200,7 +202,10 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
     plan_boundaries(C, all);
     for (int w = 0; w < n_win; ++w) out[w] = made[w];
   });
-  if (status != PEPS_OK)
+  if (status != PEPS_OK) {
     for (peps_env* e : made) delete e;
+    if (out && n_win > 0)
+      for (int w = 0; w < n_win; ++w) out[w] = nullptr;
+  }
   return status;
 }

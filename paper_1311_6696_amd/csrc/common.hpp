@@ -10,7 +10,9 @@
 namespace pe {
 
 // Status codes mirror peps_status of include/peps_env.h.
-enum : int { ST_OK = 0, ST_INVALID = -1, ST_OOM = -2, ST_HIP = -3, ST_NONFINITE = -5, ST_UNSUPPORTED = -6 };
+enum : int {
+  ST_OK = 0, ST_INVALID = -1, ST_OOM = -2, ST_HIP = -3, ST_NOT_CONVERGED = -4, ST_NONFINITE = -5, ST_UNSUPPORTED = -6
+};
 
 struct Error : std::runtime_error {
   int code;

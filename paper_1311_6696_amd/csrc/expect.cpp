@@ -21,6 +21,10 @@ namespace {
 std::vector<std::pair<size_t, size_t>> budget_groups(const std::vector<size_t>& sz, size_t budget) {
   std::vector<std::pair<size_t, size_t>> g;
   size_t i = 0;
+  for (size_t k = 0; k < sz.size(); ++k)
+    if (sz[k] > budget)
+      throw Error(ST_OOM, "one sandwich needs " + std::to_string(sz[k]) + " bytes of workspace, above the cap of " +
+                              std::to_string(budget) + " (peps_ctx_set_workspace)");
   while (i < sz.size()) {
     size_t j = i, tot = 0;
     while (j < sz.size() && (j == i || tot + sz[j] <= budget)) tot += sz[j++];

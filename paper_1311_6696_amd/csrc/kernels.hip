@@ -1761,6 +1761,24 @@ __global__ __launch_bounds__(256) void ew_kernel(const EwDesc* __restrict__ ds, 
   const EwDesc& d = ds[lo];
   const int64_t stride = (int64_t)d.nblocks * 256;
   const int64_t n = d.n;
+  if (d.kind == EW_LOGACC) {   // a short sequential sum (one per boundary side)
+    if (bid == d.block_base && threadIdx.x == 0) {
+      const double* const* w = (const double* const*)d.src;
+      double* out = (double*)d.dst;
+      double acc = 0.0;
+      out[0] = 0.0;
+      for (int64_t k = 0; k < n; ++k) {
+        acc += 0.5 * log(*w[k]);
+        out[k + 1] = acc;
+      }
+    }
+    return;
+  }
+  if (d.kind == EW_NONFINITE) {   // every writer stores the same value
+    for (int64_t i = (int64_t)(bid - d.block_base) * 256 + threadIdx.x; i < n; i += stride)
+      if (!isfinite(ew_load(d.src, d.src_dt, i))) ((double*)d.dst)[0] = d.a;
+    return;
+  }
   for (int64_t i = (int64_t)(bid - d.block_base) * 256 + threadIdx.x; i < n; i += stride) {
     double v;
     switch (d.kind) {

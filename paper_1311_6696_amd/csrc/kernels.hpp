@@ -145,6 +145,9 @@ enum EwKind : int {
   EW_SPLITMIX = 3,    // dst[i] = SplitMix64 value i of stream state `key`, in [-1, 1)
   EW_RSQRT = 4,       // dst = src / sqrt(*sptr)
   EW_IDENTITY = 5,    // dst = a * identity (n = D*D)
+  EW_NONFINITE = 6,   // dst[0] = a wherever src holds NaN or Inf (dst untouched otherwise)
+  EW_LOGACC = 7,      // one thread: dst[0] = 0, dst[k+1] = dst[k] + log(*src[k]) / 2 for k < n
+                      //   (src: device array of n pointers to squared norms)
 };
 struct EwDesc {
   const void* src;

@@ -56,6 +56,8 @@ struct AJob {
   void *P = nullptr, *Q = nullptr;
   double *N = nullptr, *W = nullptr, *R = nullptr;
   double* omega = nullptr;
+  int H = 0;            // half-sweeps recorded so far
+  bool conv = true;     // stopped by the tolerance (or no tolerance)
   std::vector<void*> scratch;
 };
 
@@ -185,25 +187,23 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
   cast_copies(rec, js, o);
 }
 
-void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
-  if (js.empty()) return;
+// Views of one ALS job's tensors (contraction dtype unless noted).
+struct AlsViews {
+  int cdt;
+  TV E(AJob* j, int c) const { return dense(j->E[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}); }
+  TV F(AJob* j, int c) const { return dense(j->F[c], cdt, "yrse", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}); }
+  TV X(AJob* j, int c) const { return dense(j->Xc[c], cdt, "xdgy", {j->bout[c], j->Dd[c], j->Dd[c], j->bout[c + 1]}); }
+  TV N(AJob* j, int c) const {   // float64 site solution
+    return dense(j->N, DT_F64, "xdgy", {j->bout[c], j->Dd[c], j->Dd[c], j->bout[c + 1]});
+  }
+};
+
+// ALS start: SplitMix64 tensors, right-canonical by LQ, right environments.
+void als_start(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
   const int prec = o.prec(), cdt = o.cdt();
-  const int H = o.halfsweeps;
+  const AlsViews v{cdt};
   int maxLc = 0;
   for (AJob* j : js) maxLc = std::max(maxLc, j->Lc);
-  auto Ev = [&](AJob* j, int c) {
-    return dense(j->E[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]});
-  };
-  auto Fv = [&](AJob* j, int c) {
-    return dense(j->F[c], cdt, "yrse", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]});
-  };
-  auto Xv = [&](AJob* j, int c) {
-    return dense(j->Xc[c], cdt, "xdgy", {j->bout[c], j->Dd[c], j->Dd[c], j->bout[c + 1]});
-  };
-  auto Nv = [&](AJob* j, int c) {
-    return dense(j->N, DT_F64, "xdgy", {j->bout[c], j->Dd[c], j->Dd[c], j->bout[c + 1]});
-  };
-  // start tensors (SplitMix64) and their right-canonical form
   {
     std::vector<EwDesc> f;
     for (AJob* j : js)
@@ -235,7 +235,6 @@ void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
     rec.tc(TP_F64, DT_F64, mv, false);
   }
   cast_copies(rec, js, o);
-  // right environments of the start
   for (int s = 0; s + 1 < maxLc; ++s) {
     St st(3, prec);
     std::vector<TcDesc> env;
@@ -243,93 +242,145 @@ void plan_als(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       const int c = j->Lc - 1 - s;
       if (c < 1) continue;
       const double f0 = st.flops;
-      TV y3 = chain_right(st, Fv(j, c + 1), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
-      env.push_back(tc_build(dense(j->F[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}), y3, Xv(j, c)));
+      TV y3 = chain_right(st, v.F(j, c + 1), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
+      env.push_back(tc_build(dense(j->F[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}), y3, v.X(j, c)));
       j->env->flops += st.flops - f0 + tc_flops(env.back());
     }
     st.record(rec, prec, cdt);
     rec.tc(prec, cdt, env);
   }
-  // alternating half-sweeps
-  for (int h = 0; h < H; ++h) {
-    const bool l2r = (h % 2 == 0);
-    for (int s = 0; s < maxLc; ++s) {
-      St st(3, prec);
-      std::vector<TcDesc> site, env;
-      std::vector<QrDesc> qrs;
-      std::vector<AJob*> upd;
-      for (AJob* j : js) {
-        if (s >= j->Lc) continue;
-        const int Lc = j->Lc;
-        if (l2r) {
-          const int c = s;
-          const bool reuse = (h > 0 && c == 0);
-          const bool need_env = c < Lc - 1;
-          if (reuse && !need_env) continue;
-          const double f0 = st.flops;
-          TV y3 = chain_left(st, Ev(j, c), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
-          j->env->flops += st.flops - f0;
-          if (!reuse) site.push_back(tc_build(Nv(j, c), y3, Fv(j, c + 1)));
-          if (!reuse) j->env->flops += tc_flops(site.back());
-          if (need_env) {
-            const int64_t m = j->bout[c] * j->Dd[c] * j->Dd[c], n = j->bout[c + 1];
-            qrs.push_back(qr_desc(j->N, n, 1, j->X[c], n, 1, nullptr, 0, 0, j->W, (int)m, (int)n));
-            env.push_back(tc_build(dense(j->E[c + 1], cdt, "yrse", {j->bout[c + 1], j->Dl[c + 1], j->Dl[c + 1], j->bin[c + 1]}),
-                                   y3, Xv(j, c)));
-            j->env->flops += tc_flops(env.back());
-            upd.push_back(j);
-          }
-        } else {
-          const int c = Lc - 1 - s;
-          const bool reuse = (c == Lc - 1);
-          const bool need_env = c > 0;
-          if (reuse && !need_env) continue;
-          const double f0 = st.flops;
-          TV y3 = chain_right(st, Fv(j, c + 1), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
-          j->env->flops += st.flops - f0;
-          if (!reuse) site.push_back(tc_build(Nv(j, c), y3, Ev(j, c)));
-          if (!reuse) j->env->flops += tc_flops(site.back());
-          if (need_env) {
-            const int64_t m = j->Dd[c] * j->Dd[c] * j->bout[c + 1], n = j->bout[c];
-            qrs.push_back(qr_desc(j->N, 1, m, j->X[c], 1, m, nullptr, 0, 0, j->W, (int)m, (int)n));
-            env.push_back(tc_build(dense(j->F[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}), y3,
-                                   Xv(j, c)));
-            j->env->flops += tc_flops(env.back());
-            upd.push_back(j);
-          }
-        }
-      }
-      st.record(rec, prec, cdt);
-      rec.tc(prec, DT_F64, site);
-      rec.qr(qrs);
-      if (cdt != DT_F64) {
-        std::vector<EwDesc> ew;
-        for (AJob* j : upd) {
-          const int c = l2r ? s : j->Lc - 1 - s;
-          ew.push_back(ew_desc(EW_COPY, j->X[c], DT_F64, j->Xc[c], DT_F32,
-                               j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]));
-        }
-        rec.ew(ew);
-      }
-      rec.tc(prec, cdt, env);
-    }
-    std::vector<RedDesc> rd;
+  for (AJob* j : js) j->H = 0;
+}
+
+// Half-sweep h of every job (all at the same h): left to right for even h.
+// Each site step: the local solution N = E.(T A A).F, its QR gauge, the
+// environment update; the squared norm of the last N goes to omega[h].
+void als_halfsweep(Rec& rec, std::vector<AJob*>& js, const Opts& o, int h) {
+  const int prec = o.prec(), cdt = o.cdt();
+  const AlsViews v{cdt};
+  int maxLc = 0;
+  for (AJob* j : js) maxLc = std::max(maxLc, j->Lc);
+  const bool l2r = (h % 2 == 0);
+  for (int s = 0; s < maxLc; ++s) {
+    St st(3, prec);
+    std::vector<TcDesc> site, env;
+    std::vector<QrDesc> qrs;
+    std::vector<AJob*> upd;
     for (AJob* j : js) {
-      const int c = l2r ? j->Lc - 1 : 0;
-      rd.push_back(red_desc(j->N, nullptr, j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1], j->omega + h, DT_F64));
+      if (s >= j->Lc) continue;
+      const int Lc = j->Lc;
+      if (l2r) {
+        const int c = s;
+        const bool reuse = (h > 0 && c == 0);
+        const bool need_env = c < Lc - 1;
+        if (reuse && !need_env) continue;
+        const double f0 = st.flops;
+        TV y3 = chain_left(st, v.E(j, c), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
+        j->env->flops += st.flops - f0;
+        if (!reuse) site.push_back(tc_build(v.N(j, c), y3, v.F(j, c + 1)));
+        if (!reuse) j->env->flops += tc_flops(site.back());
+        if (need_env) {
+          const int64_t m = j->bout[c] * j->Dd[c] * j->Dd[c], n = j->bout[c + 1];
+          qrs.push_back(qr_desc(j->N, n, 1, j->X[c], n, 1, nullptr, 0, 0, j->W, (int)m, (int)n));
+          env.push_back(tc_build(dense(j->E[c + 1], cdt, "yrse", {j->bout[c + 1], j->Dl[c + 1], j->Dl[c + 1], j->bin[c + 1]}),
+                                 y3, v.X(j, c)));
+          j->env->flops += tc_flops(env.back());
+          upd.push_back(j);
+        }
+      } else {
+        const int c = Lc - 1 - s;
+        const bool reuse = (c == Lc - 1);
+        const bool need_env = c > 0;
+        if (reuse && !need_env) continue;
+        const double f0 = st.flops;
+        TV y3 = chain_right(st, v.F(j, c + 1), Tview(*j, c, "auve", cdt), j->Ak[c], j->Ab[c], j->P, j->Q, cdt);
+        j->env->flops += st.flops - f0;
+        if (!reuse) site.push_back(tc_build(v.N(j, c), y3, v.E(j, c)));
+        if (!reuse) j->env->flops += tc_flops(site.back());
+        if (need_env) {
+          const int64_t m = j->Dd[c] * j->Dd[c] * j->bout[c + 1], n = j->bout[c];
+          qrs.push_back(qr_desc(j->N, 1, m, j->X[c], 1, m, nullptr, 0, 0, j->W, (int)m, (int)n));
+          env.push_back(tc_build(dense(j->F[c], cdt, "xlma", {j->bout[c], j->Dl[c], j->Dl[c], j->bin[c]}), y3,
+                                 v.X(j, c)));
+          j->env->flops += tc_flops(env.back());
+          upd.push_back(j);
+        }
+      }
     }
-    rec.reduce(rd);
+    st.record(rec, prec, cdt);
+    rec.tc(prec, DT_F64, site);
+    rec.qr(qrs);
+    if (cdt != DT_F64) {
+      std::vector<EwDesc> ew;
+      for (AJob* j : upd) {
+        const int c = l2r ? s : j->Lc - 1 - s;
+        ew.push_back(ew_desc(EW_COPY, j->X[c], DT_F64, j->Xc[c], DT_F32,
+                             j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]));
+      }
+      rec.ew(ew);
+    }
+    rec.tc(prec, cdt, env);
   }
-  // normalise the centre tensor
+  std::vector<RedDesc> rd;
+  for (AJob* j : js) {
+    const int c = l2r ? j->Lc - 1 : 0;
+    rd.push_back(red_desc(j->N, nullptr, j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1], j->omega + h, DT_F64));
+    j->H = h + 1;
+  }
+  rec.reduce(rd);
+}
+
+// Normalise each job's centre tensor (site Lc-1 after an odd number of
+// half-sweeps, site 0 after an even one) and refresh the compute-dtype copies.
+void als_finish(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
   std::vector<EwDesc> sc;
   for (AJob* j : js) {
-    const int c = (H % 2 == 1) ? j->Lc - 1 : 0;
+    const int c = (j->H % 2 == 1) ? j->Lc - 1 : 0;
     EwDesc e = ew_desc(EW_RSQRT, j->N, DT_F64, j->X[c], DT_F64, j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]);
-    e.sptr = j->omega + (H - 1);
+    e.sptr = j->omega + (j->H - 1);
     sc.push_back(e);
   }
   rec.ew(sc);
   cast_copies(rec, js, o);
+}
+
+// ALS truncation of every job of one precision: `o.halfsweeps` half-sweeps,
+// then, for jobs with a tolerance, one more at a time (each decided on the
+// host after the GPU has caught up) until |omega_h - omega_(h-1)| <=
+// tol * omega_h or the job's cap.
+void plan_als(Rec& rec, Arena& call, Ctx& ctx, std::vector<AJob*>& js, const Opts& o) {
+  if (js.empty()) return;
+  als_start(rec, js, o);
+  for (int h = 0; h < o.halfsweeps; ++h) als_halfsweep(rec, js, o, h);
+  std::vector<AJob*> act;
+  for (AJob* j : js) {
+    j->conv = true;
+    if (j->env->opts.tol > 0.0 && j->env->opts.max_halfsweeps > j->H) act.push_back(j);
+  }
+  std::vector<double> w(2 * js.size());
+  while (!act.empty()) {
+    rec.flush(call);
+    for (size_t i = 0; i < act.size(); ++i)
+      dev::d2h(&w[2 * i], act[i]->omega + (act[i]->H - 2), 2 * sizeof(double), ctx.stream);
+    dev::sync(ctx.stream);
+    std::vector<AJob*> next;
+    for (size_t i = 0; i < act.size(); ++i) {
+      AJob* j = act[i];
+      const double a = w[2 * i], b = w[2 * i + 1];
+      if (!(std::isfinite(a) && std::isfinite(b) && b > 0.0))
+        throw Error(ST_NONFINITE, "boundary row " + std::to_string(j->k) + " has squared norm " + std::to_string(b));
+      if (std::fabs(b - a) <= j->env->opts.tol * b) continue;
+      if (j->H >= j->env->opts.max_halfsweeps) {
+        j->conv = false;
+        continue;
+      }
+      next.push_back(j);
+    }
+    if (next.empty()) break;
+    als_halfsweep(rec, next, o, next[0]->H);
+    act.swap(next);
+  }
+  als_finish(rec, js, o);
 }
 
 }  // namespace
@@ -409,7 +460,7 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
       peps_env* e = j.env;
       const int cdt = e->opts.cdt();
       const size_t esz = dtype_size(cdt);
-      const int H = j.exact ? 1 : e->opts.halfsweeps;
+      const int H = j.exact ? 1 : std::max(e->opts.halfsweeps, e->opts.max_halfsweeps);
       j.omega = (double*)e->arena.alloc(sizeof(double) * H);
       int64_t maxX = 1, maxQR = 1, maxR = 1, maxP = 1, maxQ = 1;
       for (int c = 0; c < j.Lc; ++c) {
@@ -466,7 +517,7 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
       if (a.empty() && b.empty()) continue;
       const Opts& o = (a.empty() ? b[0] : a[0])->env->opts;
       plan_exact(rec, scr, a, o);
-      plan_als(rec, scr, b, o);
+      plan_als(rec, call, ctx, b, o);
     }
     for (AJob& j : jobs) {
       j.Tout->t64 = j.X;
@@ -474,34 +525,53 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
       j.Tout->bond.assign(j.bout.begin(), j.bout.end());
       j.Tout->leg.assign(j.Dd.begin(), j.Dd.end());
       j.Tout->omega = j.omega;
-      j.Tout->n_omega = j.exact ? 1 : j.env->opts.halfsweeps;
+      j.Tout->n_omega = j.exact ? 1 : j.H;
       j.Tout->truncated = !j.exact;
+      j.Tout->converged = j.exact || j.conv;
       for (void* p : j.scratch) scr.put(p);
     }
     rec.flush(call);   // the GPU starts on this row while the next one is planned
   }
-  rec.run(call);
-  // log-scales (FP64 on the host) and diagnostics
+  // log-scales: the FP64 sums of log(omega)/2 over the absorbed rows of every
+  // side run on the device; one copy brings all of them back
+  std::vector<EwDesc> acc;
+  size_t nlog = 0;
+  for (peps_env* e : envs) nlog += 2 * (size_t)e->lat.Lr;
+  double* logs = (double*)call.alloc(sizeof(double) * std::max<size_t>(nlog, 1));
+  size_t at = 0;
   for (peps_env* e : envs) {
-    const int Lr = e->lat.Lr;
-    e->omegas.clear();
-    e->n_trunc = 0;
     for (int side = 0; side < 2; ++side) {
       std::vector<Mps>& vec = side == 0 ? e->top : e->bot;
+      std::vector<const double*> w;
+      for (size_t k = 1; k < vec.size(); ++k) w.push_back(vec[k].omega + (vec[k].n_omega - 1));
+      EwDesc d = ew_desc(EW_LOGACC, nullptr, DT_F64, logs + at, DT_F64, (int64_t)w.size());
+      d.src = w.empty() ? nullptr : rec.aux(call, w.data(), w.size() * sizeof(const double*));
+      acc.push_back(d);
+      at += e->lat.Lr;
+    }
+  }
+  rec.ew(acc);
+  rec.run(call);
+  std::vector<double> hl(std::max<size_t>(nlog, 1));
+  dev::d2h(hl.data(), logs, sizeof(double) * nlog, ctx.stream);
+  dev::sync(ctx.stream);
+  at = 0;
+  for (peps_env* e : envs) {
+    const int Lr = e->lat.Lr;
+    for (int side = 0; side < 2; ++side) {
       std::vector<double>& lg = side == 0 ? e->top_log : e->bot_log;
-      lg.assign(Lr, 0.0);
-      for (int k = 1; k < (int)vec.size(); ++k) {
-        std::vector<double> om(vec[k].n_omega);
-        dev::d2h(om.data(), vec[k].omega, sizeof(double) * om.size(), ctx.stream);
-        dev::sync(ctx.stream);
-        const double w = om.back();
-        if (!(std::isfinite(w) && w > 0.0))
-          throw Error(ST_NONFINITE, "boundary row " + std::to_string(k - 1) + " has squared norm " + std::to_string(w));
-        lg[k] = lg[k - 1] + 0.5 * std::log(w);
-        if (vec[k].truncated) {
-          e->omegas.insert(e->omegas.end(), om.begin(), om.end());
-          e->n_trunc++;
-        }
+      lg.assign(hl.begin() + at, hl.begin() + at + Lr);
+      at += Lr;
+      for (int k = 1; k < Lr; ++k)
+        if (!std::isfinite(lg[k]))
+          throw Error(ST_NONFINITE, "boundary row " + std::to_string(k - 1) + " (side " + std::to_string(side) +
+                                        ") has a non-finite or non-positive squared norm");
+      if (e->opts.strict) {
+        const std::vector<Mps>& vec = side == 0 ? e->top : e->bot;
+        for (size_t k = 1; k < vec.size(); ++k)
+          if (!vec[k].converged)
+            throw Error(ST_NOT_CONVERGED, "boundary row " + std::to_string(k - 1) + " (side " + std::to_string(side) +
+                                              ") reached max_halfsweeps before the tolerance");
       }
     }
   }

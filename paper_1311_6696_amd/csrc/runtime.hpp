@@ -198,12 +198,16 @@ struct Mps {
   std::vector<int> bond;   // Lc+1 entries, bond[0] = bond[Lc] = 1
   std::vector<int> leg;    // Lc entries
   const double* omega = nullptr;   // device slots of the squared centre norms (null: closing)
-  int n_omega = 0;                 // 1 for an exact row, halfsweeps for a truncated one
+  int n_omega = 0;                 // 1 for an exact row, the half-sweeps run for a truncated one
   bool truncated = false;
+  bool converged = true;           // false: stopped at max_halfsweeps before the tolerance
 };
 
 struct Opts {
   int chi = 1, dtype = 0, halfsweeps = 4;
+  int max_halfsweeps = 4;   // > halfsweeps only with tol > 0
+  double tol = 0.0;         // relative change of the squared centre norm that ends the ALS sweeps
+  bool strict = false;      // an unconverged row fails the call
   uint64_t seed = 0;
   bool columns = false;   // also the left and right boundaries
   int prec() const { return dtype; }
@@ -230,9 +234,7 @@ struct peps_env {
   std::shared_ptr<void> shared_owner;             // keeps a parent's packed data alive
   std::vector<pe::Mps> top;   // top[k] = T_{k-1}: rows 0..k-1 absorbed, k = 0..Lr-1
   std::vector<pe::Mps> bot;   // bot[k]: rows Lr-k..Lr-1 absorbed (flipped frame)
-  std::vector<double> top_log, bot_log;   // cumulative log-scales
-  std::vector<double> omegas;             // per truncated row, halfsweeps values
-  int n_trunc = 0;
+  std::vector<double> top_log, bot_log;   // cumulative log-scales (accumulated on the device, FP64)
   bool window = false;
   int ci = 0, cj = 0;                     // centre (window coordinates)
   double flops = 0.0;

@@ -36,7 +36,7 @@ def test_null_arguments_are_rejected_without_a_device():
     lib = binding.load()
     lib.peps_env_free(None)
     lib.peps_ctx_destroy(None)
-    assert lib.peps_env_info(None, None, None, None) == -1
+    assert lib.peps_env_info(None, None, None, None, None, None) == -1
     assert b"must not be NULL" in lib.peps_last_error()
     assert lib.peps_expect(None, None, 0, None) == -1
     assert lib.peps_env_boundary(None, None, 0, None, None) == -1
@@ -59,7 +59,7 @@ def test_missing_library_fails_loudly(tmp_path):
 def test_struct_layouts_match_header():
     # sizes of the records shared with C (x86-64 ABI)
     assert C.sizeof(binding.State) == 4 * 3 + 4 + 8 + 8
-    assert C.sizeof(binding.Opts) == 4 * 4 + 8
+    assert C.sizeof(binding.Opts) == 4 * 4 + 8 + 2 * 4 + 8
     assert C.sizeof(binding.Window) == 7 * 4
     assert C.sizeof(binding.Result) == 5 * 8
     assert C.sizeof(binding.SiteReq) == 8 + 4 * 4 + 3 * 8   # r, c, dir and padding
@@ -81,4 +81,13 @@ def test_option_flags_match_header():
     text = open(os.path.join(ROOT, "include", "peps_env.h")).read()
     assert binding.OPTS_PER_STATE == int(re.search(r"#define PEPS_OPTS_PER_STATE (\d+)", text).group(1))
     assert binding.OPTS_COLUMNS == int(re.search(r"#define PEPS_OPTS_COLUMNS (\d+)", text).group(1))
-    assert binding.OPTS_PER_STATE & binding.OPTS_COLUMNS == 0
+    assert binding.OPTS_STRICT == int(re.search(r"#define PEPS_OPTS_STRICT (\d+)", text).group(1))
+    flags = (binding.OPTS_PER_STATE, binding.OPTS_COLUMNS, binding.OPTS_STRICT)
+    assert all(a & b == 0 for i, a in enumerate(flags) for b in flags[i + 1:])
+
+
+def test_status_codes_match_header():
+    text = open(os.path.join(ROOT, "include", "peps_env.h")).read()
+    for code, name in binding.STATUS.items():
+        if code:
+            assert int(re.search(r"PEPS_ERR_%s = (-\d+)" % name, text).group(1)) == code, name

@@ -84,6 +84,29 @@ def test_truncated_parity(sess, case):
         np.testing.assert_allclose(got, want, rtol=1e-10)
 
 
+def test_tolerance_stop_parity(sess):
+    """ALS with the omega tolerance: every truncated row runs the oracle's
+    number of half-sweeps (on this state no stopping decision lies within
+    10 % of the tolerance, so rounding cannot flip one), with the same
+    squared centre norms, and the observables agree."""
+    say("tolerance stop 4x4 D=3 chi=6")
+    A = make_peps(4, 4, 3, "near_product", 8)
+    env = sess.env_boundary([binding.to_device(A)], 6, halfsweeps=2, tol=1e-12, max_halfsweeps=60)[0]
+    r = sess.expect([env])[0]
+    w, sweeps, unconv = env.info(full=True)
+    env.free()
+    oenv = api.env_boundary(A, 6, 2, tol=1e-12, max_halfsweeps=60)
+    ref = api.expect(oenv)
+    rows = [i for row in (oenv.top, oenv.bottom) for (_, _, i) in row[1:] if not i.exact]
+    assert unconv == 0
+    assert list(sweeps) == [len(i.omegas) for i in rows]
+    for k, i in enumerate(rows):
+        np.testing.assert_allclose(w[k, :len(i.omegas)], i.omegas, rtol=1e-10)
+        assert np.all(np.isnan(w[k, len(i.omegas):]))
+    assert max_obs_diff(r, ref) < TOL64
+    assert abs(r["log_norm"] - ref["log_norm"]) < TOL64 * max(1.0, abs(ref["log_norm"]))
+
+
 def test_product_state(sess):
     say("product state 3x5")
     A = product_state(3, 5, seed=2)
