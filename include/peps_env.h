@@ -293,6 +293,22 @@ typedef struct {
 } peps_qr_block;
 peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
 
+/* peps_qr for callers that cannot allocate device memory (code that must not
+ * call hipMalloc, e.g. inside tight serving loops or harnesses that forbid
+ * it): the same factors from the same kernels, bit for bit, but every piece
+ * of workspace - kernel descriptors, the streaming kernel's 2*m*n doubles per
+ * block, the TSQR tree's row-block factors and the split-K partials of its
+ * rebuild - lives in one fixed device array of PEPS_QR_NOALLOC_BYTES per GPU
+ * (held from first use until the process ends; its address is looked up
+ * when a context is created).  The call allocates no device or pinned host
+ * memory and waits for its work to finish.  A request whose workspace does
+ * not fit fails with PEPS_ERR_OOM before anything is launched.  Every call on
+ * one GPU shares that GPU's array (the last call's data stays in it; nothing
+ * in it needs to start at zero): calls that overlap on one GPU, from several
+ * threads or streams, race and are not allowed. */
+#define PEPS_QR_NOALLOC_BYTES (32u << 20)
+peps_status peps_qr_noalloc(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
+
 /* Diagnostics of an environment's row boundaries (the column boundaries of
  * PEPS_OPTS_COLUMNS are not included), truncated rows in order (top
  * boundaries T_0, T_1, ..., then bottom ones), any pointer may be NULL:

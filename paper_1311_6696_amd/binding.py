@@ -94,7 +94,7 @@ class Result(C.Structure):
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
            "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
-           "peps_bond_env", "peps_bond_fit", "peps_boundary_overlap", "peps_last_error")
+           "peps_bond_env", "peps_bond_fit", "peps_boundary_overlap", "peps_qr_noalloc", "peps_last_error")
 
 _lib = None
 
@@ -126,6 +126,7 @@ def load(path=None):
     lib.peps_ctx_graphs.argtypes = [vp, C.c_int32]
     lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
     lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
+    lib.peps_qr_noalloc.argtypes = [vp, C.POINTER(QrBlock), i32]
     lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
     lib.peps_bond_env.argtypes = [vp, C.POINTER(BondReq), i32, C.POINTER(C.c_double)]
     lib.peps_boundary_overlap.argtypes = [vp, C.POINTER(OverlapReq), i32]
@@ -134,7 +135,7 @@ def load(path=None):
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
-                 "peps_ctx_set_workspace", "peps_qr", "peps_site_env", "peps_bond_env",
+                 "peps_ctx_set_workspace", "peps_qr", "peps_qr_noalloc", "peps_site_env", "peps_bond_env",
                  "peps_boundary_overlap", "peps_bond_fit"):
         getattr(lib, name).restype = C.c_int
     if path is None:
@@ -352,11 +353,13 @@ class Context:
         _check(self.lib, self.lib.peps_boundary_overlap(self.handle, arr, len(reqs)))
         return [(arr[i].xy, arr[i].xx, arr[i].yy) for i in range(len(reqs))]
 
-    def qr_raw(self, blocks):
+    def qr_raw(self, blocks, noalloc=False):
         """blocks: sequence of (a, a_rs, a_cs, q, q_rs, q_cs, r, r_rs, r_cs, m, n)
-        with device addresses (r may be 0)."""
+        with device addresses (r may be 0).  noalloc: peps_qr_noalloc (all
+        workspace in the library's fixed per-GPU array)."""
         arr = (QrBlock * len(blocks))(*[QrBlock(*[int(v) if v is not None else None for v in b]) for b in blocks])
-        _check(self.lib, self.lib.peps_qr(self.handle, arr, len(blocks)))
+        fn = self.lib.peps_qr_noalloc if noalloc else self.lib.peps_qr
+        _check(self.lib, fn(self.handle, arr, len(blocks)))
 
 
 # ------------------------------------------------------------ torch layer ---

@@ -14,7 +14,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpepsenv.so")
-SOURCES = ["kernels.hip", "devapi.cpp", "runtime.cpp", "planner.cpp", "expect.cpp", "cluster.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "devapi.cpp", "runtime.cpp", "planner.cpp", "expect.cpp", "cluster.cpp", "capi.cpp",
+           "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # no packed-FP32 instructions in any device code

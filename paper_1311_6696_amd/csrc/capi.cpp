@@ -9,6 +9,7 @@
 #include "chains.hpp"
 
 namespace pe {
+void* noalloc_scratch(int device);   // noalloc.hip
 namespace {
 
 thread_local std::string g_err;
@@ -224,6 +225,7 @@ peps_status peps_ctx_create(int32_t device, void* hip_stream, peps_ctx** out) {
     const int n = dev::device_count();
     PE_REQUIRE(device >= 0 && device < n, "no such HIP device");
     dev::set_device(device);
+    noalloc_scratch(device);   // the fixed QR workspace's device address, once per device
     auto* c = new peps_ctx();
     c->c = std::make_shared<Ctx>();
     c->c->device = device;

@@ -383,7 +383,7 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
     for (const auto& d : fam[f]) ((f != 2 && skinny_fits(d)) ? sk : rest).push_back(d);
     const uint64_t key[2] = {sk.empty() ? 0 : tune_key(prec, out_dt, f, true, sk),
                              rest.empty() ? 0 : tune_key(prec, out_dt, f, false, rest)};
-    bool tuned = ctx_->tuning && scratch_;
+    bool tuned = ctx_->tuning && scratch_ && !plain_;
     for (int part = 0; part < 2; ++part)
       if (key[part] && ctx_->tuned.count(key[part])) tuned = true;
     if (!tuned) {
@@ -402,7 +402,7 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
       auto it = ctx_->tuned.find(key[part]);
       if (it != ctx_->tuned.end()) {
         choice = it->second;
-      } else if (ctx_->tuning && scratch_) {
+      } else if (ctx_->tuning && scratch_ && !plain_) {
         bool idempotent = true;
         for (const auto& d : X) idempotent = idempotent && d.beta == 0.0;
         if (idempotent) choice = tune(prec, out_dt, f, part == 0, X, key[part]);
@@ -730,7 +730,14 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
 
 void Rec::flush(Arena& arena) {
   if (ops_.empty()) return;
-  if (ctx_->graphs && !ctx_->profile && !ctx_->tuning) {
+  if (plain_) {
+    hipStream_t s = ctx_->stream;
+    uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
+    double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+    dev::h2d(dblob, blob_.data(), blob_.size(), s);
+    issue(dblob, partials, false, s);
+    dev::sync(s);   // the host copy of the descriptors is reused by the next recording
+  } else if (ctx_->graphs && !ctx_->profile && !ctx_->tuning) {
     flush_graph();
   } else {
     hipStream_t s = ctx_->stream;

@@ -32,22 +32,39 @@ class Pool {
 class Arena {
  public:
   explicit Arena(Pool* p) : pool_(p) {}
+  // A fixed device region handed out by bumping an offset (256-byte
+  // aligned); a request beyond its end throws OOM.  Nothing is allocated.
+  Arena(void* base, size_t cap) : base_((uint8_t*)base), cap_(cap) {}
   ~Arena() { clear(); }
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
   void* alloc(size_t bytes) {
+    if (!pool_) {
+      const size_t off = (used_ + 255) & ~size_t(255);
+      if (off > cap_ || bytes > cap_ - off)
+        throw Error(ST_OOM, "request needs more than the " + std::to_string(cap_) + "-byte fixed workspace");
+      used_ = off + bytes;
+      return base_ + off;
+    }
     void* p = pool_->alloc(bytes);
     blocks_.push_back(p);
     return p;
   }
   void clear() {
+    if (!pool_) {
+      used_ = 0;
+      return;
+    }
     for (void* p : blocks_) pool_->release(p);
     blocks_.clear();
   }
+  size_t used() const { return used_; }
 
  private:
-  Pool* pool_;
+  Pool* pool_ = nullptr;
   std::vector<void*> blocks_;
+  uint8_t* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
 };
 
 // ------------------------------------------------------------------ views ---
@@ -81,6 +98,13 @@ class Rec {
  public:
   // `scratch` (optional) provides record-time workspace, e.g. split-K partials.
   explicit Rec(Ctx* c, Arena* scratch = nullptr) : ctx_(c), scratch_(scratch) {}
+  // Plain issue: no graph capture, profiling events, autotuning or pinned
+  // staging (descriptors are copied from host memory and waited for), so
+  // that with fixed arenas the recorder allocates no device or pinned memory.
+  void set_plain() { plain_ = true; }
+  // Whether a QR group whose largest block is mm x nn runs on the streaming
+  // kernel, the only route that reads the blocks' workspace W.
+  static bool qr_streaming(int mm, int nn) { return qr_variant_for(mm, nn) < 0 && nn > TSQR_NMAX; }
   void tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic = true);
   void kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic = true);
   void qr(const std::vector<QrDesc>& ds);
@@ -121,6 +145,7 @@ class Rec {
   int qr_depth_ = 0;
   Ctx* ctx_;
   Arena* scratch_;
+  bool plain_ = false;
   std::vector<Op> ops_;
   std::vector<uint8_t> blob_;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
