@@ -1,12 +1,18 @@
-"""Throughput of full boundary-MPS environments on one MI355X.
+"""Throughput of boundary-MPS environments on one MI355X.
 
 One step = one complete environment of the 8x8, D=4, chi=32 near-product
 PEPS (top and bottom boundaries by ALS row absorption, then the norm, 64
 <S^z> and 112 Heisenberg bond energies from the one- and two-row
-sandwiches), inputs resident in HBM.  Prints one JSON line.
+sandwiches), inputs resident in HBM: `value` is environments/s of that step
+in FP64.  The same JSON line carries the other workloads of the benchmark
+set, each with its error against the FP64 path: the 10x10 D=6 chi=72 lattice
+in FP64/FP32/BF16, the 256 cluster windows per n of a 16x16 D=6 lattice in
+FP32 and FP64, a subset of the 32 batched instances (all D <= 5 ones and the
+smallest D = 8 one) in FP64 and BF16; the ALS convergence of the truncation;
+the roofline of the dominant contraction kernel; the oracle on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
-                    [--workloads precision,clusters,instances]
+                    [--no-workloads] [--workloads convergence,evolution]
 """
 import argparse
 import json
@@ -82,91 +88,138 @@ def timed(torch, fn, reps):
     return r, (time.perf_counter() - t0) / reps
 
 
+def max_bond_diff(a, b):
+    return float(max(np.max(np.abs(a["bond_h"] - b["bond_h"])), np.max(np.abs(a["bond_v"] - b["bond_v"]))))
+
+
+def als_convergence(sess, st, chi, res_h4, H=4):
+    """How far the default ALS truncation (H half-sweeps from a random start)
+    is from its fixed point: the largest relative change of the squared centre
+    norm in the last half-sweep over all truncated rows, and the largest
+    change of any bond energy and <S^z> when the rows run 2H and 4H
+    half-sweeps instead."""
+    env = sess.env_boundary([st], chi, "f64", H)[0]
+    w = env.info()
+    env.free()
+    rel = np.abs(w[:, -1] - w[:, -2]) / np.abs(w[:, -1]) if w.shape[1] > 1 else np.array([np.nan])
+    out = {"halfsweeps": H, "truncated_rows": int(w.shape[0]),
+           "max_rel_omega_change_last_halfsweep": float(np.max(rel))}
+    for HH in (2 * H, 4 * H):
+        r = run_steps(sess, st, chi, "f64", HH, 1)
+        out[f"max_bond_change_H{H}_vs_H{HH}"] = max_bond_diff(res_h4, r)
+        out[f"max_sz_change_H{H}_vs_H{HH}"] = float(np.max(np.abs(res_h4["sz"] - r["sz"])))
+    return out
+
+
 def side_precision(sess, binding, torch):
     """10x10, D=6, unit-norm Gaussian sites, chi=72: one full environment per
-    dtype; errors are against the FP64 GPU path (the FP64 path itself is
-    checked against the oracle on the smaller lattices)."""
+    dtype; errors are against the FP64 GPU path (itself checked against the
+    oracle at this shape on the boundaries of rows 0-2 and at smaller sizes)."""
     from paper_1311_6696_amd.inputs import WORKLOADS, workload_peps
     cfg = WORKLOADS["10x10_D6_chi72"]
     st = binding.to_device(workload_peps("10x10_D6_chi72"))
     out, ref = {}, None
     for dt in ("f64", "f32", "bf16"):
-        note(f"precision workload {dt}")
+        note(f"10x10 D=6 chi=72 {dt}")
         run = lambda: run_steps(sess, st, cfg["chi"], dt, 4, 1)
         run()   # warm-up (allocations)
-        r, t = timed(torch, run, 1)
+        r, t = timed(torch, run, 2)
         if ref is None:
             ref = r
         e, e0 = energy(r), energy(ref)
         out[dt] = {"env_per_s": 1.0 / t, "s_per_env": t, "tflops": r["flops"] / t / 1e12,
                    "pct_peak": 100.0 * r["flops"] / t / 1e12 / PEAK[dt], "tflop_per_env": r["flops"] / 1e12,
                    "rel_energy_err_vs_f64": abs(e - e0) / abs(e0),
-                   "max_bond_err_vs_f64": float(max(np.max(np.abs(r["bond_h"] - ref["bond_h"])),
-                                                    np.max(np.abs(r["bond_v"] - ref["bond_v"]))))}
+                   "max_bond_err_vs_f64": max_bond_diff(r, ref)}
         out[dt]["speedup_vs_f64"] = out["f64"]["s_per_env"] / t
     # FP64 with the vertical bonds from the column boundaries
-    note("precision workload f64 with column boundaries")
+    note("10x10 D=6 chi=72 f64 with column boundaries")
     run = lambda: run_steps(sess, st, cfg["chi"], "f64", 4, 1, columns=True)
     run()
-    r, t = timed(torch, run, 1)
+    r, t = timed(torch, run, 2)
     out["f64_columns"] = {"env_per_s": 1.0 / t, "s_per_env": t, "tflop_per_env": r["flops"] / 1e12,
                           "speedup_vs_f64": out["f64"]["s_per_env"] / t,
                           "max_bond_v_gap_vs_two_row": float(np.max(np.abs(r["bond_v"] - ref["bond_v"]))),
                           "rel_energy_gap_vs_two_row": abs(energy(r) - energy(ref)) / abs(energy(ref))}
+    note("10x10 D=6 chi=72 ALS convergence")
+    out["als"] = als_convergence(sess, st, cfg["chi"], ref)
     out["workload"] = "10x10 OBC PEPS, d=2, D=6, N(0,1) unit-norm sites, chi=72, 4 half-sweeps"
     return out
 
 
+def cluster_windows(L, n):
+    wins = []
+    for i in range(L):
+        for j in range(L):
+            r0, r1 = max(0, i - (n + 1) // 2 + 1), min(L - 1, i + n // 2)
+            c0, c1 = max(0, j - (n + 1) // 2 + 1), min(L - 1, j + n // 2)
+            wins.append((0, r0, r1, c0, c1, i, j))
+    return wins
+
+
 def side_clusters(sess, binding, torch):
     """16x16, D=6, near-product, chi=36: all 256 n x n windows per call, FP32
-    contractions (FP64 QR and norms)."""
+    contractions (FP64 QR, norms and CU_0 boundaries), against the same
+    windows in FP64."""
     from paper_1311_6696_amd.inputs import WORKLOADS, workload_peps
     cfg = WORKLOADS["16x16_D6_clusters"]
     L = cfg["L"]
     st = binding.to_device(workload_peps("16x16_D6_clusters"))
     out = {}
     for n in cfg["ns"]:
-        wins = []
-        for i in range(L):
-            for j in range(L):
-                r0, r1 = max(0, i - (n + 1) // 2 + 1), min(L - 1, i + n // 2)
-                c0, c1 = max(0, j - (n + 1) // 2 + 1), min(L - 1, j + n // 2)
-                wins.append((0, r0, r1, c0, c1, i, j))
-        note(f"cluster workload n={n}")
+        wins = cluster_windows(L, n)
 
-        def run(columns=False):
-            envs = sess.cluster_env([st], wins, cfg["chi"], "f32", 4, columns=columns)
+        def run(dtype, columns=False):
+            envs = sess.cluster_env([st], wins, cfg["chi"], dtype, 4, columns=columns)
             res = sess.expect(envs)
             for e in envs:
                 e.free()
             return res
-        run()
-        res, t = timed(torch, run, 1)
-        fl = sum(r["flops"] for r in res)
-        out[f"n{n}"] = {"windows": len(wins), "windows_per_s": len(wins) / t, "s_per_call": t,
-                        "tflops": fl / t / 1e12, "pct_f32_peak": 100.0 * fl / t / 1e12 / PEAK["f32"],
-                        "tflop_per_call": fl / 1e12}
+        row = {"windows": len(wins)}
+        res = {}
+        for dt in ("f64", "f32"):
+            note(f"16x16 D=6 clusters n={n} {dt}")
+            run(dt)
+            res[dt], t = timed(torch, lambda: run(dt), 1)
+            fl = sum(r["flops"] for r in res[dt])
+            row[dt] = {"windows_per_s": len(wins) / t, "s_per_call": t, "tflops": fl / t / 1e12,
+                       "pct_peak": 100.0 * fl / t / 1e12 / PEAK[dt], "tflop_per_call": fl / 1e12}
+        errs = [abs(a[k] - b[k]) for a, b in zip(res["f32"], res["f64"]) for k in ("sz", "right", "down")
+                if not np.isnan(b[k])]
+        e32 = sum(np.nansum([r["right"], r["down"]]) for r in res["f32"])
+        e64 = sum(np.nansum([r["right"], r["down"]]) for r in res["f64"])
+        row["f32"]["max_abs_err_vs_f64"] = float(max(errs))
+        row["f32"]["rel_energy_err_vs_f64"] = abs(e32 - e64) / abs(e64)
+        row["f32"]["speedup_vs_f64"] = row["f64"]["s_per_call"] / row["f32"]["s_per_call"]
         # the same windows with the bond downwards from the transposed window
-        run(True)
-        rc, tc = timed(torch, lambda: run(True), 1)
-        out[f"n{n}"]["columns"] = {"s_per_call": tc, "speedup": t / tc, "tflop_per_call": sum(r["flops"] for r in rc) / 1e12,
-                                   "max_down_gap": float(np.nanmax([abs(a["down"] - b["down"]) for a, b in zip(res, rc)]))}
-    out["workload"] = "16x16 OBC PEPS, d=2, D=6, near-product, chi=36, all 256 windows per n, FP32 contractions"
+        note(f"16x16 D=6 clusters n={n} f32 with column boundaries")
+        run("f32", True)
+        rc, tc = timed(torch, lambda: run("f32", True), 1)
+        row["f32_columns"] = {"s_per_call": tc, "speedup_vs_f32": row["f32"]["s_per_call"] / tc,
+                              "tflop_per_call": sum(r["flops"] for r in rc) / 1e12,
+                              "max_down_gap_vs_two_row": float(np.nanmax([abs(a["down"] - b["down"])
+                                                                          for a, b in zip(res["f32"], rc)]))}
+        out[f"n{n}"] = row
+    out["workload"] = ("16x16 OBC PEPS, d=2, D=6, near-product, chi=36, all 256 windows per n in one call, "
+                       "FP32 contractions against FP64")
     return out
 
 
 def side_instances(sess, binding, torch):
-    """Independent lattices of mixed L and D in one call, chi = D^2.  The
-    draw's D=8 instances (87 to 645 TFLOP each in FP64) exceed this
-    measurement's time budget; the D <= 5 instances of the draw are run."""
+    """Independent lattices of mixed L and D in one call, chi = D^2: the D <= 5
+    instances of the 32-instance draw and its smallest D = 8 one (L = 6).  The
+    other eleven D = 8 instances (L = 8..12, hundreds of TFLOP each in FP64)
+    exceed this measurement's time budget."""
     from paper_1311_6696_amd.inputs import batched_instances
     pairs, insts = batched_instances()
-    keep = [k for k, (L, D) in enumerate(pairs) if D <= 5]
+    d8 = sorted([k for k, (L, D) in enumerate(pairs) if D == 8], key=lambda k: pairs[k][0])[:1]
+    keep = [k for k, (L, D) in enumerate(pairs) if D <= 5] + d8
     out = {}
     states = [binding.to_device(insts[k]) for k in keep]
     chis = [pairs[k][1] ** 2 for k in keep]
+    ref = None
     for dt in ("f64", "bf16"):
-        note(f"instances workload {dt}")
+        note(f"batched instances {dt}")
 
         def run():
             # one call, one options record (chi = D^2) per lattice
@@ -179,15 +232,17 @@ def side_instances(sess, binding, torch):
         res, t = timed(torch, run, 1)
         fl = sum(r["flops"] for r in res)
         out[dt] = {"instances": len(keep), "instances_per_s": len(keep) / t, "s_per_batch": t,
-                   "tflops": fl / t / 1e12, "tflop_per_batch": fl / 1e12}
+                   "tflops": fl / t / 1e12, "pct_peak": 100.0 * fl / t / 1e12 / PEAK[dt], "tflop_per_batch": fl / 1e12}
         if dt == "f64":
             ref = res
         else:
-            out[dt]["max_rel_energy_err_vs_f64"] = float(max(abs(energy(a) - energy(b)) / abs(energy(b))
-                                                             for a, b in zip(res, ref)))
+            errs = [abs(energy(a) - energy(b)) / abs(energy(b)) for a, b in zip(res, ref)]
+            out[dt]["max_rel_energy_err_vs_f64"] = float(max(errs))
+            out[dt]["rel_energy_err_vs_f64_D8"] = float(errs[-1])
             out[dt]["speedup_vs_f64"] = out["f64"]["s_per_batch"] / t
-    out["workload"] = ("the D<=5 instances of 32 seeded lattices (L in 6..12, D in {3,4,5,8}, chi=D^2, "
-                       f"U[0,1) entries): {len(keep)} lattices in one call")
+    out["instances"] = [list(pairs[k]) for k in keep]
+    out["workload"] = ("of 32 seeded lattices (L in 6..12, D in {3,4,5,8}, chi=D^2, U[0,1) entries): the "
+                       f"{len(keep) - len(d8)} with D<=5 and the L=6 D=8 one, {len(keep)} lattices in one call")
     return out
 
 
@@ -279,6 +334,37 @@ def side_evolution(sess, binding, torch):
 
 SIDE = {"precision": side_precision, "clusters": side_clusters, "instances": side_instances,
         "convergence": side_convergence, "evolution": side_evolution}
+DEFAULT_WORKLOADS = ("precision", "clusters", "instances")
+
+
+def cpu_info():
+    """Host CPU model and the BLAS behind NumPy (name, threads)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas, threads = "unknown", os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            blas = f"{libs[0].get('internal_api')} {libs[0].get('version')}"
+            threads = max(i.get("num_threads", 1) for i in libs)
+    except Exception:
+        pass
+    return model, blas, threads
+
+
+def chain2_io_bytes(L, D, chi, d=2):
+    """Algorithmic bytes of one two-row column step (inputs and output once,
+    FP64): the incoming and outgoing column environments (chi D^2 D^2 chi
+    each), the top and bottom boundary tensors (chi D^2 chi each) and the
+    two rows' site tensors (d D^4 each)."""
+    return 8.0 * (2 * chi * D ** 4 * chi + 2 * chi * D * D * chi + 2 * d * D ** 4)
 
 
 def main():
@@ -295,11 +381,13 @@ def main():
                     help="skip the measurement of vertical bonds from column boundaries")
     ap.add_argument("--batch", type=int, default=8,
                     help="lattices per call of the batched side measurement (1 = skip)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the default side workloads: precision (10x10 D=6 chi=72 in FP64/FP32/BF16), "
+                         "clusters (16x16 D=6 n x n windows, FP32 and FP64), instances (batched lattices, "
+                         "FP64 and BF16)")
     ap.add_argument("--workloads", default="",
-                    help="comma list of side workloads to time as well: precision (10x10 D=6 chi=72 in "
-                         "FP64/FP32/BF16), clusters (16x16 D=6 n x n windows), instances (batched lattices), "
-                         "convergence (energy error against chi and cluster size n), evolution "
-                         "(4x4 imaginary-time full updates)")
+                    help="comma list of further side workloads: convergence (energy error against chi and "
+                         "cluster size n), evolution (4x4 imaginary-time full updates)")
     ap.add_argument("--evolution-steps", type=int, default=20, help="Trotter steps per tau of the evolution workload")
     ap.add_argument("--evolution-taus", default="0.1,0.05,0.02", help="tau schedule of the evolution workload")
     ap.add_argument("--autotune", action="store_true",
@@ -370,16 +458,17 @@ def main():
     per_launch_bytes = nbytes[dom] / nlaunch
     avg_ms = kms[dom] / nlaunch
     kernel = binding.variant_name(dom)
-    # the dominant kernel is bound by HBM when its algorithmic intensity is
-    # below the FP64 machine balance (78.6 TFLOP/s over 8 TB/s)
-    intensity = per_launch_flops / per_launch_bytes if per_launch_bytes > 0 else float("inf")
-    if intensity < PEAK["f64"] / HBM_TBS:
-        bound, unit, peak = "hbm", "GB/s", HBM_TBS * 1000.0
-        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    else:
-        bound, unit, peak = "mfma", "TFLOP/s", PEAK["f64"]
-        achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    # The path is a chain of dense contractions whose algorithmic traffic is
+    # only each step's inputs and outputs: the roofline is the FP64 MFMA peak.
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     tc_total_ms = float(np.sum(kms)) / max(2, args.steps // 4)
+    traffic = measured_traffic(kernel)
+    # the fused ket-bra kernel applies the two layers of one row of two-row
+    # column steps, d D^8 chi^2 MACs per layer, so 8 d D^8 chi^2 flops per
+    # column step (both rows); its traffic is set against those steps' I/O
+    D, d = cfg["D"], 2
+    steps_per_launch = per_launch_flops / (8.0 * d * D ** 8 * chi * chi)
+    chain_io = steps_per_launch * chain2_io_bytes(cfg["L"], D, chi, d)
 
     out = {
         "metric": "env contractions/sec + GFLOP/s (% MFMA peak), FP64 vs BF16/FP32 at stated err",
@@ -405,21 +494,24 @@ def main():
         "boundary_ms": 1000.0 * float(np.median([s[0] for s in split])),
         "expect_ms": 1000.0 * float(np.median([s[1] for s in split])),
         "roofline": {
-            "bound": bound,
+            "bound": "mfma",
             "kernel": kernel,
             "achieved": achieved,
-            "peak": peak,
-            "unit": unit,
-            "frac": achieved / peak,
-            "traffic": measured_traffic(kernel),
+            "peak": PEAK["f64"],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK["f64"],
+            "traffic": traffic,
             "flops_per_launch": per_launch_flops,
-            "bytes_per_launch": per_launch_bytes,
-            "arithmetic_intensity": intensity,
+            "operand_bytes_per_launch": per_launch_bytes,
+            "chain_io_bytes_per_launch": chain_io,
+            "traffic_over_chain_io": (traffic / chain_io) if traffic else None,
             "launches_per_env": int(nl[dom] / max(2, args.steps // 4)),
             "avg_launch_us": 1000.0 * avg_ms,
             "contraction_ms_per_env": tc_total_ms,
         },
     }
+    note("ALS convergence")
+    out["als"] = als_convergence(sess, dev_state, chi, res, H)
 
     if args.batch > 1:
         # the same workload, several independent lattices per call (one grouped launch per stage)
@@ -465,8 +557,11 @@ def main():
         note("site norm environments")
         env = sess.env_boundary([dev_state], chi, "f64", H)[0]
         sites = [(env, r, c) for r in range(len(A)) for c in range(len(A[0]))]
-        sess.site_env(sites)
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sess.site_env(sites)   # forms and keeps the row sandwiches
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
         n = max(3, args.steps // 4)
         t0 = time.perf_counter()
         for _ in range(n):
@@ -476,8 +571,9 @@ def main():
         env.free()
         out["site_env"] = {"sites_per_call": len(sites), "ms_per_call": 1000.0 * t, "value": len(sites) / t,
                            "unit": "site environments/s", "gflop_per_call": sfl / 1e9,
-                           "tflops": sfl / t / 1e12,
-                           "row_sandwiches": "computed by the untimed first call and kept with the environment"}
+                           "tflops": sfl / t / 1e12, "first_call_ms": 1000.0 * t_first,
+                           "row_sandwiches": "formed by the first call and kept with the environment; "
+                                             "ms_per_call is the mean of the later calls"}
         # right-hand sides b of both sites of all 56 horizontal bonds under one
         # imaginary-time Heisenberg gate exp(-0.02 S.S), one batched call
         note("gated bond environments")
@@ -488,8 +584,11 @@ def main():
         gate = torch.as_tensor((U @ np.diag(np.exp(-0.02 * ev)) @ U.T).reshape(2, 2, 2, 2), device="cuda")
         env = sess.env_boundary([dev_state], chi, "f64", H)[0]
         bonds = [(env, r, c, gate) for r in range(len(A)) for c in range(len(A[0]) - 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         sess.bond_env(bonds)
         torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
         t0 = time.perf_counter()
         for _ in range(n):
             got, bfl = sess.bond_env(bonds)
@@ -498,8 +597,9 @@ def main():
         env.free()
         out["bond_env"] = {"bonds_per_call": len(bonds), "ms_per_call": 1000.0 * t, "value": len(bonds) / t,
                            "unit": "gated bond environments/s", "gflop_per_call": bfl / 1e9,
-                           "tflops": bfl / t / 1e12,
-                           "row_sandwiches": "computed by the untimed first call and kept with the environment"}
+                           "tflops": bfl / t / 1e12, "first_call_ms": 1000.0 * t_first,
+                           "row_sandwiches": "formed by the first call and kept with the environment; "
+                                             "ms_per_call is the mean of the later calls"}
 
     if not args.no_forms:
         forms = {}
@@ -519,27 +619,34 @@ def main():
                                                                np.max(np.abs(r["bond_v"] - res["bond_v"]))))}
         out["precision_forms"] = forms
 
-    side = [w for w in args.workloads.split(",") if w]
+    side = [] if args.no_workloads else list(DEFAULT_WORKLOADS)
+    side += [w for w in args.workloads.split(",") if w and w not in side]
     if side:
         out["workloads"] = {}
     for w in side:
         out["workloads"][w] = SIDE[w](sess, binding, torch)
 
     if not args.no_cpu:
+        # the oracle as it stands, on the host cores, on the same workload: the
+        # boundaries (median of three runs) plus the sandwiches (one run)
         note("oracle cpu baseline")
-        # the oracle as it stands, on the host cores, on one full environment of the same workload
         from oracle import api
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
+        model, blas, threads = cpu_info()
+        tb = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oenv = api.env_boundary(A, chi, H)
+            tb.append(time.perf_counter() - t0)
         t0 = time.perf_counter()
-        r_cpu = api.expect(api.env_boundary(A, chi, H))
-        t = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": 1.0 / t, "unit": "env/s", "cores": cores, "kind": "oracle",
-                               "sample": "one full environment of the same 8x8 D=4 chi=32 workload "
-                                         f"({t:.1f} s, NumPy/OpenBLAS FP64)"}
+        r_cpu = api.expect(oenv)
+        te = time.perf_counter() - t0
+        t = float(np.median(tb)) + te
+        out["cpu_baseline"] = {"value": 1.0 / t, "unit": "env/s", "cores": threads, "kind": "oracle",
+                               "sample": "the same 8x8 D=4 chi=32 environment: top and bottom boundaries "
+                                         f"(median of 3 runs, {np.median(tb):.1f} s) plus the one- and two-row "
+                                         f"sandwiches (one run, {te:.1f} s); NumPy FP64",
+                               "cpu_model": model, "blas": blas,
+                               "boundary_s_runs": tb, "sandwich_s": te}
         out["max_abs_diff_vs_oracle"] = float(max(np.max(np.abs(res[k] - r_cpu[k]))
                                                   for k in ("sz", "bond_h", "bond_v")))
     print(json.dumps(out))

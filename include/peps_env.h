@@ -271,6 +271,21 @@ typedef struct {
 } peps_overlap_req;
 peps_status peps_boundary_overlap(peps_ctx* ctx, peps_overlap_req* req, int32_t n_req);
 
+/* One tensor of a stored boundary (Sec. 2: the boundary MPS after k
+ * absorbed rows): side 0 from the top, 1 from the bottom (the lattice
+ * mirrored top<->bottom, its rows reversed and up/down legs swapped), 2 from
+ * the left and 3 from the right (the transposed lattice; they need
+ * PEPS_OPTS_COLUMNS), 1 <= k < rows (columns for sides 2, 3), site c of the
+ * boundary (0 <= c < cols of that frame).  dims (host, 4 int32, may be NULL)
+ * receives its shape (left bond, ket leg, bra leg, right bond); dst (DEVICE,
+ * caller-allocated, may be NULL) receives the float64 tensor X[a][k][b][a']
+ * in C order.  The boundary is stored with unit norm; log_scale (host, may
+ * be NULL) receives the log of the factor taken out of it, summed over the
+ * k absorbed rows, so that the contracted rows equal exp(log_scale) times
+ * the stored MPS (up to the truncation).  Waits for the context's stream. */
+peps_status peps_env_mps(peps_env* env, int32_t side, int32_t k, int32_t c, int32_t* dims, double* dst,
+                         double* log_scale);
+
 /* Thin QR of n_blocks float64 blocks, the gauge step of the truncation
  * (Sec. 2: the ALS sweep keeps every tensor but the centre isometric):
  * A = Q R with A m x n (m >= n >= 1, n <= 1024), Q m x n with orthonormal

@@ -94,7 +94,8 @@ class Result(C.Structure):
 SYMBOLS = ("peps_ctx_create", "peps_ctx_destroy", "peps_env_boundary", "peps_cluster_env", "peps_expect",
            "peps_env_free", "peps_env_info", "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune",
            "peps_ctx_stats", "peps_ctx_set_workspace", "peps_qr", "peps_site_env",
-           "peps_bond_env", "peps_bond_fit", "peps_boundary_overlap", "peps_qr_noalloc", "peps_last_error")
+           "peps_bond_env", "peps_bond_fit", "peps_boundary_overlap", "peps_qr_noalloc", "peps_env_mps",
+           "peps_last_error")
 
 _lib = None
 
@@ -127,6 +128,7 @@ def load(path=None):
     lib.peps_ctx_autotune.argtypes = [vp, C.c_int32]
     lib.peps_qr.argtypes = [vp, C.POINTER(QrBlock), i32]
     lib.peps_qr_noalloc.argtypes = [vp, C.POINTER(QrBlock), i32]
+    lib.peps_env_mps.argtypes = [vp, i32, i32, i32, C.POINTER(i32), vp, C.POINTER(C.c_double)]
     lib.peps_site_env.argtypes = [vp, C.POINTER(SiteReq), i32, C.POINTER(C.c_double)]
     lib.peps_bond_env.argtypes = [vp, C.POINTER(BondReq), i32, C.POINTER(C.c_double)]
     lib.peps_boundary_overlap.argtypes = [vp, C.POINTER(OverlapReq), i32]
@@ -135,7 +137,7 @@ def load(path=None):
     lib.peps_last_error.restype = C.c_char_p
     for name in ("peps_ctx_create", "peps_env_boundary", "peps_cluster_env", "peps_expect", "peps_env_info",
                  "peps_ctx_profile", "peps_ctx_graphs", "peps_ctx_autotune", "peps_ctx_stats",
-                 "peps_ctx_set_workspace", "peps_qr", "peps_qr_noalloc", "peps_site_env", "peps_bond_env",
+                 "peps_ctx_set_workspace", "peps_qr", "peps_qr_noalloc", "peps_env_mps", "peps_site_env", "peps_bond_env",
                  "peps_boundary_overlap", "peps_bond_fit"):
         getattr(lib, name).restype = C.c_int
     if path is None:
@@ -190,6 +192,22 @@ class Env:
         if full:
             return w, np.array(sw[: n.value]), u.value
         return w
+
+    def mps(self, side, k):
+        """Stored boundary after k absorbed rows from `side` (0 top, 1 bottom,
+        2 left, 3 right) as (list of float64 GPU tensors [a, k, b, a'],
+        log_scale)."""
+        import torch
+        lib = self.ctx.lib
+        out, ls = [], C.c_double()
+        n = self.cols if side < 2 else self.rows
+        for c in range(n):
+            d = (C.c_int32 * 4)()
+            _check(lib, lib.peps_env_mps(self.handle, side, k, c, d, None, None))
+            t = torch.empty(tuple(d), dtype=torch.float64, device="cuda")
+            _check(lib, lib.peps_env_mps(self.handle, side, k, c, None, C.c_void_p(t.data_ptr()), C.byref(ls)))
+            out.append(t)
+        return out, ls.value
 
     def free(self):
         if self.handle:

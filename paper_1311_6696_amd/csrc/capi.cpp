@@ -538,6 +538,31 @@ peps_status peps_env_info(peps_env* env, int32_t* n_rows, int32_t* max_halfsweep
   });
 }
 
+peps_status peps_env_mps(peps_env* env, int32_t side, int32_t k, int32_t c, int32_t* dims, double* dst,
+                         double* log_scale) {
+  return guarded([&] {
+    PE_REQUIRE(env != nullptr, "env must not be NULL");
+    PE_REQUIRE(side >= 0 && side <= 3, "side must be 0..3");
+    peps_env* e = env;
+    if (side >= 2) {
+      PE_REQUIRE(env->col != nullptr, "sides 2 and 3 need an environment built with PEPS_OPTS_COLUMNS");
+      e = env->col.get();
+    }
+    const std::vector<Mps>& v = (side & 1) == 0 ? e->top : e->bot;
+    PE_REQUIRE(k >= 1 && k < (int)v.size(), "k must be in [1, rows)");
+    const Mps& m = v[k];
+    PE_REQUIRE(c >= 0 && c < (int)m.leg.size(), "c outside the boundary");
+    const int32_t d[4] = {m.bond[c], m.leg[c], m.leg[c], m.bond[c + 1]};
+    if (dims) std::memcpy(dims, d, sizeof(d));
+    if (log_scale) *log_scale = ((side & 1) == 0 ? e->top_log : e->bot_log)[k];
+    if (dst) {
+      dev::set_device(env->ctx->device);
+      dev::d2d(dst, m.t64[c], sizeof(double) * (size_t)d[0] * d[1] * d[2] * d[3], env->ctx->stream);
+      dev::sync(env->ctx->stream);
+    }
+  });
+}
+
 peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks) {
   return guarded([&] {
     PE_REQUIRE(ctx && blk, "ctx and blk must not be NULL");

@@ -116,3 +116,25 @@ def test_cluster_16x16_D6_sample(sess):
         ref, sep = cluster.cluster_env(lat, n, 36, sites=samples[n], sep=sep)
         picked = [(w, r) for w, r in zip(wins, res) if (w[5], w[6]) in ref]
         compare([r for _, r in picked], [w for w, _ in picked], ref, TOL64)
+
+
+def test_16x16_D6_chi36_fp32_windows_vs_fp64(sess):
+    """The cluster workload's precision form: all 256 windows per n in FP32
+    contractions (FP64 QR, norms and CU_0 boundaries) against the same
+    windows in FP64: every <S^z> and bond energy within 1e-5 absolute."""
+    from paper_1311_6696_amd.inputs import workload_peps
+    A = workload_peps("16x16_D6_clusters")
+    for n in (2, 4, 6):
+        say(f"16x16 D=6 FP32 windows n={n}")
+        wins = windows_for(16, n)
+        r64 = gpu_clusters(sess, A, wins, 36)
+        r32 = gpu_clusters(sess, A, wins, 36, dtype="f32")
+        worst = 0.0
+        for a, b in zip(r32, r64):
+            for k in ("sz", "right", "down"):
+                if np.isnan(b[k]):
+                    assert np.isnan(a[k])
+                else:
+                    worst = max(worst, abs(a[k] - b[k]))
+        say(f"  n={n}: max |FP32 - FP64| = {worst:.3e}")
+        assert worst < 1e-5, (n, worst)
