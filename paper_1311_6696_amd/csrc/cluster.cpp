@@ -127,9 +127,13 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
         if (D.Lr < 2) continue;
         std::vector<SepSite> fs;
         int64_t tot = 0;
+        int dmax = 1;
         for (int k = 0; k < D.Lr; ++k)
           for (int c = 0; c < D.Lc; ++c) {
             fs.push_back(frame_site(st[i], dir, k, c));
+            const SepSite& q = fs.back();
+            PE_REQUIRE(q.d <= 2, "CU_0 boundaries need physical dimension <= 2");
+            dmax = std::max({dmax, q.Dl, q.Du, q.Dr, q.Dd});
             if (k + 1 < D.Lr) {
               D.off.push_back(tot);
               tot += (int64_t)fs.back().Dd * fs.back().Dd;
@@ -144,12 +148,13 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
         sd.Lr = D.Lr;
         sd.Lc = D.Lc;
         sd.max_sweeps = 500;
+        sd.dmax = dmax;
         sd.tol = 1e-14;
         sd.sites = (const SepSite*)rec.aux(tmp, fs.data(), fs.size() * sizeof(SepSite));
         sd.off = (const int64_t*)rec.aux(tmp, D.off.data(), D.off.size() * sizeof(int64_t));
         sd.sig = D.sig64;
         const size_t V = SEP_MAXD * SEP_MAXD;
-        sd.work = (double*)tmp.alloc(sizeof(double) * ((3 * (size_t)D.Lc + 3) * V + 4 * V * V));
+        sd.work = (double*)tmp.alloc(sizeof(double) * ((3 * (size_t)D.Lc + 3) * V + 2 * V * V));
         sd.sweeps = D.sweeps;
         sd.delta = D.delta;
         seps.push_back(sd);

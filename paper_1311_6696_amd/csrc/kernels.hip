@@ -1812,232 +1812,339 @@ void launch_ew(const EwDesc* d, int nd, int nb, hipStream_t s) {
 
 // ===========================================================================
 // CU_0 separable boundaries (one workgroup per lattice direction).
+//
+// Every site step contracts one site's two layers with D x D matrices on its
+// four legs, O(d D^5) per step (Sec. 5.1).  The steps of a direction form
+// one long dependent chain (rows, sweeps, sites), so the kernel is built for
+// latency: one 1024-thread workgroup per direction; the site tensor, the
+// matrices on its legs and the two intermediates live in LDS, every virtual
+// leg padded with zeros to the direction's largest bond DM (a template
+// argument, so index arithmetic is by constants; the zeros change no sum);
+// the final contraction over four legs (DM^2 outputs by d DM^3 terms) is
+// split over all threads in fixed slices, summed in slice order.  The b of a
+// site and the environment update in the same direction share their first
+// two contractions.
 // ===========================================================================
 namespace {
 
 constexpr int SEP_V = SEP_MAXD * SEP_MAXD;            // one D x D matrix slot
-constexpr int SEP_W = 2 * SEP_V * SEP_V;               // d * D^4 with d <= 2
+constexpr int SEP_T = 1024;                           // threads per workgroup
+
+struct SepSh {
+  double* A;      // staged site [p][l][u][r][d], legs padded to DM
+  double* W1;
+  double* W2;
+  double* part;   // SEP_T partial sums
+  double* B;      // DM x DM
+  double* red;    // SEP_T / 64
+  double* e;      // the step's left, up, right and down matrices, DM x DM each
+  double* su;
+  double* f;
+  double* sg;
+};
 
 __device__ inline double sepA(const SepSite& s, int p, int l, int u, int r, int d) {
   return s.A[p * s.sp + l * s.sl + u * s.su + r * s.sr + d * s.sd];
 }
 
+__device__ inline double sep_block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < SEP_T / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Copy an n x n matrix (row stride n) into a zero-padded DM x DM one.
+template <int DM>
+__device__ inline void sep_pad(double* dst, const double* src, int n) {
+  const int i = threadIdx.x;
+  if (i < DM * DM) {
+    const int a = i / DM, b = i % DM;
+    dst[i] = (a < n && b < n) ? src[a * n + b] : 0.0;
+  }
+}
+
+// Stage one site step's operands in LDS (null matrices: not needed by this
+// step; `pad_env` false: e and f are already padded DM x DM slots).
+template <int DM>
+__device__ void sep_stage(const SepSite& s, const SepSh& sh, const double* e, const double* su, const double* f,
+                          const double* sg) {
+  constexpr int V4 = DM * DM * DM * DM;
+  const int n = s.d * V4;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {
+    const int d = i % DM, r = (i / DM) % DM, u = (i / (DM * DM)) % DM, l = (i / (DM * DM * DM)) % DM, p = i / V4;
+    sh.A[i] = (l < s.Dl && u < s.Du && r < s.Dr && d < s.Dd) ? sepA(s, p, l, u, r, d) : 0.0;
+  }
+  const int i = threadIdx.x;
+  if (e && i < DM * DM) sh.e[i] = e[i];
+  if (f && i < DM * DM) sh.f[i] = f[i];
+  if (su) sep_pad<DM>(sh.su, su, s.Du);
+  if (sg) sep_pad<DM>(sh.sg, sg, s.Dd);
+  __syncthreads();
+}
+
+// out[o] = sum over q < K of term(o, q) for o < DM^2: thread t takes output
+// t % DM^2 over the (t / DM^2)-th of SEP_T / DM^2 equal slices of q; the
+// slices are then summed in order.
+template <int DM, class F>
+__device__ void sep_reduce(int K, double* part, double* out, F term) {
+  constexpr int NO = DM * DM, ns = SEP_T / NO;
+  const int t = threadIdx.x;
+  if (t < ns * NO) {
+    const int o = t % NO, j = t / NO;
+    const int qa = (K * j) / ns, qb = (K * (j + 1)) / ns;
+    double acc = 0.0;
+    for (int q = qa; q < qb; ++q) acc += term(o, q);
+    part[t] = acc;
+  }
+  __syncthreads();
+  if (t < NO) {
+    double acc = 0.0;
+    for (int j = 0; j < ns; ++j) acc += part[j * NO + t];
+    out[t] = acc;
+  }
+  __syncthreads();
+}
+
 // Scale x[0..n) to unit Frobenius norm (every thread of the block calls this).
 __device__ void sep_unit(double* x, int n, double* red) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += x[i] * x[i];
-  s = block_sum256(s, red);
+  for (int i = threadIdx.x; i < n; i += SEP_T) s += x[i] * x[i];
+  s = sep_block_sum(s, red);
   const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) x[i] *= inv;
+  for (int i = threadIdx.x; i < n; i += SEP_T) x[i] *= inv;
   __syncthreads();
 }
 
-// W1[p][m][u][r][d] = sum_l e[l][m] A[p,l,u,r,d];  W2[p][m][v][r][d] = sum_u W1 su[u][v]
-__device__ void sep_left_half(const SepSite& s, const double* e, const double* su, double* W1, double* W2) {
-  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
-  const int n = P * Dl * Du * Dr * Dd;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int r = t % Dr; t /= Dr;
-    const int u = t % Du; t /= Du;
-    const int m = t % Dl; t /= Dl;
-    const int p = t;
+// Left half of a site step: W2[p][m][v][r][d] = sum e[l][m] su[u][v] A[p,l,u,r,d]
+template <int DM>
+__device__ void sep_left(int P, const SepSh& sh) {
+  const int n = P * DM * DM * DM * DM;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {   // W1[p][m][u][r][d] = sum_l e[l][m] A[p,l,u,r,d]
+    const int urd = i % (DM * DM * DM), m = (i / (DM * DM * DM)) % DM, p = i / (DM * DM * DM * DM);
     double acc = 0.0;
-    for (int l = 0; l < Dl; ++l) acc += e[l * Dl + m] * sepA(s, p, l, u, r, d);
-    W1[i] = acc;
+#pragma unroll
+    for (int l = 0; l < DM; ++l) acc += sh.e[l * DM + m] * sh.A[(p * DM + l) * DM * DM * DM + urd];
+    sh.W1[i] = acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 256) {
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int r = t % Dr; t /= Dr;
-    const int v = t % Du; t /= Du;
-    const int pm = t;   // p*Dl + m
+  for (int i = threadIdx.x; i < n; i += SEP_T) {   // W2[p][m][v][r][d] = sum_u W1[p][m][u][r][d] su[u][v]
+    const int rd = i % (DM * DM), v = (i / (DM * DM)) % DM, pm = i / (DM * DM * DM);
     double acc = 0.0;
-    for (int u = 0; u < Du; ++u) acc += W1[((pm * Du + u) * Dr + r) * Dd + d] * su[u * Du + v];
-    W2[i] = acc;
+#pragma unroll
+    for (int u = 0; u < DM; ++u) acc += sh.W1[(pm * DM + u) * DM * DM + rd] * sh.su[u * DM + v];
+    sh.W2[i] = acc;
   }
   __syncthreads();
 }
 
-// b[d][g] = sum e[l][m] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] f[r][s]
-__device__ void sep_b(const SepSite& s, const double* e, const double* su, const double* f, double* W1, double* W2,
-                      double* out) {
-  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
-  sep_left_half(s, e, su, W1, W2);
-  const int n = P * Dl * Du * Dr * Dd;
-  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][m][v][s][d] = sum_r W2[p][m][v][r][d] f[r][s]
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int ss = t % Dr; t /= Dr;
-    const int pmv = t;
+// Right half: W2[p][l][v][s][d] = sum f[r][s] su[u][v] A[p,l,u,r,d]
+template <int DM>
+__device__ void sep_right(int P, const SepSh& sh) {
+  const int n = P * DM * DM * DM * DM;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {   // W1[p][l][u][s][d] = sum_r A[p,l,u,r,d] f[r][s]
+    const int d = i % DM, ss = (i / DM) % DM, plu = i / (DM * DM);
     double acc = 0.0;
-    for (int r = 0; r < Dr; ++r) acc += W2[(pmv * Dr + r) * Dd + d] * f[r * Dr + ss];
-    W1[i] = acc;
+#pragma unroll
+    for (int r = 0; r < DM; ++r) acc += sh.A[(plu * DM + r) * DM + d] * sh.f[r * DM + ss];
+    sh.W1[i] = acc;
   }
   __syncthreads();
-  const int K = P * Dl * Du * Dr;
-  for (int o = threadIdx.x; o < Dd * Dd; o += 256) {
-    const int d = o / Dd, g = o % Dd;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {   // W2[p][l][v][s][d] = sum_u W1[p][l][u][s][d] su[u][v]
+    const int sd = i % (DM * DM), v = (i / (DM * DM)) % DM, pl = i / (DM * DM * DM);
     double acc = 0.0;
-    for (int q = 0; q < K; ++q) {
-      int t = q;
-      const int ss = t % Dr; t /= Dr;
-      const int v = t % Du; t /= Du;
-      const int m = t % Dl; t /= Dl;
-      const int p = t;
-      acc += W1[q * Dd + d] * sepA(s, p, m, v, ss, g);
-    }
-    out[o] = acc;
+#pragma unroll
+    for (int u = 0; u < DM; ++u) acc += sh.W1[(pl * DM + u) * DM * DM + sd] * sh.su[u * DM + v];
+    sh.W2[i] = acc;
   }
   __syncthreads();
 }
 
-// e'[r][s] = sum e[l][m] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] sig[d][g]
-__device__ void sep_eupd(const SepSite& s, const double* e, const double* su, const double* sg, double* W1,
-                         double* W2, double* out) {
-  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
-  sep_left_half(s, e, su, W1, W2);
-  const int n = P * Dl * Du * Dr * Dd;
-  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][m][v][r][g] = sum_d W2[p][m][v][r][d] sg[d][g]
-    const int g = i % Dd, base = i - g;
+// b[d][g] = sum_{p,m,v,s} W1[p][m][v][s][d] A[p,m,v,s,g] (W1 made by the caller)
+template <int DM>
+__device__ void sep_b_final(int P, const SepSh& sh, double* out) {
+  const double* W = sh.W1;
+  const double* A = sh.A;
+  sep_reduce<DM>(P * DM * DM * DM, sh.part, out, [&](int o, int q) {
+    const int d = o / DM, g = o % DM;
+    return W[q * DM + d] * A[q * DM + g];
+  });
+}
+
+// b from the left half in W2: W1[p][m][v][s][d] = sum_r W2[p][m][v][r][d] f[r][s]
+template <int DM>
+__device__ void sep_b_from_left(int P, const SepSh& sh, double* out) {
+  const int n = P * DM * DM * DM * DM;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {
+    const int d = i % DM, ss = (i / DM) % DM, pmv = i / (DM * DM);
     double acc = 0.0;
-    for (int d = 0; d < Dd; ++d) acc += W2[base + d] * sg[d * Dd + g];
-    W1[i] = acc;
+#pragma unroll
+    for (int r = 0; r < DM; ++r) acc += sh.W2[(pmv * DM + r) * DM + d] * sh.f[r * DM + ss];
+    sh.W1[i] = acc;
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < Dr * Dr; o += 256) {
-    const int r = o / Dr, ss = o % Dr;
+  sep_b_final<DM>(P, sh, out);
+}
+
+// b from the right half in W2: W1[p][m][v][s][d] = sum_l e[l][m] W2[p][l][v][s][d]
+template <int DM>
+__device__ void sep_b_from_right(int P, const SepSh& sh, double* out) {
+  constexpr int V3 = DM * DM * DM;
+  const int n = P * DM * V3;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {
+    const int vsd = i % V3, m = (i / V3) % DM, p = i / (DM * V3);
     double acc = 0.0;
-    for (int p = 0; p < P; ++p)
-      for (int m = 0; m < Dl; ++m)
-        for (int v = 0; v < Du; ++v)
-          for (int g = 0; g < Dd; ++g)
-            acc += W1[(((p * Dl + m) * Du + v) * Dr + r) * Dd + g] * sepA(s, p, m, v, ss, g);
-    out[o] = acc;
+#pragma unroll
+    for (int l = 0; l < DM; ++l) acc += sh.e[l * DM + m] * sh.W2[(p * DM + l) * V3 + vsd];
+    sh.W1[i] = acc;
+  }
+  __syncthreads();
+  sep_b_final<DM>(P, sh, out);
+}
+
+// W1[...][g] = sum_d W2[...][d] sig[d][g] (the last leg contracted with sigma)
+template <int DM>
+__device__ void sep_close_down(int P, const SepSh& sh, const double* sg) {
+  const int n = P * DM * DM * DM * DM;
+  for (int i = threadIdx.x; i < n; i += SEP_T) {
+    const int g = i % DM, base = i - g;
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < DM; ++d) acc += sh.W2[base + d] * sg[d * DM + g];
+    sh.W1[i] = acc;
   }
   __syncthreads();
 }
 
-// f'[l][m] = sum f[r][s] su[u][v] A[p,l,u,r,d] A[p,m,v,s,g] sig[d][g]
-__device__ void sep_fupd(const SepSite& s, const double* f, const double* su, const double* sg, double* W1,
-                         double* W2, double* out) {
-  const int P = s.d, Dl = s.Dl, Du = s.Du, Dr = s.Dr, Dd = s.Dd;
-  const int n = P * Dl * Du * Dr * Dd;
-  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][l][u][s][d] = sum_r A[p,l,u,r,d] f[r][s]
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int ss = t % Dr; t /= Dr;
-    const int u = t % Du; t /= Du;
-    const int l = t % Dl; t /= Dl;
-    const int p = t;
-    double acc = 0.0;
-    for (int r = 0; r < Dr; ++r) acc += sepA(s, p, l, u, r, d) * f[r * Dr + ss];
-    W1[i] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 256) {   // W2[p][l][v][s][d] = sum_u W1[p][l][u][s][d] su[u][v]
-    int t = i;
-    const int d = t % Dd; t /= Dd;
-    const int ss = t % Dr; t /= Dr;
-    const int v = t % Du; t /= Du;
-    const int pl = t;
-    double acc = 0.0;
-    for (int u = 0; u < Du; ++u) acc += W1[((pl * Du + u) * Dr + ss) * Dd + d] * su[u * Du + v];
-    W2[i] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 256) {   // W1[p][l][v][s][g] = sum_d W2[p][l][v][s][d] sg[d][g]
-    const int g = i % Dd, base = i - g;
-    double acc = 0.0;
-    for (int d = 0; d < Dd; ++d) acc += W2[base + d] * sg[d * Dd + g];
-    W1[i] = acc;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < Dl * Dl; o += 256) {
-    const int l = o / Dl, m = o % Dl;
-    double acc = 0.0;
-    for (int p = 0; p < P; ++p)
-      for (int v = 0; v < Du; ++v)
-        for (int ss = 0; ss < Dr; ++ss)
-          for (int g = 0; g < Dd; ++g)
-            acc += W1[(((p * Dl + l) * Du + v) * Dr + ss) * Dd + g] * sepA(s, p, m, v, ss, g);
-    out[o] = acc;
-  }
-  __syncthreads();
+// e'[r][s] from the left half in W2 = sum_{p,m,v,g} (W2 sig)[p][m][v][r][g] A[p,m,v,s,g]
+template <int DM>
+__device__ void sep_e_from_left(int P, const SepSh& sh, const double* sg, double* out) {
+  sep_close_down<DM>(P, sh, sg);
+  const double* W = sh.W1;
+  const double* A = sh.A;
+  sep_reduce<DM>(P * DM * DM * DM, sh.part, out, [&](int o, int q) {   // q = (p, m, v, g)
+    const int r = o / DM, ss = o % DM, g = q % DM, pmv = q / DM;
+    return W[(pmv * DM + r) * DM + g] * A[(pmv * DM + ss) * DM + g];
+  });
+}
+
+// f'[l][m] from the right half in W2 = sum_{p,v,s,g} (W2 sig)[p][l][v][s][g] A[p,m,v,s,g]
+template <int DM>
+__device__ void sep_f_from_right(int P, const SepSh& sh, const double* sg, double* out) {
+  constexpr int V3 = DM * DM * DM;
+  sep_close_down<DM>(P, sh, sg);
+  const double* W = sh.W1;
+  const double* A = sh.A;
+  sep_reduce<DM>(P * V3, sh.part, out, [&](int o, int q) {   // q = (p, v, s, g)
+    const int l = o / DM, m = o % DM, vsg = q % V3, p = q / V3;
+    return W[(p * DM + l) * V3 + vsg] * A[(p * DM + m) * V3 + vsg];
+  });
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void sep_kernel(const SepDesc* __restrict__ ds) {
+template <int DM>
+__global__ __launch_bounds__(SEP_T) void sep_kernel(const SepDesc* __restrict__ ds, int a_in_lds) {
+  extern __shared__ double sep_lds[];
+  constexpr int V4 = DM * DM * DM * DM, V2 = DM * DM;
   const SepDesc& D = ds[blockIdx.x];
-  __shared__ double red[4];
-  __shared__ double one[1];
+  __shared__ double red[SEP_T / 64];
+  __shared__ double one[SEP_V];
+  __shared__ double part[SEP_T];
+  __shared__ double mats[5 * SEP_V];
+  const int P = D.sites[0].d;
+  SepSh sh;
+  sh.W1 = sep_lds;
+  sh.W2 = sep_lds + 2 * V4;
+  // the staged site: in LDS, or (DM = 8, where LDS holds only the two
+  // intermediates) in the direction's global work buffer
+  sh.A = a_in_lds ? sep_lds + 4 * V4 : D.work + (size_t)(3 * D.Lc + 3) * SEP_V;
+  sh.part = part;
+  sh.B = mats;
+  sh.e = mats + SEP_V;
+  sh.su = mats + 2 * SEP_V;
+  sh.f = mats + 3 * SEP_V;
+  sh.sg = mats + 4 * SEP_V;
+  sh.red = red;
   const int Lr = D.Lr, Lc = D.Lc;
-  double* E = D.work;                       // (Lc+1) slots
-  double* F = E + (size_t)(Lc + 1) * SEP_V;  // (Lc+1) slots
+  double* E = D.work;                        // (Lc+1) padded slots
+  double* F = E + (size_t)(Lc + 1) * SEP_V;  // (Lc+1) padded slots
   double* OLD = F + (size_t)(Lc + 1) * SEP_V;
-  double* W1 = OLD + (size_t)Lc * SEP_V;
-  double* W2 = W1 + SEP_W;
-  double* B = W2 + SEP_W;
-  if (threadIdx.x == 0) one[0] = 1.0;
+  if (threadIdx.x < V2) {
+    const double v = threadIdx.x == 0 ? 1.0 : 0.0;
+    one[threadIdx.x] = v;
+    E[threadIdx.x] = v;
+    F[(size_t)Lc * SEP_V + threadIdx.x] = v;
+  }
   __syncthreads();
   for (int k = 0; k + 1 < Lr; ++k) {
     const SepSite* row = D.sites + (size_t)k * Lc;
     auto sup = [&](int c) -> const double* { return k == 0 ? one : D.sig + D.off[(size_t)(k - 1) * Lc + c]; };
     auto sig = [&](int c) -> double* { return D.sig + D.off[(size_t)k * Lc + c]; };
+    // sigma start: identity / sqrt(D) (compact Dd x Dd in global memory)
     for (int c = 0; c < Lc; ++c) {
       const int Dd = row[c].Dd;
-      for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = (i / Dd == i % Dd) ? 1.0 / sqrt((double)Dd) : 0.0;
-    }
-    if (threadIdx.x == 0) {
-      E[0] = 1.0;
-      F[(size_t)Lc * SEP_V] = 1.0;
+      for (int i = threadIdx.x; i < Dd * Dd; i += SEP_T) sig(c)[i] = (i / Dd == i % Dd) ? 1.0 / sqrt((double)Dd) : 0.0;
     }
     __syncthreads();
     for (int c = Lc - 1; c >= 1; --c) {
-      sep_fupd(row[c], F + (size_t)(c + 1) * SEP_V, sup(c), sig(c), W1, W2, F + (size_t)c * SEP_V);
-      sep_unit(F + (size_t)c * SEP_V, row[c].Dl * row[c].Dl, red);
+      // k = 0: the up closing is the padded 1 x 1 identity (the up legs have dimension 1)
+      sep_stage<DM>(row[c], sh, nullptr, k == 0 ? nullptr : sup(c), F + (size_t)(c + 1) * SEP_V, sig(c));
+      if (k == 0 && threadIdx.x < V2) sh.su[threadIdx.x] = one[threadIdx.x];
+      __syncthreads();
+      sep_right<DM>(P, sh);
+      sep_f_from_right<DM>(P, sh, sh.sg, F + (size_t)c * SEP_V);
+      sep_unit(F + (size_t)c * SEP_V, V2, red);
     }
     int sweeps = 0;
     double delta = 0.0;
     while (true) {
       for (int c = 0; c < Lc; ++c)
-        for (int i = threadIdx.x; i < row[c].Dd * row[c].Dd; i += 256) OLD[(size_t)c * SEP_V + i] = sig(c)[i];
+        for (int i = threadIdx.x; i < row[c].Dd * row[c].Dd; i += SEP_T) OLD[(size_t)c * SEP_V + i] = sig(c)[i];
       __syncthreads();
-      for (int c = 0; c < Lc; ++c) {
-        const int Dd = row[c].Dd;
-        sep_b(row[c], E + (size_t)c * SEP_V, sup(c), F + (size_t)(c + 1) * SEP_V, W1, W2, B);
-        sep_unit(B, Dd * Dd, red);
-        for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = B[i];
-        __syncthreads();
-        if (c + 1 < Lc) {
-          sep_eupd(row[c], E + (size_t)c * SEP_V, sup(c), sig(c), W1, W2, E + (size_t)(c + 1) * SEP_V);
-          sep_unit(E + (size_t)(c + 1) * SEP_V, row[c].Dr * row[c].Dr, red);
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool l2r = pass == 0;
+        for (int s = 0; s < Lc; ++s) {
+          const int c = l2r ? s : Lc - 1 - s;
+          const int Dd = row[c].Dd;
+          sep_stage<DM>(row[c], sh, E + (size_t)c * SEP_V, k == 0 ? nullptr : sup(c), F + (size_t)(c + 1) * SEP_V,
+                        nullptr);
+          if (k == 0 && threadIdx.x < V2) sh.su[threadIdx.x] = one[threadIdx.x];
+          __syncthreads();
+          if (l2r) {   // b, then the left environment of c+1
+            sep_left<DM>(P, sh);
+            sep_b_from_left<DM>(P, sh, sh.B);
+          } else {     // b, then the right environment of c
+            sep_right<DM>(P, sh);
+            sep_b_from_right<DM>(P, sh, sh.B);
+          }
+          sep_unit(sh.B, V2, red);
+          for (int i = threadIdx.x; i < Dd * Dd; i += SEP_T) sig(c)[i] = sh.B[(i / Dd) * DM + i % Dd];
+          if (l2r && c + 1 < Lc) {
+            sep_e_from_left<DM>(P, sh, sh.B, E + (size_t)(c + 1) * SEP_V);
+            sep_unit(E + (size_t)(c + 1) * SEP_V, V2, red);
+          }
+          if (!l2r && c > 0) {
+            sep_f_from_right<DM>(P, sh, sh.B, F + (size_t)c * SEP_V);
+            sep_unit(F + (size_t)c * SEP_V, V2, red);
+          }
         }
       }
-      for (int c = Lc - 1; c >= 0; --c) {
-        const int Dd = row[c].Dd;
-        sep_b(row[c], E + (size_t)c * SEP_V, sup(c), F + (size_t)(c + 1) * SEP_V, W1, W2, B);
-        sep_unit(B, Dd * Dd, red);
-        for (int i = threadIdx.x; i < Dd * Dd; i += 256) sig(c)[i] = B[i];
-        __syncthreads();
-        if (c > 0) {
-          sep_fupd(row[c], F + (size_t)(c + 1) * SEP_V, sup(c), sig(c), W1, W2, F + (size_t)c * SEP_V);
-          sep_unit(F + (size_t)c * SEP_V, row[c].Dl * row[c].Dl, red);
-        }
-      }
+      __syncthreads();
       ++sweeps;
       double dmax = 0.0;
       for (int c = 0; c < Lc; ++c) {
         const int Dd = row[c].Dd;
         double s = 0.0;
-        for (int i = threadIdx.x; i < Dd * Dd; i += 256) {
+        for (int i = threadIdx.x; i < Dd * Dd; i += SEP_T) {
           const double x = sig(c)[i] - OLD[(size_t)c * SEP_V + i];
           s += x * x;
         }
-        s = block_sum256(s, red);
+        s = sep_block_sum(s, red);
         dmax = fmax(dmax, sqrt(s));
       }
       delta = dmax;
@@ -2051,9 +2158,28 @@ __global__ __launch_bounds__(256) void sep_kernel(const SepDesc* __restrict__ ds
   }
 }
 
-void launch_sep(const SepDesc* d, int nd, hipStream_t s) {
+template <int DM>
+static void sep_launch_dm(const SepDesc* d, int nd, hipStream_t s) {
+  const int v4 = (int)sizeof(double) * 2 * DM * DM * DM * DM;   // one d <= 2 site-sized array
+  const bool a_in_lds = 3 * v4 <= 136 * 1024;                   // W1, W2 and the site
+  const int lds = a_in_lds ? 3 * v4 : 2 * v4;
+  if (lds > 48 * 1024)
+    PE_HIP(hipFuncSetAttribute((const void*)sep_kernel<DM>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  sep_kernel<DM><<<nd, SEP_T, lds, s>>>(d, a_in_lds ? 1 : 0);
+}
+
+void launch_sep(const SepDesc* d, int nd, int dmax, hipStream_t s) {
   if (nd <= 0) return;
-  sep_kernel<<<nd, 256, 0, s>>>(d);
+  switch (dmax) {
+    case 1: case 2: sep_launch_dm<2>(d, nd, s); break;
+    case 3: sep_launch_dm<3>(d, nd, s); break;
+    case 4: sep_launch_dm<4>(d, nd, s); break;
+    case 5: sep_launch_dm<5>(d, nd, s); break;
+    case 6: sep_launch_dm<6>(d, nd, s); break;
+    case 7: sep_launch_dm<7>(d, nd, s); break;
+    case 8: sep_launch_dm<8>(d, nd, s); break;
+    default: throw Error(ST_UNSUPPORTED, "CU_0 boundaries support virtual bonds up to 8");
+  }
   PE_HIP(hipGetLastError());
 }
 

@@ -180,16 +180,19 @@ struct SepSite {
   int64_t sp, sl, su, sr, sd;   // strides of the frame's (p, l, u, r, d) legs
 };
 struct SepDesc {
-  int32_t Lr, Lc, max_sweeps, pad;
+  int32_t Lr, Lc, max_sweeps;
+  int32_t dmax;           // largest virtual bond of the direction's sites
   double tol;
   const SepSite* sites;   // Lr*Lc, frame row-major
   double* sig;            // sigma of frame row k, column c at sig + off[k*Lc + c] (Dd x Dd)
   const int64_t* off;
-  double* work;           // (3*Lc + 2) * SEP_MAXD^2 doubles
+  double* work;           // (3*Lc + 3) * SEP_MAXD^2 + 2 * SEP_MAXD^4 doubles
   int32_t* sweeps;        // Lr-1 entries
   double* delta;          // Lr-1 entries
 };
-void launch_sep(const SepDesc* d_desc, int n_desc, hipStream_t s);
+// dmax: the largest dmax of the descriptors (every leg is padded to it);
+// the physical dimension must be at most 2.
+void launch_sep(const SepDesc* d_desc, int n_desc, int dmax, hipStream_t s);
 
 // SplitMix64 (Steele, Lea, Flood 2014): output function and stream state.
 __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {

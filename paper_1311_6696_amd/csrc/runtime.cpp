@@ -684,7 +684,11 @@ void Rec::ew(std::vector<EwDesc> ds) {
 
 void Rec::sep(const std::vector<SepDesc>& ds) {
   if (ds.empty()) return;
-  ops_.push_back(Op{OK_SEP, 0, 0, 0, (int)ds.size(), (int)ds.size(), push_bytes(ds.data(), ds.size() * sizeof(SepDesc)), 0.0});
+  int dmax = 1;
+  for (const auto& d : ds) dmax = std::max(dmax, (int)d.dmax);
+  Op op{OK_SEP, 0, 0, 0, (int)ds.size(), (int)ds.size(), push_bytes(ds.data(), ds.size() * sizeof(SepDesc)), 0.0};
+  op.kp = dmax;
+  ops_.push_back(op);
 }
 
 void* Rec::aux(Arena& arena, const void* data, size_t bytes) {
@@ -718,7 +722,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
         break;
       case OK_RED: launch_reduce((const RedDesc*)d, op.nd, op.grid, partials, s); break;
       case OK_EW: launch_ew((const EwDesc*)d, op.nd, op.grid, s); break;
-      case OK_SEP: launch_sep((const SepDesc*)d, op.nd, s); break;
+      case OK_SEP: launch_sep((const SepDesc*)d, op.nd, op.kp, s); break;
     }
     if (e0) {
       void* e1 = dev::event_create();

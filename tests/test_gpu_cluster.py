@@ -53,7 +53,8 @@ def compare(res, wins, ref, tol):
     return worst
 
 
-@pytest.mark.parametrize("L,D,n,chi,H", [(4, 2, 2, 4, 4), (5, 2, 3, 4, 3), (6, 3, 4, 6, 2), (5, 2, 6, 4, 2)])
+@pytest.mark.parametrize("L,D,n,chi,H", [(4, 2, 2, 4, 4), (5, 2, 3, 4, 3), (6, 3, 4, 6, 2), (5, 2, 6, 4, 2),
+                                         (3, 8, 2, 64, 2), (4, 7, 2, 49, 2), (4, 5, 3, 9, 2)])
 def test_cluster_windows_parity(sess, L, D, n, chi, H):
     say(f"clusters L={L} D={D} n={n} chi={chi}")
     A = make_peps(L, L, D, "near_product", 40 + L + n)
