@@ -361,18 +361,18 @@ peps_status peps_ctx_graphs(peps_ctx* ctx, int32_t enable);
 
 /* Profiling of the contraction kernel: when enabled, every contraction
  * launch is bracketed by HIP events on the context's stream; statistics are
- * kept per kernel variant, index = (prec*2 + out_dtype)*15 + tile
+ * kept per kernel variant, index = (prec*2 + out_dtype)*16 + tile
  * (prec: 0 f64, 1 f32, 2 bf16; out_dtype: 0 f64, 1 f32; tile: 0 64x64,
  * 1 128x32, 2 256x16, 3 32x128, 4 64x32, 5 64x16, 6 128x48, 7 64x80,
  * 8..12 the skinny kernel for outputs up to 16, 32, 48, 64, 80 wide, 13..14
- * the fused ket-bra kernel for dr*p up to 16, 32).  Enabling clears the
- * statistics. */
+ * the fused ket-bra kernel for dr*p up to 16, 32, 15 the fused two-row
+ * column step).  Enabling clears the statistics. */
 peps_status peps_ctx_profile(peps_ctx* ctx, int32_t enable);
 /* Copies the PEPS_N_STATS per-variant statistics: algorithmic flops,
  * milliseconds, launch counts and algorithmic bytes (each operand read once,
  * the output written once) into host arrays of PEPS_N_STATS entries each;
  * bytes may be NULL. */
-#define PEPS_N_STATS 90
+#define PEPS_N_STATS 96
 peps_status peps_ctx_stats(peps_ctx* ctx, double* flops, double* ms, int64_t* launches, double* bytes);
 /* Upper bound (bytes) of the transient workspace one call may hold for the
  * chain intermediates of a batch (default 48 GiB, at least 1 MiB); larger

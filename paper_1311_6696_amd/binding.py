@@ -20,7 +20,7 @@ OPTS_COLUMNS = 2     # peps_env_opts.flags: also the left/right boundaries (vert
 OPTS_STRICT = 4      # peps_env_opts.flags: an ALS row that reaches max_halfsweeps before tol fails the call
 DEFAULT_SEED = 0x13116696
 TILES = ("64x64", "128x32", "256x16", "32x128", "64x32", "64x16", "128x48", "64x80",
-         "skinny16", "skinny32", "skinny48", "skinny64", "skinny80", "ketbra16", "ketbra32")
+         "skinny16", "skinny32", "skinny48", "skinny64", "skinny80", "ketbra16", "ketbra32", "tworow")
 N_STATS = 3 * 2 * len(TILES)
 
 
@@ -33,6 +33,8 @@ def variant_name(i):
         return f"tcs_kernel<{prec}, out={out}, N<={tile[6:]}>"
     if tile.startswith("ketbra"):
         return f"kb_kernel<{prec}, out={out}, dr*p<={tile[6:]}>"
+    if tile == "tworow":
+        return "k2_kernel (fused two-row column step, f64)"
     return f"tc_kernel<{prec}, out={out}, {tile}>"
 
 

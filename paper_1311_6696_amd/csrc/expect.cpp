@@ -144,6 +144,62 @@ TV step2_right(St& st, std::vector<TcDesc>& fin, const R2Job& j, int c, const TV
   return o;
 }
 
+// The fused two-row column step (k2_kernel) takes a column whose sites all
+// have legs of dimension K2_D and physical dimension 2, float64, bonds up to
+// K2_CHI.
+bool fuse2(const R2Job& j, int c, int prec) {
+  if (prec != TP_F64) return false;
+  for (const Site* s : {j.s1[c], j.s2[c]})
+    if (s->d != 2 || s->Dl != K2_D || s->Du != K2_D || s->Dr != K2_D || s->Dd != K2_D) return false;
+  if (j.T->leg[c] != K2_D || j.B->leg[c] != K2_D) return false;
+  for (int64_t b : {j.bT[c], j.bT[c + 1], j.bB[c], j.bB[c + 1]})
+    if (b < 1 || b > K2_CHI) return false;
+  return true;
+}
+
+// Algorithmic flops of one fused column step (those of the unfused chain):
+// top boundary, two ket and two bra layers, bottom boundary.
+double k2_flops(const K2Desc& d) {
+  return 2.0 * d.X * d.E * (256.0 * 16 * d.A + 4 * 131072.0 + 256.0 * 16 * d.Y);
+}
+
+// Canonical form of a two-row column step (see K2Desc): the left-to-right
+// step as it is, the right-to-left one with incoming and outgoing roles of
+// every horizontal leg and bond exchanged.
+K2Desc k2_desc(const R2Job& j, int c, bool left, const TV& in, const TV& out, int op1, int op2) {
+  const Site& a = *j.s1[c];
+  const Site& b = *j.s2[c];
+  TV T = dense(j.T->tc[c], DT_F64, "auve", {j.bT[c], j.T->leg[c], j.T->leg[c], j.bT[c + 1]});
+  TV B = dense(j.B->tc[c], DT_F64, "xDGy", {j.bB[c], j.B->leg[c], j.B->leg[c], j.bB[c + 1]});
+  const TV sv[4] = {site_tv(a, op1, false, DT_F64, "plurd"), site_tv(a, 0, false, DT_F64, "pmvsg"),
+                    site_tv(b, op2, false, DT_F64, "qLdRD"), site_tv(b, 0, false, DT_F64, "qMgSG")};
+  K2Desc d;
+  std::memset(&d, 0, sizeof(d));
+  d.L = (const double*)in.p;
+  d.T = (const double*)T.p;
+  d.B = (const double*)B.p;
+  d.O = (double*)const_cast<void*>(out.p);
+  for (int k = 0; k < 6; ++k) {
+    d.sL[k] = in.str[k];
+    d.sO[k] = out.str[k];
+  }
+  const int h[4] = {3, 1, 2, 0};   // exchange the horizontal roles: (a,u,v,e) -> (e,u,v,a)
+  for (int k = 0; k < 4; ++k) {
+    d.sT[k] = left ? T.str[k] : T.str[h[k]];
+    d.sB[k] = left ? B.str[k] : B.str[h[k]];
+  }
+  const int hs[5] = {0, 3, 2, 1, 4};   // (p, in, up, out, down) from (p, l, u, r, d)
+  for (int v = 0; v < 4; ++v) {
+    d.s[v] = (const double*)sv[v].p;
+    for (int k = 0; k < 5; ++k) d.ss[v][k] = left ? sv[v].str[k] : sv[v].str[hs[k]];
+  }
+  d.X = (int32_t)(left ? j.bB[c] : j.bB[c + 1]);
+  d.A = (int32_t)(left ? j.bT[c] : j.bT[c + 1]);
+  d.E = (int32_t)(left ? j.bT[c + 1] : j.bT[c]);
+  d.Y = (int32_t)(left ? j.bB[c + 1] : j.bB[c]);
+  return d;
+}
+
 // Normalise the raw outputs in place: nu = |X|^2 into `slot`, X /= sqrt(nu).
 void normalise(Rec& rec, const std::vector<std::pair<TV, double*>>& outs) {
   std::vector<RedDesc> rd;
@@ -246,6 +302,8 @@ void column_envs(Rec& rec, Arena& call, Scratch& scr, std::vector<RJob>& rj, std
     for (int s = 0; s < maxLc; ++s) {
       St st1(3, prec), st2(5, prec);
       std::vector<TcDesc> fin;
+      std::vector<K2Desc> k2s;
+      double k2f = 0.0;
       std::vector<std::pair<TV, double*>> outs;
       for (size_t i = g.first; i < g.second; ++i) {
         const Slot& sl = slots[i];
@@ -269,12 +327,21 @@ void column_envs(Rec& rec, Arena& call, Scratch& scr, std::vector<RJob>& rj, std
           R2Job& j = r2[sl.job];
           if (s >= j.Lc) continue;
           const double f0 = st2.flops;
+          const int c = sl.kind == 2 ? s : j.Lc - 1 - s;
+          if (fuse2(j, c, prec)) {   // the whole column step in one fused launch
+            const TV in = sl.kind == 2 ? env2v(j, j.L[c], c, "xLMlma", cdt) : env2v(j, j.R[c + 1], c + 1, "yRSrse", cdt);
+            const TV o = sl.kind == 2 ? env2v(j, j.L[c + 1], c + 1, "yRSrse", cdt) : env2v(j, j.R[c], c, "xLMlma", cdt);
+            k2s.push_back(k2_desc(j, c, sl.kind == 2, in, o, 0, 0));
+            const double f = k2_flops(k2s.back());
+            k2f += f;
+            j.e->flops += f;
+            outs.push_back({o, sl.kind == 2 ? j.nuL + c + 1 : j.nuR + c});
+            continue;
+          }
           if (sl.kind == 2) {
-            const int c = s;
             TV o = step2_left(st2, fin, j, c, env2v(j, j.L[c], c, "xLMlma", cdt), 0, 0, j.L[c + 1], p, q, cdt);
             outs.push_back({o, j.nuL + c + 1});
           } else {
-            const int c = j.Lc - 1 - s;
             TV o = step2_right(st2, fin, j, c, env2v(j, j.R[c + 1], c + 1, "yRSrse", cdt), j.R[c], p, q, cdt);
             outs.push_back({o, j.nuR + c});
           }
@@ -284,6 +351,7 @@ void column_envs(Rec& rec, Arena& call, Scratch& scr, std::vector<RJob>& rj, std
       st1.record(rec, prec, cdt);
       st2.record(rec, prec, cdt);
       rec.tc(prec, cdt, fin);
+      rec.k2(k2s, k2f);
       normalise(rec, outs);
       rec.flush(call);
     }
@@ -441,9 +509,21 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       for (auto g : budget_groups(sz, budget)) {
         St st1(3, prec), st2(5, prec);
         std::vector<TcDesc> fin;
+        std::vector<K2Desc> k2s;
+        double k2f = 0.0;
         std::vector<void*> tmp;
         for (size_t k = g.first; k < g.second; ++k) {
           const Item& it = items[k];
+          if (it.level == 2 && fuse2(r2[it.job], it.c, prec)) {   // the column step with the bond operators, fused
+            R2Job& j = r2[it.job];
+            k2s.push_back(k2_desc(j, it.c, true, env2v(j, j.L[it.c], it.c, "xLMlma", cdt),
+                                  env2v(j, Y2[it.job][it.c][it.t], it.c + 1, "yRSrse", cdt), BOND_O1[it.t],
+                                  BOND_O2[it.t]));
+            const double f = k2_flops(k2s.back());
+            k2f += f;
+            j.e->flops += f;
+            continue;
+          }
           if (it.level < 2) {
             RJob& j = rj[it.job];
             auto pq = step_scratch(j, it.level == 0 ? it.c : it.c + 1);
@@ -476,6 +556,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         st1.record(rec, prec, cdt);
         st2.record(rec, prec, cdt);
         rec.tc(prec, cdt, fin);
+        rec.k2(k2s, k2f);
         for (void* p : tmp) scr.put(p);
         rec.flush(call);
       }

@@ -2183,4 +2183,269 @@ void launch_sep(const SepDesc* d, int nd, int dmax, hipStream_t s) {
   PE_HIP(hipGetLastError());
 }
 
+// ===========================================================================
+// Fused two-row column step (see K2Desc).  1024 threads (16 waves) per
+// workgroup, one workgroup per (descriptor, e); the workgroup runs the whole
+// chain of the column step for x = 0..X-1: the top boundary absorbed into the
+// incoming environment, the ket and bra layers of row 1 and of row 2, then
+// the bottom boundary, accumulated over x in registers.  Wave w owns block
+// o = w of row 1 (o = its incoming legs (L, M)) and of row 2 (o = row 1's
+// outgoing legs (r, s)): everything a wave computes for its own block stays
+// in its private LDS area and needs no barrier; only row 1's output, which
+// row 2 reads across blocks, and the bottom boundary slab are shared; they
+// are double-buffered, so one barrier per x suffices.  Every intermediate lives in LDS (row pitches padded
+// against bank conflicts); HBM sees the incoming environment (read from L2
+// by the workgroups of one descriptor, which share an XCD), the boundary and
+// site tensors and the outgoing environment.  MFMA f64 16x16x4, issued as
+// D = B^T A^T so that lanes 0..15 run along the rows; 16 waves with at most
+// 128 registers each keep four waves on every SIMD.
+// ===========================================================================
+namespace {
+
+constexpr int K2_T = 1024, K2_W = 16;
+constexpr int K2_QP = 17;              // pitch of a [16][16] block (rows of 16 + 1)
+constexpr int K2_BP = 16 * K2_QP;      // one such block
+constexpr int K2_ZP = 33;              // pitch of the ket intermediate's rows
+constexpr int K2_PRIV = 16 * K2_ZP;    // private LDS of one wave (doubles): its block, or its ket rows
+
+__device__ inline d4_t k2_mma(double a, double b, d4_t c) {   // a: lane = (row, k); b: lane = (k, col)
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+}
+
+__device__ inline d4_t k2_zero() {
+  d4_t z;
+  z[0] = z[1] = z[2] = z[3] = 0.0;
+  return z;
+}
+
+// One row's ket and bra for one block, from the block's input In[q][k]
+// (pitch K2_QP; q the bra's contracted leg pair, k the ket's):
+//   Z[q][(ab,p)] = sum_k In[q][k] Ks[k][(ab,p)],  Y[ab][gs] = sum_(p,q) Z[q][(ab,p)] Bs[(p,q)][gs]
+// Z (pitch K2_ZP) may share the wave's private area with In: the whole block
+// is read into registers before Z is written.  Returns this lane's part of Y
+// (rows ab = lane & 15, columns gs = lane / 16 + 4j).
+// SW: In is an unpadded [16][16] block whose columns are XOR-swizzled per
+// row (column k of row q at q*16 + (k ^ k2_swz(q))), else a padded one.
+__device__ inline int k2_swz(int q) { return 4 * ((q >> 1) & 3); }
+
+template <bool SW>
+__device__ inline d4_t k2_row(const double* In, const double* Ks, const double* Bs, double* Z, int lr, int lk) {
+  double av[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) av[s] = SW ? In[lr * 16 + ((4 * s + lk) ^ k2_swz(lr))] : In[lr * K2_QP + 4 * s + lk];
+  d4_t z0 = k2_zero(), z1 = k2_zero();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    z0 = k2_mma(av[s], Ks[(4 * s + lk) * 32 + lr], z0);
+    z1 = k2_mma(av[s], Ks[(4 * s + lk) * 32 + 16 + lr], z1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();   // In is read before Z overwrites it
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    Z[lr * K2_ZP + lk + 4 * j] = z0[j];
+    Z[lr * K2_ZP + 16 + lk + 4 * j] = z1[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // two accumulators (even and odd k steps), so that consecutive MFMAs do not depend on each other
+  d4_t ya = k2_zero(), yb = k2_zero();
+#pragma unroll
+  for (int s = 0; s < 8; s += 2) {
+    const int ka = 4 * s + lk, kb = ka + 4;
+    const double za = Z[(ka & 15) * K2_ZP + lr * 2 + (ka >> 4)], ba = Bs[ka * 16 + lr];
+    const double zb = Z[(kb & 15) * K2_ZP + lr * 2 + (kb >> 4)], bq = Bs[kb * 16 + lr];
+    ya = k2_mma(za, ba, ya);
+    yb = k2_mma(zb, bq, yb);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();   // Z is read before the area is rewritten
+  return ya + yb;
+}
+
+}  // namespace
+
+template <int CH>   // largest bond of the launch (sizes registers and LDS)
+__global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds, int nd, int nblocks) {
+  __shared__ double Te[CH * 16];
+  __shared__ double K1s[16 * 32], B1s[32 * 16], K2s[16 * 32], B2s[32 * 16];
+  // shared, double-buffered by the parity of x: the bottom boundary slab and
+  // row 1's output [(r,s)][(M,g)][(L,d)] (swizzled [16][16] blocks)
+  __shared__ double Bx[2][16 * CH];
+  __shared__ double Y2[2][16 * 256];
+  __shared__ double Priv[K2_W * K2_PRIV];    // per wave: its block or its ket rows
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  double* Pw = Priv + w * K2_PRIV;
+  // XCD-aware order: consecutive virtual blocks (the e values of one
+  // descriptor) go to one XCD, so they share the incoming environment in L2
+  const int grid = gridDim.x, per = grid / 8;
+  const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (v >= nblocks) return;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
+  }
+  const K2Desc& d = ds[lo];
+  const int e = v - d.block_base;
+  const int X = d.X, A = d.A, Y = d.Y;
+  const int A4 = (A + 3) & ~3;
+  // ---- stage the site tensors and the top boundary column of this e
+  for (int i = tid; i < 512; i += K2_T) {
+    {   // K1s[(l,u)][(d,r,p)]
+      const int k = i >> 5, n = i & 31, l = k >> 2, u = k & 3, dd = n >> 3, r = (n >> 1) & 3, p = n & 1;
+      const int64_t* t = d.ss[0];
+      K1s[i] = d.s[0][p * t[0] + l * t[1] + u * t[2] + r * t[3] + dd * t[4]];
+    }
+    {   // B1s[(p,(m,v))][(g,s)]
+      const int row = i >> 4, col = i & 15, p = row >> 4, m = (row >> 2) & 3, vv = row & 3, g = col >> 2, sx = col & 3;
+      const int64_t* t = d.ss[1];
+      B1s[i] = d.s[1][p * t[0] + m * t[1] + vv * t[2] + sx * t[3] + g * t[4]];
+    }
+    {   // K2s[(L,d)][(D,R,q)]
+      const int k = i >> 5, n = i & 31, L = k >> 2, dd = k & 3, D = n >> 3, R = (n >> 1) & 3, q = n & 1;
+      const int64_t* t = d.ss[2];
+      K2s[i] = d.s[2][q * t[0] + L * t[1] + dd * t[2] + R * t[3] + D * t[4]];
+    }
+    {   // B2s[(q,(M,g))][(G,S)]
+      const int row = i >> 4, col = i & 15, q = row >> 4, M = (row >> 2) & 3, g = row & 3, G = col >> 2, S = col & 3;
+      const int64_t* t = d.ss[3];
+      B2s[i] = d.s[3][q * t[0] + M * t[1] + g * t[2] + S * t[3] + G * t[4]];
+    }
+  }
+  for (int i = tid; i < A4 * 16; i += K2_T) {
+    const int a = i >> 4, uv = i & 15;
+    Te[i] = a < A ? d.T[a * d.sT[0] + (uv >> 2) * d.sT[1] + (uv & 3) * d.sT[2] + e * d.sT[3]] : 0.0;
+  }
+  const int nct = (Y + 15) >> 4;   // column tiles of the output
+  d4_t out[CH / 16];
+#pragma unroll
+  for (int c = 0; c < CH / 16; ++c) out[c] = k2_zero();
+  // This lane's row of the incoming environment (its row-1 block) and its
+  // share of the bottom boundary slab; the values for x + 1 are loaded while
+  // x is computed (each after its x values have gone to LDS).  Loads are
+  // unconditional (indices clamped, values masked) so that they issue back
+  // to back.
+  const int64_t ro = (w >> 2) * d.sL[1] + (w & 3) * d.sL[2] + (lr >> 2) * d.sL[3] + (lr & 3) * d.sL[4];   // (L,M,l,m)
+  constexpr int KMAX = CH / 4;
+  constexpr int NBX = (16 * CH + K2_T - 1) / K2_T;
+  double lxf[KMAX];
+  double bxf[NBX];
+  auto load_l = [&](int x) {
+    const double* Lx = d.L + x * d.sL[0];
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (4 * ks < A4) {
+        const int a = 4 * ks + lk, ac = a < A ? a : A - 1;
+        const double val = Lx[ro + ac * d.sL[5]];
+        lxf[ks] = a < A ? val : 0.0;
+      }
+    }
+  };
+  auto load_b = [&](int x) {
+#pragma unroll
+    for (int j = 0; j < NBX; ++j) {
+      const int i = tid + K2_T * j;
+      if (i < 16 * CH) {
+        const int k = i / CH, y = i % CH, yc = y < Y ? y : Y - 1;
+        const double val = d.B[x * d.sB[0] + (k >> 2) * d.sB[1] + (k & 3) * d.sB[2] + yc * d.sB[3]];
+        bxf[j] = y < Y ? val : 0.0;
+      }
+    }
+  };
+  load_l(0);
+  load_b(0);
+  __syncthreads();
+
+  for (int x = 0; x < X; ++x) {
+    // ---- row 1 for this wave's block o = (L, M): y1[(l,m)][(u,v)] = sum_a Lin[x,L,M,l,m,a] T[a,u,v,e]
+    //      into the block [q=(m,v)][k=(l,u)], then ket and bra
+    {
+      d4_t acc = k2_zero(), acc2 = k2_zero();
+#pragma unroll
+      for (int ks = 0; ks < KMAX; ks += 2) {
+        if (4 * ks < A4) acc = k2_mma(lxf[ks], Te[(4 * ks + lk) * 16 + lr], acc);
+        if (4 * ks + 4 < A4) acc2 = k2_mma(lxf[ks + 1], Te[(4 * ks + 4 + lk) * 16 + lr], acc2);
+      }
+      acc += acc2;
+      const int l = lr >> 2, m = lr & 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int uv = lk + 4 * j, u = uv >> 2, vv = uv & 3;
+        Pw[(m * 4 + vv) * K2_QP + l * 4 + u] = acc[j];
+      }
+    }
+    if (x + 1 < X) load_l(x + 1);   // in flight during the rows and the bottom boundary
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const d4_t y2 = k2_row<false>(Pw, K1s, B1s, Pw, lr, lk);
+    // row 1's output y2[(L,M)=w][(d,r)][(g,s)] -> Y2 [(r,s)][(M,g)][(L,d)]; the bottom slab of x.
+    // The buffers of parity x & 1 were last read at x - 2, which every wave
+    // finished before the barrier of x - 1, so no barrier is needed here.
+    double* Y2x = Y2[x & 1];
+    double* Bxx = Bx[x & 1];
+    {
+      const int L = w >> 2, M = w & 3, dd = lr >> 2, r = lr & 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int gs = lk + 4 * j, g = gs >> 2, sx = gs & 3, q2 = M * 4 + g;
+        Y2x[(r * 4 + sx) * 256 + q2 * 16 + ((L * 4 + dd) ^ k2_swz(q2))] = y2[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NBX; ++j)
+      if (tid + K2_T * j < 16 * CH) Bxx[tid + K2_T * j] = bxf[j];
+    if (x + 1 < X) load_b(x + 1);   // in flight during row 2 and the bottom boundary
+    __syncthreads();
+    // ---- row 2 for this wave's block o = (r, s), then the bottom boundary:
+    //      out[(r,s)][(R,S)][y] += sum_(D,G) y3[(r,s)][(R,S)][(D,G)] Bx[(D,G)][y]
+    {
+      const d4_t y3 = k2_row<true>(Y2x + w * 256, K2s, B2s, Pw, lr, lk);   // rows (D,R), columns (G,S)
+      const int D = lr >> 2, R = lr & 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int GS = lk + 4 * j, G = GS >> 2, S = GS & 3;
+        Pw[(R * 4 + S) * K2_QP + D * 4 + G] = y3[j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      double av[4], bv[4][CH / 16];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        av[s] = Pw[lr * K2_QP + 4 * s + lk];
+#pragma unroll
+        for (int c = 0; c < CH / 16; ++c) bv[s][c] = Bxx[(4 * s + lk) * CH + 16 * c + lr];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < CH / 16; ++c)
+          if (c < nct) out[c] = k2_mma(av[s], bv[s][c], out[c]);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();   // the block is read before the next x rewrites it
+    }
+  }
+  // ---- store: this lane's rows (R,S) = lane & 15 of block (r,s) = w; columns y
+  {
+    const int r = w >> 2, sx = w & 3, R = lr >> 2, S = lr & 3;
+    const int64_t rowoff = R * d.sO[1] + S * d.sO[2] + r * d.sO[3] + sx * d.sO[4] + e * d.sO[5];
+#pragma unroll
+    for (int c = 0; c < CH / 16; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = 16 * c + lk + 4 * j;
+        if (c < nct && y < Y) d.O[rowoff + y * d.sO[0]] = out[c][j];
+      }
+  }
+}
+
+void launch_k2(const K2Desc* d, int nd, int nblocks, int chmax, hipStream_t s) {
+  if (nblocks <= 0) return;
+  const int grid = (nblocks + 7) / 8 * 8;   // a multiple of the XCD count: the block order is a bijection
+  if (chmax > K2_CHI) throw Error(ST_INVALID, "two-row column step: bond above the fused kernel's limit");
+  k2_kernel<K2_CHI><<<grid, K2_T, 0, s>>>(d, nd, nblocks);
+  PE_HIP(hipGetLastError());
+}
+
 }  // namespace pe

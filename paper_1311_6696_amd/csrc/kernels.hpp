@@ -63,6 +63,34 @@ void launch_kb(int prec, int out_dt, int nb1, const KbDesc* d_desc, int n_desc, 
 int kb_lds_bytes(int prec, int nb1, int lup, int pqp, int qmax);
 constexpr int KB_QC = 8;   // q values per shared-memory chunk
 
+// Fused two-row column step (one column of the two-row sandwich): with every
+// virtual leg of dimension 4 and physical dimension 2,
+//   O[y; R,S,r,s; e] = sum L[x; L,M,l,m; a] T[a; u,v; e] K1[p; l,u,r,d] B1[p; m,v,s,g]
+//                          K2[q; L,d,R,D] B2[q; M,g,S,G] Bb[x; D,G; y]
+// (names of the left-to-right step; the right-to-left step is the same
+// contraction with the horizontal roles exchanged through the strides).  One
+// workgroup per output value e runs the whole chain for every x, all
+// intermediates in LDS, accumulating over x in registers.  Site views list
+// their strides as (physical, incoming leg, up, outgoing leg, down).
+constexpr int K2_D = 4, K2_CHI = 32;   // leg dimension, largest bond
+struct K2Desc {
+  const double* L;
+  const double* T;
+  const double* B;
+  double* O;
+  const double* s[4];   // K1, B1, K2, B2
+  int64_t sL[6];        // x, L, M, l, m, a
+  int64_t sT[4];        // a, u, v, e
+  int64_t sB[4];        // x, D, G, y
+  int64_t sO[6];        // y, R, S, r, s, e
+  int64_t ss[4][5];
+  int32_t X, A, E, Y;   // bonds: x (L, Bb), a (L, T), e (T, O), y (Bb, O), each <= K2_CHI
+  int32_t block_base;   // first workgroup (output value e = 0) of this descriptor
+  int32_t pad;
+};
+// chmax: the largest bond (A or Y) of the launch's descriptors.
+void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, hipStream_t s);
+
 // Arithmetic of a contraction.
 enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 // Tile shapes (MT x NT per 256-thread workgroup).
@@ -70,14 +98,15 @@ enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 enum TcTile : int {
   TT_64x64 = 0, TT_128x32 = 1, TT_256x16 = 2, TT_32x128 = 3, TT_64x32 = 4, TT_64x16 = 5, TT_128x48 = 6, TT_64x80 = 7,
   TT_S16 = 8, TT_S32 = 9, TT_S48 = 10, TT_S64 = 11, TT_S80 = 12, TT_KB16 = 13, TT_KB32 = 14,
-  TT_COUNT = 15
+  TT_K2 = 15,   // the fused two-row column step (statistics slot only)
+  TT_COUNT = 16
 };
 inline int tile_mt(int t) {
-  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64, 128, 64, 64, 64, 64, 64, 64, 16, 16};
+  static const int v[TT_COUNT] = {64, 128, 256, 32, 64, 64, 128, 64, 64, 64, 64, 64, 64, 16, 16, 256};
   return v[t];
 }
 inline int tile_nt(int t) {
-  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16, 48, 80, 16, 32, 48, 64, 80, 16, 32};
+  static const int v[TT_COUNT] = {64, 32, 16, 128, 32, 16, 48, 80, 16, 32, 48, 64, 80, 16, 32, 64};
   return v[t];
 }
 // Statistics slot of a contraction variant.

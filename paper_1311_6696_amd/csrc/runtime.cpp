@@ -289,7 +289,7 @@ double kb_flops(const KbDesc& d) {
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -582,6 +582,31 @@ void Rec::kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic) {
   ops_.push_back(op);
 }
 
+void Rec::k2(std::vector<K2Desc> ds, double flops) {
+  if (ds.empty()) return;
+  int64_t blocks = 0;
+  double by = 0.0;
+  int chmax = 1;
+  for (auto& d : ds) {
+    chmax = std::max(chmax, std::max(d.A, d.Y));
+    PE_REQUIRE(d.X >= 1 && d.A >= 1 && d.E >= 1 && d.Y >= 1 && d.X <= K2_CHI && d.A <= K2_CHI && d.E <= K2_CHI &&
+                   d.Y <= K2_CHI,
+               "two-row column step: bond outside the fused kernel's range");
+    d.block_base = (int32_t)blocks;
+    blocks += d.E;
+    // algorithmic bytes: the incoming environment, both boundary tensors, four sites, the outgoing environment
+    by += 8.0 * ((double)d.X * 256 * d.A + (double)d.A * 16 * d.E + (double)d.X * 16 * d.Y + 4 * 512.0 +
+                 (double)d.Y * 256 * d.E);
+  }
+  PE_REQUIRE(blocks < INT_MAX / 8, "fused two-row step too large");
+  Op op{OK_K2, TP_F64, DT_F64, TT_K2, (int)ds.size(), (int)blocks, push_bytes(ds.data(), ds.size() * sizeof(K2Desc)),
+        flops};
+  op.bytes = by;
+  op.kp = chmax;
+  flops_ += flops;
+  ops_.push_back(op);
+}
+
 // Householder QR of every block of the group.  Blocks that fit a
 // register-resident variant run as one grouped launch; taller blocks with at
 // most TSQR_NMAX columns are factored as a tree (TSQR): row blocks of at most
@@ -703,7 +728,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
     void* e0 = nullptr;
-    if (timed && (op.kind == OK_TC || op.kind == OK_TCS || op.kind == OK_KB)) {
+    if (timed && (op.kind == OK_TC || op.kind == OK_TCS || op.kind == OK_KB || op.kind == OK_K2)) {
       e0 = dev::event_create();
       dev::event_record(e0, s);
     }
@@ -713,6 +738,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
       case OK_TCS:
         launch_tcs(op.prec, op.out_dt, op.tile - TT_S16 + 1, op.ksm, (const TcDesc*)d, op.nd, op.grid, op.kp, s);
         break;
+      case OK_K2: launch_k2((const K2Desc*)d, op.nd, op.grid, op.kp, s); break;
       case OK_KB:
         launch_kb(op.prec, op.out_dt, op.tile - TT_KB16 + 1, (const KbDesc*)d, op.nd, op.grid, op.ksm, op.kp, op.q, s);
         break;

@@ -107,6 +107,8 @@ class Rec {
   static bool qr_streaming(int mm, int nn) { return qr_variant_for(mm, nn) < 0 && nn > TSQR_NMAX; }
   void tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic = true);
   void kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic = true);
+  // Fused two-row column steps (float64); `flops` their algorithmic flops.
+  void k2(std::vector<K2Desc> ds, double flops);
   void qr(const std::vector<QrDesc>& ds);
   void reduce(std::vector<RedDesc> ds);
   void ew(std::vector<EwDesc> ds);
