@@ -463,11 +463,18 @@ def main():
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     tc_total_ms = float(np.sum(kms)) / max(2, args.steps // 4)
     traffic = measured_traffic(kernel)
-    # the fused ket-bra kernel applies the two layers of one row of two-row
-    # column steps, d D^8 chi^2 MACs per layer, so 8 d D^8 chi^2 flops per
-    # column step (both rows); its traffic is set against those steps' I/O
+    # Launches are set against the I/O of the two-row column steps they carry,
+    # counted in full-bond (chi) steps through the flops of one such step:
+    # the fused two-row kernel does, per (x, e) pair of bonds, the incoming
+    # environment times the top boundary (D^6 chi MACs), the four layers
+    # (d D^8 each) and the bottom boundary (D^6 chi); the fused ket-bra
+    # kernel applies the two layers of one row, 8 d D^8 chi^2 flops per step.
     D, d = cfg["D"], 2
-    steps_per_launch = per_launch_flops / (8.0 * d * D ** 8 * chi * chi)
+    if kernel.startswith("k2_kernel"):
+        step_flops = 2.0 * chi * chi * (2 * D ** 6 * chi + 4 * d * D ** 8)
+    else:
+        step_flops = 8.0 * d * D ** 8 * chi * chi
+    steps_per_launch = per_launch_flops / step_flops
     chain_io = steps_per_launch * chain2_io_bytes(cfg["L"], D, chi, d)
 
     out = {

@@ -295,7 +295,8 @@ peps_status peps_env_mps(peps_env* env, int32_t side, int32_t k, int32_t c, int3
  * strides (in-place), otherwise the outputs must not overlap any input.
  * The blk array is host memory.  All blocks run as one batched group with
  * the kernels of the boundary truncation: CholeskyQR2 for tall blocks up to
- * 512 x 32 (Householder when a block is too ill-conditioned for it),
+ * 512 x 32 (128-row slices on separate, co-resident workgroups; Householder
+ * when a block is too ill-conditioned for it),
  * register-resident Householder, TSQR or the streaming kernel otherwise. */
 typedef struct {
   const double* a;
@@ -312,15 +313,18 @@ peps_status peps_qr(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
  * call hipMalloc, e.g. inside tight serving loops or harnesses that forbid
  * it): the same factors from the same kernels, bit for bit, but every piece
  * of workspace - kernel descriptors, the streaming kernel's 2*m*n doubles per
- * block, the TSQR tree's row-block factors and the split-K partials of its
- * rebuild - lives in one fixed device array of PEPS_QR_NOALLOC_BYTES per GPU
- * (held from first use until the process ends; its address is looked up
- * when a context is created).  The call allocates no device or pinned host
- * memory and waits for its work to finish.  A request whose workspace does
- * not fit fails with PEPS_ERR_OOM before anything is launched.  Every call on
- * one GPU shares that GPU's array (the last call's data stays in it; nothing
- * in it needs to start at zero): calls that overlap on one GPU, from several
- * threads or streams, race and are not allowed. */
+ * block, the multi-workgroup CholeskyQR2's per-block Q1, partial Gram
+ * matrices and factors, the TSQR tree's row-block factors and the split-K
+ * partials of its rebuild - lives in one fixed device array of
+ * PEPS_QR_NOALLOC_BYTES per GPU (held from first use until the process ends;
+ * its address is looked up when a context is created), with the
+ * CholeskyQR2 route's arrival counters (one unsigned int per block).  The
+ * call allocates no device or pinned host memory and waits for its work to
+ * finish.  A request whose workspace does not fit fails with PEPS_ERR_OOM
+ * before anything is launched.  Every call on one GPU shares that GPU's
+ * array (the last call's data stays in it; nothing in it needs to start at
+ * zero): calls that overlap on one GPU, from several threads or streams,
+ * race and are not allowed. */
 #define PEPS_QR_NOALLOC_BYTES (32u << 20)
 peps_status peps_qr_noalloc(peps_ctx* ctx, const peps_qr_block* blk, int32_t n_blocks);
 

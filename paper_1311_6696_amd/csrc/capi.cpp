@@ -226,11 +226,11 @@ peps_status peps_ctx_create(int32_t device, void* hip_stream, peps_ctx** out) {
     PE_REQUIRE(device >= 0 && device < n, "no such HIP device");
     dev::set_device(device);
     noalloc_scratch(device);   // the fixed QR workspace's device address, once per device
-    auto* c = new peps_ctx();
+    std::unique_ptr<peps_ctx> c(new peps_ctx());
     c->c = std::make_shared<Ctx>();
     c->c->device = device;
     c->c->stream = (hipStream_t)hip_stream;
-    *out = c;
+    *out = c.release();
   });
 }
 

@@ -1272,19 +1272,24 @@ __global__ __launch_bounds__(64 * NW) void qr_reg_kernel(const QrDesc* __restric
 }
 
 // ===========================================================================
-// CholeskyQR2 for tall blocks: m <= 32*CPW rows, n <= 16*NB columns, eight
-// waves, one workgroup per block.  Pass 1: G = A^T A on MFMA (one partial
-// tile set per wave, summed in wave order), G = R1^T R1 and W1 = R1^-1 in one
-// wave, Q1 = A W1.  Pass 2 does the same for Q1 (G2 = R2^T R2, Q = Q1 W2) and
-// R = R2 R1.  When A is not too ill-conditioned the second pass makes Q
-// orthonormal to working precision and (Q, R) agree with the Householder
-// factors to the conditioning of the problem.  Otherwise the block is
-// factored by Householder in the same launch: the fallback is taken when a
-// pivot of the first Cholesky is not clearly positive relative to its
-// diagonal entry, or when an entry of Q1^T Q1 - I exceeds 1e-2.  Nothing is
-// stored before that decision, so Q may alias A.
+// CholeskyQR2 for tall blocks (m <= 512 rows, n <= 16*NB columns), spread
+// over workgroups of CQ_ROWS rows each, in three launches.  Pass 1: each
+// workgroup forms the Gram matrix of its rows on MFMA (one partial tile set
+// per wave, summed in wave order); the last workgroup of the block to arrive
+// sums the workgroups' sets in workgroup order, factors G = R1^T R1 and
+// forms W1 = R1^-1 in one wave.  Pass 2: Q1 = A W1 per workgroup (kept in
+// the workspace) and the same for Q1 (G2 = R2^T R2, W2, R = R2 R1).  Pass 3:
+// Q = Q1 W2.  The sums run in fixed orders, so the result does not depend on
+// which workgroup arrives last.  When A is not too ill-conditioned the
+// second pass makes Q orthonormal to working precision and (Q, R) agree
+// with the Householder factors to the conditioning of the problem.
+// Otherwise the third launch factors the block by Householder in one
+// workgroup: the fallback is taken when a pivot of the first Cholesky is not
+// clearly positive relative to its diagonal entry, or when an entry of
+// Q1^T Q1 - I exceeds 1e-2.  Only the third launch writes Q, so Q may alias A.
 //
-// Wave w owns rows [4*CPW*w, 4*CPW*(w+1)) and keeps two register images:
+// Wave w of a workgroup owns its rows [4*CPW*w, 4*CPW*(w+1)) and keeps two
+// register images:
 //   Gram image  g[c][b] = X[4*CPW*w + 4c + (lane>>4)][16b + (lane&15)]
 //               (operand with k over rows: X^T X),
 //   row image   x[t][s] = X[4*CPW*w + 16t + (lane&15)][4s + (lane>>4)]
@@ -1569,69 +1574,258 @@ __device__ __attribute__((always_inline)) inline void cq_store_r(const QrDesc& d
   }
 }
 
-template <int NB, int CPW>
-__host__ __device__ constexpr int cq_area() {
-  return 8 * (NB * (NB + 1) / 2) * 256 > qr_house_lds<CPW / 2, 2 * NB, 8>() ? 8 * (NB * (NB + 1) / 2) * 256
-                                                                            : qr_house_lds<CPW / 2, 2 * NB, 8>();
+// Workspace of one block (doubles): the workgroups' partial Gram tile sets,
+// R1, W1 and W2 ((NP+1)-pitched) and the two pass flags.
+__host__ __device__ inline int64_t cq_mat_off(int P, int NB) { return (int64_t)P * (NB * (NB + 1) / 2) * 256; }
+__host__ __device__ inline int64_t cq_flag_off(int P, int NB) {
+  return cq_mat_off(P, NB) + 3 * (int64_t)(16 * NB) * (16 * NB + 1);
+}
+size_t cq_ws_doubles(int m, int n) {
+  const int NB = n <= 16 ? 1 : 2, P = (m + CQ_ROWS - 1) / CQ_ROWS;
+  return (size_t)cq_flag_off(P, NB) + 2;
 }
 
-template <int NB, int CPW, bool GF>
-__device__ __attribute__((always_inline)) inline void cholqr_body(const QrDesc& d, double* sm) {
-  constexpr int NP = 16 * NB, LD = NP + 1, AREA = cq_area<NB, CPW>();
-  static_assert(CPW % 4 == 0, "whole 16-row tiles per wave");
-  static_assert(3 * NP * LD + 128 + NP <= AREA, "G, R, W and the row buffers fit the partial-tile area");
-  double* Gs = sm;                 // partial tiles, then G (pass 1 and 2)
-  double* Rs = sm + NP * LD;
-  double* Ws = sm + 2 * NP * LD;
-  double* rowb = sm + 3 * NP * LD;
-  double* R1s = sm + AREA;         // R1, kept for R = R2 R1
-  double* flag = R1s + NP * LD;
+// The block whose workgroup range holds workgroup b, and b's index in it.
+__device__ inline const CqDesc& cq_find(const CqDesc* ds, int nd, int b, int& p) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= b) lo = mid; else hi = mid - 1;
+  }
+  p = b - ds[lo].block_base;
+  return ds[lo];
+}
+
+// This workgroup's rows of a block as a block of their own.
+__device__ inline QrDesc cq_rows(const QrDesc& d, int p) {
+  QrDesc q = d;
+  q.A = d.A + (int64_t)CQ_ROWS * p * d.sAr;
+  q.Q = d.Q + (int64_t)CQ_ROWS * p * d.sQr;
+  q.m = min(CQ_ROWS, d.m - CQ_ROWS * p);
+  return q;
+}
+
+// Data that workgroups of one block exchange (partial Gram sets, factors,
+// flags) is written and read with device-scope accesses, which bypass the
+// per-XCD L2 caches' stale copies, so no cache-wide write-back or
+// invalidation is needed: a writer waits for its stores to complete before
+// the counter moves, and a reader loads after it has seen the counter move.
+__device__ inline void cq_st(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline double cq_ld(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Arrival at the block's counter: the value before this workgroup's
+// increment (its device-scope stores before the call are complete).
+__device__ inline unsigned cq_arrive(unsigned* c, int* sh) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) *sh = (int)__hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const unsigned old = (unsigned)*sh;
+  __syncthreads();
+  return old;
+}
+
+// Wait until the counter reaches `target` (the last workgroup of the pass
+// has published its factor).  Every workgroup of a launch is resident (at
+// most CQ_MAXWG of them, one per compute unit), so the wait ends; the polls
+// are bounded all the same, and a wait that runs out returns false.
+__device__ inline bool cq_wait(unsigned* c, unsigned target, int* sh) {
+  if (threadIdx.x == 0) {
+    int ok = 0;
+    for (int it = 0; it < (1 << 20); ++it) {
+      if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *sh = ok;
+  }
+  __syncthreads();
+  const bool ok = *sh != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Publication of a factor by the last workgroup: its device-scope stores
+// complete, then the counter moves.
+__device__ inline void cq_publish(unsigned* c) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A wait that ran out: this workgroup's rows of Q become NaN, which the
+// callers' finiteness checks report.
+__device__ inline void cq_poison(const QrDesc& q) {
+  for (int e = threadIdx.x; e < q.m * q.n; e += blockDim.x)
+    q.Q[(int64_t)(e / q.n) * q.sQr + (int64_t)(e % q.n) * q.sQc] = __builtin_nan("");
+}
+
+// Partial Gram tile set of one workgroup (the eight waves' sets in sm,
+// summed in wave order) to its slot of the workspace.
+template <int NB>
+__device__ inline void cq_put_part(const double* sm, double* part, int p, int tid) {
+  constexpr int NE = NB * (NB + 1) / 2 * 256;
+  for (int e = tid; e < NE; e += 512) {
+    double v = sm[e];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) v += sm[w * NE + e];
+    cq_st(&part[(int64_t)p * NE + e], v);
+  }
+}
+
+// Sum of the P <= CQ_MAXP workgroups' tile sets in workgroup order, stored
+// as the full symmetric matrix G[i*(NP+1) + j] (512 threads; all loads are
+// issued before the first add).
+template <int NB>
+__device__ inline void cq_sum_parts(const double* part, int P, double* G, int tid) {
+  constexpr int NT = NB * (NB + 1) / 2, NE = NT * 256, LD = 16 * NB + 1, PER = (NE + 511) / 512;
+  double v[PER][CQ_MAXP];
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+#pragma unroll
+    for (int w = 0; w < CQ_MAXP; ++w) {
+      const int e = tid + 512 * q;
+      v[q][w] = (w < P && e < NE) ? cq_ld(&part[(int64_t)w * NE + e]) : 0.0;
+    }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 512 * q;
+    if (e >= NE) continue;
+    double s = v[q][0];
+#pragma unroll
+    for (int w = 1; w < CQ_MAXP; ++w) s += v[q][w];   // zeros past P leave the sum unchanged
+    int t = e >> 8, bi = 0;
+    while (t >= NB - bi) {
+      t -= NB - bi;
+      ++bi;
+    }
+    const int bj = bi + t, l = e & 63, r = (e >> 6) & 3;
+    const int i = 16 * bi + (l >> 4) + 4 * r, j = 16 * bj + (l & 15);
+    G[i * LD + j] = s;
+    if (bi != bj) G[j * LD + i] = s;
+  }
+}
+
+constexpr int CQ_CPW = CQ_ROWS / 32;   // row chunks of 4 per wave (eight waves)
+static_assert(CQ_CPW % 4 == 0, "whole 16-row tiles per wave");
+
+// One launch per group of blocks, all workgroups resident.  A block's
+// counter (zero at launch) counts the P arrivals after pass 1, +1 when W1 is
+// published, the P arrivals after pass 2 and +1 when W2 is published.  After
+// a failed check the first workgroup factors the whole block by Householder
+// (A is untouched until pass 3) and the others leave.
+template <int NB>
+__global__ __launch_bounds__(512) void cq_kernel(const CqDesc* __restrict__ ds, int nd, unsigned* __restrict__ counters) {
+  constexpr int CPW = CQ_CPW, NP = 16 * NB, LD = NP + 1, NT = NB * (NB + 1) / 2;
+  constexpr int A1 = NP * LD + 8 * NT * 256, A2 = 4 * NP * LD + 128 + NP, A3 = qr_house_lds<8, 2 * NB, 8>();
+  constexpr int AREA = A1 > A2 ? (A1 > A3 ? A1 : A3) : (A2 > A3 ? A2 : A3);
+  __shared__ double sm[AREA];
+  __shared__ int sh;
+  int p;
+  const CqDesc& d = cq_find(ds, nd, blockIdx.x, p);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = d.P;
+  unsigned* cnt = counters + d.cnt;
+  double* part = d.ws;
+  double* mat = d.ws + cq_mat_off(P, NB);   // R1, W1, W2
+  double* flags = d.ws + cq_flag_off(P, NB);
+  double *Gs = sm, *Rs = sm + NP * LD, *Ws = sm + 2 * NP * LD, *rowb = sm + 3 * NP * LD;
+  double* R1s = rowb + 128 + NP;
+  double* Wb = sm;                 // W1 or W2 for the products
+  double* wpart = sm + NP * LD;    // the waves' partial tile sets
+  const QrDesc q = cq_rows(d.q, p);
   double g[CPW][NB], x[CPW / 4][4 * NB];
-  cq_load<NB, CPW, GF>(d, g, x, wave, lane);
-  // ---- pass 1
-  cq_gram<NB, CPW>(g, sm, wave, lane);
+  if ((d.q.sAc < 0 ? -d.q.sAc : d.q.sAc) <= (d.q.sAr < 0 ? -d.q.sAr : d.q.sAr))
+    cq_load<NB, CPW, true>(q, g, x, wave, lane);
+  else
+    cq_load<NB, CPW, false>(q, g, x, wave, lane);
+  // ---- pass 1: G = A^T A, R1, W1
+  cq_gram<NB, CPW>(g, wpart, wave, lane);
   __syncthreads();
-  cq_reduce<NB>(sm, tid);
-  if (wave == 0) {
-    const bool ok = cq_chol<NB>(Gs, Rs, Ws, rowb, d.n, 1e-14, 0.0, lane);
-    if (lane == 0) flag[0] = ok ? 1.0 : 0.0;
+  cq_put_part<NB>(wpart, part, p, tid);
+  if (cq_arrive(cnt, &sh) == (unsigned)(P - 1)) {
+    cq_sum_parts<NB>(part, P, Gs, tid);
+    __syncthreads();
+    if (wave == 0) {
+      const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 1e-14, 0.0, lane);
+      for (int e = lane; e < NP * LD; e += 64) {
+        cq_st(&mat[e], Rs[e]);             // R1
+        cq_st(&mat[NP * LD + e], Ws[e]);   // W1
+      }
+      if (lane == 0) cq_st(&flags[0], good ? 1.0 : 0.0);
+    }
+    cq_publish(cnt);
   }
-  __syncthreads();
-  if (flag[0] == 0.0) {
-    qr_house<CPW / 2, 2 * NB, 8>(d, sm);
+  if (!cq_wait(cnt, (unsigned)P + 1, &sh)) {
+    cq_poison(q);
     return;
   }
-  for (int e = tid; e < NP * LD; e += 512) R1s[e] = Rs[e];
-  cq_right<NB, CPW>(x, Ws, g, lane);   // Q1, Gram image
-  cq_to_rows<NB, CPW>(g, x, lane);     // Q1, row image
-  __syncthreads();                     // W1 and R1 are read before the partial tiles reuse the area
-  // ---- pass 2
-  cq_gram<NB, CPW>(g, sm, wave, lane);
-  __syncthreads();
-  cq_reduce<NB>(sm, tid);
-  if (wave == 0) {
-    const bool ok = cq_chol<NB>(Gs, Rs, Ws, rowb, d.n, 0.5, 1e-2, lane);
-    if (lane == 0) flag[0] = ok ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (flag[0] == 0.0) {
-    qr_house<CPW / 2, 2 * NB, 8>(d, sm);
+  if (cq_ld(&flags[0]) == 0.0) {
+    if (p == 0) qr_house<8, 2 * NB, 8>(d.q, sm);
     return;
   }
-  cq_store_q<NB, CPW, GF>(d, x, Ws, wave, lane);
-  if (d.R) cq_store_r<NB>(d, Rs, R1s, wave, lane);
+  // ---- pass 2: Q1 = A W1 (kept in registers), G2 = Q1^T Q1, W2, R = R2 R1
+  for (int e = tid; e < NP * LD; e += 512) Wb[e] = cq_ld(&mat[NP * LD + e]);
+  __syncthreads();
+  cq_right<NB, CPW>(x, Wb, g, lane);
+  cq_gram<NB, CPW>(g, wpart, wave, lane);
+  __syncthreads();
+  cq_put_part<NB>(wpart, part, p, tid);
+  if (cq_arrive(cnt, &sh) == 2 * (unsigned)P) {
+    cq_sum_parts<NB>(part, P, Gs, tid);
+    for (int e = tid; e < NP * LD; e += 512) R1s[e] = cq_ld(&mat[e]);
+    __syncthreads();
+    if (wave == 0) {
+      const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 0.5, 1e-2, lane);
+      for (int e = lane; e < NP * LD; e += 64) cq_st(&mat[2 * NP * LD + e], Ws[e]);   // W2
+      if (lane == 0) {
+        cq_st(&flags[1], good ? 1.0 : 0.0);
+        sh = good;
+      }
+    }
+    __syncthreads();
+    if (sh && d.q.R) cq_store_r<NB>(d.q, Rs, R1s, wave, lane);
+    cq_publish(cnt);
+  }
+  if (!cq_wait(cnt, 2 * (unsigned)P + 2, &sh)) {
+    cq_poison(q);
+    return;
+  }
+  if (cq_ld(&flags[1]) == 0.0) {
+    if (p == 0) qr_house<8, 2 * NB, 8>(d.q, sm);
+    return;
+  }
+  // ---- pass 3: Q = Q1 W2
+  for (int e = tid; e < NP * LD; e += 512) Wb[e] = cq_ld(&mat[2 * NP * LD + e]);
+  __syncthreads();
+  cq_to_rows<NB, CPW>(g, x, lane);
+  if ((d.q.sQc < 0 ? -d.q.sQc : d.q.sQc) <= (d.q.sQr < 0 ? -d.q.sQr : d.q.sQr))
+    cq_store_q<NB, CPW, true>(q, x, Wb, wave, lane);
+  else
+    cq_store_q<NB, CPW, false>(q, x, Wb, wave, lane);
 }
 
-template <int NB, int CPW>
-__global__ __launch_bounds__(512) void cholqr_kernel(const QrDesc* __restrict__ ds) {
-  __shared__ double sm[cq_area<NB, CPW>() + (16 * NB) * (16 * NB + 1) + 2];
-  const QrDesc& d = ds[blockIdx.x];
-  const int64_t ar = d.sAr < 0 ? -d.sAr : d.sAr, ac = d.sAc < 0 ? -d.sAc : d.sAc;
-  if (ac <= ar)
-    cholqr_body<NB, CPW, true>(d, sm);
-  else
-    cholqr_body<NB, CPW, false>(d, sm);
+__global__ void cq_clear_kernel(unsigned* c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0u;
+}
+
+void launch_cq_clear(unsigned* counters, int n, hipStream_t s) {
+  if (n <= 0) return;
+  cq_clear_kernel<<<(n + 255) / 256, 256, 0, s>>>(counters, n);
+  PE_HIP(hipGetLastError());
+}
+
+void launch_cq(int nb, const CqDesc* d, int nd, int nblocks, unsigned* counters, hipStream_t s) {
+  PE_REQUIRE(nb == 1 || nb == 2, "CholeskyQR2: bad column-block count");
+  PE_REQUIRE(nblocks <= CQ_MAXWG, "CholeskyQR2: too many workgroups in one launch");
+  if (nb == 1) cq_kernel<1><<<nblocks, 512, 0, s>>>(d, nd, counters);
+  else cq_kernel<2><<<nblocks, 512, 0, s>>>(d, nd, counters);
+  PE_HIP(hipGetLastError());
 }
 
 // Register-resident variants: (rows per lane, columns per wave, waves).
@@ -1647,19 +1841,8 @@ constexpr QrVariant QR_VARIANTS[] = {{1, 2, 4},  {1, 4, 4},  {1, 1, 16}, {2, 1, 
                                      {8, 2, 16}, {4, 4, 16}, {4, 5, 16}};
 constexpr int QR_NVAR = sizeof(QR_VARIANTS) / sizeof(QR_VARIANTS[0]);
 
-// CholeskyQR2 variants, numbered after the Householder ones: (column blocks
-// of 16, row chunks of 4 per wave).  Used for tall blocks (m >= 4n, m >= 128)
-// of at most 512 rows and 32 columns.
-struct CqVariant {
-  int nb, cpw;
-};
-constexpr CqVariant CQ_VARIANTS[] = {{1, 8}, {1, 16}, {2, 8}, {2, 16}};
-constexpr int CQ_NVAR = sizeof(CQ_VARIANTS) / sizeof(CQ_VARIANTS[0]);
-
 int qr_variant_for(int m, int n) {
-  if (m >= 128 && m >= 4 * n && m <= 512 && n <= 32)
-    for (int v = 0; v < CQ_NVAR; ++v)
-      if (16 * CQ_VARIANTS[v].nb >= n && 32 * CQ_VARIANTS[v].cpw >= m) return QR_NVAR + v;
+  if (m >= 128 && m >= 4 * n && m <= 512 && n <= 32) return QR_CQ;
   int best = -1, cost = 1 << 30;
   for (int v = 0; v < QR_NVAR; ++v) {
     const QrVariant& q = QR_VARIANTS[v];
@@ -1686,10 +1869,6 @@ void launch_qr_reg(int variant, const QrDesc* d, int nd, hipStream_t s) {
     case 9: qr_reg_kernel<8, 2, 16><<<nd, 1024, 0, s>>>(d); break;
     case 10: qr_reg_kernel<4, 4, 16><<<nd, 1024, 0, s>>>(d); break;
     case 11: qr_reg_kernel<4, 5, 16><<<nd, 1024, 0, s>>>(d); break;
-    case QR_NVAR + 0: cholqr_kernel<1, 8><<<nd, 512, 0, s>>>(d); break;
-    case QR_NVAR + 1: cholqr_kernel<1, 16><<<nd, 512, 0, s>>>(d); break;
-    case QR_NVAR + 2: cholqr_kernel<2, 8><<<nd, 512, 0, s>>>(d); break;
-    case QR_NVAR + 3: cholqr_kernel<2, 16><<<nd, 512, 0, s>>>(d); break;
     default: throw Error(ST_INVALID, "bad QR variant");
   }
   PE_HIP(hipGetLastError());

@@ -144,9 +144,32 @@ struct QrDesc {
   int32_t m, n;
 };
 void launch_qr(const QrDesc* d_desc, int n_desc, hipStream_t s);
-// Register-resident variant for blocks up to m x n (-1 when none fits) and its launch.
+// Route for blocks up to m x n: a register-resident variant (>= 0), QR_CQ
+// (CholeskyQR2 over several workgroups) or -1 (none fits), and the launch of
+// a register-resident variant.
+constexpr int QR_CQ = 1000;
 int qr_variant_for(int m, int n);
 void launch_qr_reg(int variant, const QrDesc* d_desc, int n_desc, hipStream_t s);
+
+// CholeskyQR2 of a tall block (m <= 512, n <= 32) over ceil(m / CQ_ROWS)
+// workgroups that wait for each other's factors: one launch, all of whose
+// workgroups (at most CQ_MAXWG) must be resident at once.
+constexpr int CQ_ROWS = 128;
+constexpr int CQ_MAXP = 4;       // workgroups per block (m <= CQ_ROWS * CQ_MAXP)
+constexpr int CQ_MAXWG = 256;    // workgroups per launch: one per compute unit
+struct CqDesc {
+  QrDesc q;             // the block (q.W unused)
+  double* ws;           // cq_ws_doubles(m, n) doubles, private to this block during the launch
+  int32_t cnt;          // its arrival counter: an index into the launch's counters, zero at launch
+  int32_t P;            // workgroups of the block
+  int32_t block_base;   // its first workgroup in the launch
+  int32_t pad;
+};
+size_t cq_ws_doubles(int m, int n);
+// nb: 16-column blocks of the widest block (1 or 2); n_blocks: workgroups.
+void launch_cq(int nb, const CqDesc* d_desc, int n_desc, int n_blocks, unsigned* counters, hipStream_t s);
+// Zero n counters (a kernel, so that it can sit in a captured graph).
+void launch_cq_clear(unsigned* counters, int n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Deterministic sums: out = sum_i x_i * y_i (y null -> sum x_i^2), in two

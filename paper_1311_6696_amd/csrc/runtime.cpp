@@ -63,6 +63,7 @@ void Ctx::clear_graphs() {
       dev::graph_destroy(g.exec);
       pool.release(g.dblob);
       pool.release(g.partials);
+      pool.release(g.counters);
     }
   graph_cache.clear();
   graph_count = 0;
@@ -289,7 +290,7 @@ double kb_flops(const KbDesc& d) {
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8, OK_CQ = 9 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -624,6 +625,11 @@ void Rec::qr(const std::vector<QrDesc>& ds) {
     nn = std::max(nn, d.n);
   }
   const int variant = qr_variant_for(mm, nn);
+  if (variant == QR_CQ) {
+    if (qr_depth_ == 0) qr_used_ = 0;   // earlier QR ops are ordered before this one on the stream
+    qr_cq(ds, nn <= 16 ? 1 : 2);
+    return;
+  }
   if (variant < 0 && nn <= TSQR_NMAX) {
     if (qr_depth_ == 0) qr_used_ = 0;   // earlier QR ops are ordered before this one on the stream
     ++qr_depth_;
@@ -633,6 +639,32 @@ void Rec::qr(const std::vector<QrDesc>& ds) {
   }
   ops_.push_back(Op{OK_QR, 0, 0, variant, (int)ds.size(), (int)ds.size(),
                     push_bytes(ds.data(), ds.size() * sizeof(QrDesc)), 0.0});
+}
+
+// CholeskyQR2 over several workgroups per block: each block gets its own
+// workspace region and arrival counter; a launch holds at most CQ_MAXWG
+// workgroups, so that all of them are resident together.
+void Rec::qr_cq(const std::vector<QrDesc>& ds, int nb) {
+  size_t i = 0;
+  while (i < ds.size()) {
+    std::vector<CqDesc> cs;
+    int blocks = 0;
+    for (; i < ds.size(); ++i) {
+      const int P = (ds[i].m + CQ_ROWS - 1) / CQ_ROWS;
+      PE_REQUIRE(P <= CQ_MAXP, "CholeskyQR2 block too tall");
+      if (blocks + P > CQ_MAXWG) break;
+      CqDesc c{};
+      c.q = ds[i];
+      c.q.W = nullptr;
+      c.ws = qr_scratch(cq_ws_doubles(ds[i].m, 16 * nb));   // offsets follow the launch's column blocks
+      c.cnt = cq_slots_++;
+      c.P = P;
+      c.block_base = blocks;
+      blocks += P;
+      cs.push_back(c);
+    }
+    ops_.push_back(Op{OK_CQ, 0, 0, nb, (int)cs.size(), blocks, push_bytes(cs.data(), cs.size() * sizeof(CqDesc)), 0.0});
+  }
 }
 
 double* Rec::qr_scratch(size_t n) {
@@ -722,8 +754,9 @@ void* Rec::aux(Arena& arena, const void* data, size_t bytes) {
   return d;
 }
 
-void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t s) {
+void Rec::issue(const uint8_t* dblob, double* partials, unsigned* counters, bool timed, hipStream_t s) {
   for (auto& a : aux_) dev::d2d(a.first, dblob + a.second.first, a.second.second, s);
+  launch_cq_clear(counters, cq_slots_, s);
   for (size_t i = 0; i < ops_.size(); ++i) {
     const Op& op = ops_[i];
     const void* d = dblob + op.off;
@@ -746,6 +779,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t 
         if (op.tile >= 0) launch_qr_reg(op.tile, (const QrDesc*)d, op.nd, s);
         else launch_qr((const QrDesc*)d, op.nd, s);
         break;
+      case OK_CQ: launch_cq(op.tile, (const CqDesc*)d, op.nd, op.grid, counters, s); break;
       case OK_RED: launch_reduce((const RedDesc*)d, op.nd, op.grid, partials, s); break;
       case OK_EW: launch_ew((const EwDesc*)d, op.nd, op.grid, s); break;
       case OK_SEP: launch_sep((const SepDesc*)d, op.nd, op.kp, s); break;
@@ -764,8 +798,9 @@ void Rec::flush(Arena& arena) {
     hipStream_t s = ctx_->stream;
     uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
     double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+    unsigned* counters = (unsigned*)arena.alloc(sizeof(unsigned) * (size_t)std::max(cq_slots_, 1));
     dev::h2d(dblob, blob_.data(), blob_.size(), s);
-    issue(dblob, partials, false, s);
+    issue(dblob, partials, counters, false, s);
     dev::sync(s);   // the host copy of the descriptors is reused by the next recording
   } else if (ctx_->graphs && !ctx_->profile && !ctx_->tuning) {
     flush_graph();
@@ -773,16 +808,18 @@ void Rec::flush(Arena& arena) {
     hipStream_t s = ctx_->stream;
     uint8_t* dblob = (uint8_t*)arena.alloc(blob_.size());
     double* partials = (double*)arena.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+    unsigned* counters = (unsigned*)arena.alloc(sizeof(unsigned) * (size_t)std::max(cq_slots_, 1));
     void* host = ctx_->pinned_get(blob_.size());
     pinned_.push_back({host, blob_.size()});
     std::memcpy(host, blob_.data(), blob_.size());
     dev::h2d(dblob, host, blob_.size(), s);
-    issue(dblob, partials, ctx_->profile, s);
+    issue(dblob, partials, counters, ctx_->profile, s);
   }
   ops_.clear();
   blob_.clear();
   aux_.clear();
   partials_ = 0;
+  cq_slots_ = 0;
 }
 
 // Graph replay: the launch sequence is identified by everything its kernels
@@ -806,6 +843,7 @@ void Rec::flush_graph() {
     put(&a.second, sizeof(a.second));
   }
   put(&partials_, sizeof(partials_));
+  put(&cq_slots_, sizeof(cq_slots_));
   uint64_t h = 1469598103934665603ull;   // FNV-1a
   for (uint8_t c : key) h = (h ^ c) * 1099511628211ull;
   auto& bucket = ctx_->graph_cache[h];
@@ -821,6 +859,7 @@ void Rec::flush_graph() {
   Ctx::Graph g;
   g.dblob = (uint8_t*)ctx_->pool.alloc(blob_.size());
   g.partials = (double*)ctx_->pool.alloc(sizeof(double) * (size_t)std::max(partials_, 1));
+  g.counters = (unsigned*)ctx_->pool.alloc(sizeof(unsigned) * (size_t)std::max(cq_slots_, 1));
   void* host = ctx_->pinned_get(blob_.size());
   pinned_.push_back({host, blob_.size()});
   std::memcpy(host, blob_.data(), blob_.size());
@@ -831,12 +870,13 @@ void Rec::flush_graph() {
   hipStream_t cs = ctx_->capture_stream;
   dev::capture_begin(cs);
   try {
-    issue(g.dblob, g.partials, false, cs);
+    issue(g.dblob, g.partials, g.counters, false, cs);
     g.exec = dev::capture_end(cs);
   } catch (...) {
     dev::capture_abort(cs);
     ctx_->pool.release(g.dblob);
     ctx_->pool.release(g.partials);
+    ctx_->pool.release(g.counters);
     throw;
   }
   dev::graph_launch(g.exec, s);

@@ -133,13 +133,14 @@ class Rec {
     double bytes = 0.0;    // algorithmic bytes: operands read once, output written once
   };
   size_t push_bytes(const void* p, size_t n);
-  void issue(const uint8_t* dblob, double* partials, bool timed, hipStream_t s);
+  void issue(const uint8_t* dblob, double* partials, unsigned* counters, bool timed, hipStream_t s);
   void flush_graph();
   void tc_launch(int prec, int out_dt, int tile, std::vector<TcDesc> ds, bool algorithmic, bool allow_split);
   void apply_choice(int prec, int out_dt, int fam, int choice, std::vector<TcDesc> ds, bool algorithmic);
   int tune(int prec, int out_dt, int fam, bool skinny, const std::vector<TcDesc>& ds, uint64_t key);
   bool tcs_launch(int prec, int out_dt, std::vector<TcDesc>& ds, bool algorithmic);
   void qr_tall(const std::vector<QrDesc>& ds);
+  void qr_cq(const std::vector<QrDesc>& ds, int nb);
   double* qr_scratch(size_t n);
   static constexpr int TSQR_LEAF = 256, TSQR_NMAX = 80;   // leaf rows, widest tree-factored block
   double* qr_buf_ = nullptr;   // TSQR workspace (scratch), reused by every QR op of this recorder
@@ -152,6 +153,7 @@ class Rec {
   std::vector<uint8_t> blob_;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
   int partials_ = 0;
+  int cq_slots_ = 0;             // CholeskyQR2 arrival counters of this recording (zeroed at issue)
   double* part_buf_ = nullptr;   // split-K partial tiles (scratch)
   size_t part_cap_ = 0;
   double flops_ = 0.0;
@@ -186,6 +188,7 @@ struct Ctx {
     void* exec = nullptr;
     uint8_t* dblob = nullptr;
     double* partials = nullptr;
+    unsigned* counters = nullptr;
   };
   static constexpr int GRAPH_MAX = 512;
   std::unordered_map<uint64_t, std::vector<Graph>> graph_cache;
