@@ -2444,32 +2444,32 @@ __device__ inline d4_t k2_row(const double* In, const double* Ks, const double* 
 
 }  // namespace
 
-template <int CH>   // largest bond of the launch (sizes registers and LDS)
-__global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds, int nd, int nblocks) {
-  __shared__ double Te[CH * 16];
-  __shared__ double K1s[16 * 32], B1s[32 * 16], K2s[16 * 32], B2s[32 * 16];
+// Shared memory of one workgroup (CH: the launch's largest bond).
+template <int CH>
+struct K2Smem {
+  double Te[CH * 16];
+  double K1s[16 * 32], B1s[32 * 16], K2s[16 * 32], B2s[32 * 16];
   // shared, double-buffered by the parity of x: the bottom boundary slab and
   // row 1's output [(r,s)][(M,g)][(L,d)] (swizzled [16][16] blocks)
-  __shared__ double Bx[2][16 * CH];
-  __shared__ double Y2[2][16 * 256];
-  __shared__ double Priv[K2_W * K2_PRIV];    // per wave: its block or its ket rows
+  double Bx[2][16 * CH];
+  double Y2[2][16 * 256];
+  double Priv[K2_W * K2_PRIV];   // per wave: its block or its ket rows
+};
+
+// One workgroup's column step (output value e of descriptor d).  FULL: the
+// descriptor's bonds a and y equal CH, so no partial tile is masked.
+template <int CH, bool FULL>
+__device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, const int e, K2Smem<CH>& S) {
+  double* Te = S.Te;
+  double *K1s = S.K1s, *B1s = S.B1s, *K2s = S.K2s, *B2s = S.B2s;
+  double(*Bx)[16 * CH] = S.Bx;
+  double(*Y2)[16 * 256] = S.Y2;
+  double* Priv = S.Priv;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   double* Pw = Priv + w * K2_PRIV;
-  // XCD-aware order: consecutive virtual blocks (the e values of one
-  // descriptor) go to one XCD, so they share the incoming environment in L2
-  const int grid = gridDim.x, per = grid / 8;
-  const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (v >= nblocks) return;
-  int lo = 0, hi = nd - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
-  }
-  const K2Desc& d = ds[lo];
-  const int e = v - d.block_base;
-  const int X = d.X, A = d.A, Y = d.Y;
-  const int A4 = (A + 3) & ~3;
+  const int X = d.X, A = FULL ? CH : d.A, Y = FULL ? CH : d.Y;
+  const int A4 = FULL ? CH : (A + 3) & ~3;
   // ---- stage the site tensors and the top boundary column of this e
   for (int i = tid; i < 512; i += K2_T) {
     {   // K1s[(l,u)][(d,r,p)]
@@ -2497,7 +2497,7 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
     const int a = i >> 4, uv = i & 15;
     Te[i] = a < A ? d.T[a * d.sT[0] + (uv >> 2) * d.sT[1] + (uv & 3) * d.sT[2] + e * d.sT[3]] : 0.0;
   }
-  const int nct = (Y + 15) >> 4;   // column tiles of the output
+  const int nct = FULL ? CH / 16 : (Y + 15) >> 4;   // column tiles of the output
   d4_t out[CH / 16];
 #pragma unroll
   for (int c = 0; c < CH / 16; ++c) out[c] = k2_zero();
@@ -2506,30 +2506,41 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
   // x is computed (each after its x values have gone to LDS).  Loads are
   // unconditional (indices clamped, values masked) so that they issue back
   // to back.
-  const int64_t ro = (w >> 2) * d.sL[1] + (w & 3) * d.sL[2] + (lr >> 2) * d.sL[3] + (lr & 3) * d.sL[4];   // (L,M,l,m)
+  // Per-lane element offsets (32-bit: a descriptor's tensors are far below
+  // 2^31 elements), fixed over x; each x only moves the uniform base.
+  const int ro = (int)((w >> 2) * d.sL[1] + (w & 3) * d.sL[2] + (lr >> 2) * d.sL[3] + (lr & 3) * d.sL[4]);   // (L,M,l,m)
+  const int sa = (int)d.sL[5];
   constexpr int KMAX = CH / 4;
   constexpr int NBX = (16 * CH + K2_T - 1) / K2_T;
+  int boff[NBX];
+#pragma unroll
+  for (int j = 0; j < NBX; ++j) {
+    const int i = tid + K2_T * j, k = i / CH, y = i % CH, yc = y < Y ? y : Y - 1;
+    boff[j] = (int)((k >> 2) * d.sB[1] + (k & 3) * d.sB[2] + yc * d.sB[3]);
+  }
   double lxf[KMAX];
   double bxf[NBX];
   auto load_l = [&](int x) {
     const double* Lx = d.L + x * d.sL[0];
 #pragma unroll
     for (int ks = 0; ks < KMAX; ++ks) {
-      if (4 * ks < A4) {
+      if (FULL) {
+        lxf[ks] = Lx[ro + (4 * ks + lk) * sa];
+      } else if (4 * ks < A4) {
         const int a = 4 * ks + lk, ac = a < A ? a : A - 1;
-        const double val = Lx[ro + ac * d.sL[5]];
+        const double val = Lx[ro + ac * sa];
         lxf[ks] = a < A ? val : 0.0;
       }
     }
   };
   auto load_b = [&](int x) {
+    const double* Bx0 = d.B + x * d.sB[0];
 #pragma unroll
     for (int j = 0; j < NBX; ++j) {
       const int i = tid + K2_T * j;
       if (i < 16 * CH) {
-        const int k = i / CH, y = i % CH, yc = y < Y ? y : Y - 1;
-        const double val = d.B[x * d.sB[0] + (k >> 2) * d.sB[1] + (k & 3) * d.sB[2] + yc * d.sB[3]];
-        bxf[j] = y < Y ? val : 0.0;
+        const double val = Bx0[boff[j]];
+        bxf[j] = (FULL || i % CH < Y) ? val : 0.0;
       }
     }
   };
@@ -2617,6 +2628,28 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
         if (c < nct && y < Y) d.O[rowoff + y * d.sO[0]] = out[c][j];
       }
   }
+}
+
+
+template <int CH>
+__global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds, int nd, int nblocks) {
+  __shared__ K2Smem<CH> S;
+  // XCD-aware order: consecutive virtual blocks (the e values of one
+  // descriptor) go to one XCD, so they share the incoming environment in L2
+  const int grid = gridDim.x, per = grid / 8;
+  const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (v >= nblocks) return;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
+  }
+  const K2Desc& d = ds[lo];
+  const int e = v - d.block_base;
+  if (d.A == CH && d.Y == CH)
+    k2_body<CH, true>(d, e, S);
+  else
+    k2_body<CH, false>(d, e, S);
 }
 
 void launch_k2(const K2Desc* d, int nd, int nblocks, int chmax, hipStream_t s) {

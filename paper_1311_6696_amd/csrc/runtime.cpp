@@ -276,7 +276,7 @@ KbDesc kb_build(const TV& Y, const TV& X, const TV& K, const TV& B) {
 // R (ALS site steps) its per-block serial phases cost more latency than the
 // two separate launches.
 bool kb_fits(const KbDesc& d, int prec) {
-  if (prec == TP_BF16 || d.r.size < 4096) return false;
+  if (prec == TP_BF16 || d.r.size < 1024) return false;
   if (d.r.n < 1 || d.r.s0[d.r.n - 1] != 1 || d.r.s1[d.r.n - 1] != 1) return false;
   if (d.dr.size * d.p.size > 32 || d.p.size > 2 || d.gs.size > 16 || d.dr.size > 16 || d.lu.size > 64) return false;
   const int nb1 = d.dr.size * d.p.size > 16 ? 2 : 1;
