@@ -47,9 +47,11 @@ inline double tc_flops(const TcDesc& d) { return 2.0 * d.M * (double)d.N * d.K; 
 struct St {
   std::vector<std::vector<TcDesc>> s;
   std::vector<std::vector<KbDesc>> k;
+  std::vector<std::vector<KcDesc>> c;
+  std::vector<double> cflops;
   double flops = 0.0;
   int prec = TP_F64;
-  St(int n, int prec_) : s(n), k(n), prec(prec_) {}
+  St(int n, int prec_) : s(n), k(n), c(n), cflops(n, 0.0), prec(prec_) {}
   void add(int stage, const TcDesc& d) {
     s[stage].push_back(d);
     flops += tc_flops(d);
@@ -66,8 +68,45 @@ struct St {
     add_kb(stage, d);
     return true;
   }
+  // The one-row chain of a site in one launch when the fused kernel takes it
+  // (float64, D = 4, d = 2, a <= K2_CHI; returns true); `right`: the
+  // right-to-left chain, whose horizontal legs swap roles.
+  bool add_chain(int stage, const TV& out, const TV& E, const TV& T, const TV& Ak, const TV& Ab, int dt, bool right) {
+    if (prec != TP_F64 || dt != DT_F64) return false;
+    const std::vector<int64_t> site{2, 4, 4, 4, 4};
+    if (Ak.dim != site || Ab.dim != site || E.dim[1] != 4 || E.dim[2] != 4 || T.dim[1] != 4 || T.dim[2] != 4) return false;
+    const int64_t A = E.dim[3], Ne = right ? T.dim[0] : T.dim[3];
+    if (A > K2_CHI || A != (right ? T.dim[3] : T.dim[0])) return false;
+    KcDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.E = (const double*)E.p;
+    d.T = (const double*)T.p;
+    d.s[0] = (const double*)Ak.p;
+    d.s[1] = (const double*)Ab.p;
+    d.Y = (double*)const_cast<void*>(out.p);
+    const int h[4] = {3, 1, 2, 0}, hs[5] = {0, 3, 2, 1, 4};
+    for (int i = 0; i < 4; ++i) {
+      d.sE[i] = E.str[i];
+      d.sT[i] = right ? T.str[h[i]] : T.str[i];
+    }
+    for (int i = 0; i < 5; ++i) {
+      d.ss[0][i] = right ? Ak.str[hs[i]] : Ak.str[i];
+      d.ss[1][i] = right ? Ab.str[hs[i]] : Ab.str[i];
+    }
+    for (int i = 0; i < 6; ++i) d.sY[i] = out.str[i];
+    d.X = (int32_t)E.dim[0];
+    d.A = (int32_t)A;
+    d.Ne = (int32_t)Ne;
+    c[stage].push_back(d);
+    // algorithmic flops: the boundary product and the ket and bra layers
+    const double f = (double)d.X * d.Ne * (2.0 * 256 * A + 32768.0);
+    cflops[stage] += f;
+    flops += f;
+    return true;
+  }
   void record(Rec& rec, int prec_, int cdt) {
     for (size_t i = 0; i < s.size(); ++i) {
+      rec.kc(c[i], cflops[i]);
       rec.tc(prec_, cdt, s[i]);
       rec.kb(prec_, cdt, k[i]);
     }
@@ -78,9 +117,10 @@ struct St {
 inline TV chain_left(St& st, const TV& E, const TV& T, const TV& Ak, const TV& Ab, void* P, void* Q, int dt) {
   const int64_t X = E.dim[0], Dl = E.dim[1], Du = T.dim[1], Ee = T.dim[3];
   const int64_t p = Ak.dim[0], Dr = Ak.dim[3], Dd = Ak.dim[4];
+  TV f = dense(Q, dt, "xdgrse", {X, Dd, Dd, Dr, Dr, Ee});   // fused: ket and bra in one launch, into Q
+  if (st.add_chain(0, f, E, T, Ak, Ab, dt, false)) return f;   // the whole chain in one launch
   TV y1 = dense(P, dt, "xlmuve", {X, Dl, Dl, Du, Du, Ee});
   st.add(0, tc_build(y1, E, T));
-  TV f = dense(Q, dt, "xdgrse", {X, Dd, Dd, Dr, Dr, Ee});   // fused: ket and bra in one launch, into Q
   if (st.add_fused(1, f, y1, Ak, Ab)) return f;
   TV z = dense(Q, dt, "xdrpmve", {X, Dd, Dr, p, Dl, Du, Ee});
   st.add(1, tc_build(z, y1, Ak));
@@ -93,9 +133,10 @@ inline TV chain_left(St& st, const TV& E, const TV& T, const TV& Ak, const TV& A
 inline TV chain_right(St& st, const TV& F, const TV& T, const TV& Ak, const TV& Ab, void* P, void* Q, int dt) {
   const int64_t Y = F.dim[0], Dr = F.dim[1], Du = T.dim[1], Aa = T.dim[0];
   const int64_t p = Ak.dim[0], Dl = Ak.dim[1], Dd = Ak.dim[4];
+  TV f = dense(Q, dt, "ydglma", {Y, Dd, Dd, Dl, Dl, Aa});
+  if (st.add_chain(0, f, F, T, Ak, Ab, dt, true)) return f;   // the whole chain in one launch
   TV y1 = dense(P, dt, "yrsuva", {Y, Dr, Dr, Du, Du, Aa});
   st.add(0, tc_build(y1, F, T));
-  TV f = dense(Q, dt, "ydglma", {Y, Dd, Dd, Dl, Dl, Aa});
   if (st.add_fused(1, f, y1, Ak, Ab)) return f;
   TV z = dense(Q, dt, "ydlpsva", {Y, Dd, Dl, p, Dr, Du, Aa});
   st.add(1, tc_build(z, y1, Ak));

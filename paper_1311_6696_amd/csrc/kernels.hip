@@ -2652,6 +2652,97 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
     k2_body<CH, false>(d, e, S);
 }
 
+// One-row chain step: wave w of a workgroup takes x = 16 * xt + w for the
+// workgroup's (xt, e); the top boundary slab of e and both sites are staged
+// in LDS once per workgroup, the wave's row of E is read from global memory
+// (shared by the Ne workgroups of one xt, which run on one XCD).
+__global__ __launch_bounds__(K2_T) void kc_kernel(const KcDesc* __restrict__ ds, int nd, int nblocks) {
+  __shared__ double Te[K2_CHI * 16];
+  __shared__ double Ks[16 * 32], Bs[32 * 16];
+  __shared__ double Priv[K2_W * K2_PRIV];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  double* Pw = Priv + w * K2_PRIV;
+  const int grid = gridDim.x, per = grid / 8;
+  const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (v >= nblocks) return;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
+  }
+  const KcDesc& d = ds[lo];
+  const int local = v - d.block_base, xt = local / d.Ne, e = local - xt * d.Ne;
+  const int A = d.A, A4 = (A + 3) & ~3;
+  for (int i = tid; i < 512; i += K2_T) {
+    {   // Ks[(l,u)][(d,r,p)]
+      const int k = i >> 5, n = i & 31, l = k >> 2, u = k & 3, dd = n >> 3, r = (n >> 1) & 3, p = n & 1;
+      const int64_t* t = d.ss[0];
+      Ks[i] = d.s[0][p * t[0] + l * t[1] + u * t[2] + r * t[3] + dd * t[4]];
+    }
+    {   // Bs[(p,(m,v))][(g,s)]
+      const int row = i >> 4, col = i & 15, p = row >> 4, m = (row >> 2) & 3, vv = row & 3, g = col >> 2, sx = col & 3;
+      const int64_t* t = d.ss[1];
+      Bs[i] = d.s[1][p * t[0] + m * t[1] + vv * t[2] + sx * t[3] + g * t[4]];
+    }
+  }
+  for (int i = tid; i < A4 * 16; i += K2_T) {
+    const int a = i >> 4, uv = i & 15;
+    Te[i] = a < A ? d.T[a * d.sT[0] + (uv >> 2) * d.sT[1] + (uv & 3) * d.sT[2] + e * d.sT[3]] : 0.0;
+  }
+  // this wave's x (clamped for the loads; waves past X store nothing) and
+  // its lane's row (l, m) = lr of E, a = 4 ks + lk
+  const int x = 16 * xt + w;
+  const bool act = x < d.X;
+  const double* Ex = d.E + (act ? x : d.X - 1) * d.sE[0] + (lr >> 2) * d.sE[1] + (lr & 3) * d.sE[2];
+  constexpr int KMAX = K2_CHI / 4;
+  double lxf[KMAX];
+#pragma unroll
+  for (int ks = 0; ks < KMAX; ++ks) {
+    if (4 * ks < A4) {
+      const int a = 4 * ks + lk, ac = a < A ? a : A - 1;
+      const double val = Ex[ac * d.sE[3]];
+      lxf[ks] = a < A ? val : 0.0;
+    }
+  }
+  __syncthreads();
+  // y1[(l,m)][(u,v)] = sum_a E[x,l,m,a] T[a,u,v,e] into the block [q=(m,v)][k=(l,u)]
+  {
+    d4_t acc = k2_zero(), acc2 = k2_zero();
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ks += 2) {
+      if (4 * ks < A4) acc = k2_mma(lxf[ks], Te[(4 * ks + lk) * 16 + lr], acc);
+      if (4 * ks + 4 < A4) acc2 = k2_mma(lxf[ks + 1], Te[(4 * ks + 4 + lk) * 16 + lr], acc2);
+    }
+    acc += acc2;
+    const int l = lr >> 2, m = lr & 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int uv = lk + 4 * j, u = uv >> 2, vv = uv & 3;
+      Pw[(m * 4 + vv) * K2_QP + l * 4 + u] = acc[j];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const d4_t y2 = k2_row<false>(Pw, Ks, Bs, Pw, lr, lk);   // [(d,r)][(g,s)]
+  if (act) {
+    const int dd = lr >> 2, r = lr & 3;
+    const int64_t base = x * d.sY[0] + dd * d.sY[1] + r * d.sY[3] + e * d.sY[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gs = lk + 4 * j, g = gs >> 2, sx = gs & 3;
+      d.Y[base + g * d.sY[2] + sx * d.sY[4]] = y2[j];
+    }
+  }
+}
+
+void launch_kc(const KcDesc* d, int nd, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  const int grid = (nblocks + 7) / 8 * 8;   // a multiple of the XCD count: the block order is a bijection
+  kc_kernel<<<grid, K2_T, 0, s>>>(d, nd, nblocks);
+  PE_HIP(hipGetLastError());
+}
+
 void launch_k2(const K2Desc* d, int nd, int nblocks, int chmax, hipStream_t s) {
   if (nblocks <= 0) return;
   const int grid = (nblocks + 7) / 8 * 8;   // a multiple of the XCD count: the block order is a bijection

@@ -91,6 +91,26 @@ struct K2Desc {
 // chmax: the largest bond (A or Y) of the launch's descriptors.
 void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, hipStream_t s);
 
+// One-row chain step (D = 4, d = 2, float64), the ALS site step's and the
+// one-row sandwich's first three contractions in one launch:
+//   Y[x][d][g][r][s][e] = sum E[x][l][m][a] T[a][u][v][e] K[p][l][u][r][d] B[p][m][v][s][g]
+// (a right-to-left step is the same with the roles of its horizontal legs
+// exchanged through the strides).  One wave per (x, e), sixteen x per
+// workgroup.
+struct KcDesc {
+  const double* E;
+  const double* T;
+  const double* s[2];   // ket K, bra B
+  double* Y;
+  int64_t sE[4];        // x, l, m, a
+  int64_t sT[4];        // a, u, v, e
+  int64_t ss[2][5];     // p, l, u, r, d  (bra: p, m, v, s, g)
+  int64_t sY[6];        // x, d, g, r, s, e
+  int32_t X, A, Ne;     // bonds x, a (<= K2_CHI) and e
+  int32_t block_base;   // first workgroup of this descriptor: ceil(X / 16) * Ne of them, e fastest
+};
+void launch_kc(const KcDesc* d_desc, int n_desc, int n_blocks, hipStream_t s);
+
 // Arithmetic of a contraction.
 enum TcPrec : int { TP_F64 = 0, TP_F32 = 1, TP_BF16 = 2 };
 // Tile shapes (MT x NT per 256-thread workgroup).

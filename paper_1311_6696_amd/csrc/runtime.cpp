@@ -290,7 +290,7 @@ double kb_flops(const KbDesc& d) {
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8, OK_CQ = 9 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8, OK_CQ = 9, OK_KC = 10 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -608,6 +608,20 @@ void Rec::k2(std::vector<K2Desc> ds, double flops) {
   ops_.push_back(op);
 }
 
+void Rec::kc(std::vector<KcDesc> ds, double flops) {
+  if (ds.empty()) return;
+  int64_t blocks = 0;
+  for (auto& d : ds) {
+    PE_REQUIRE(d.X >= 1 && d.A >= 1 && d.Ne >= 1 && d.A <= K2_CHI, "one-row chain step: bond outside the fused kernel's range");
+    d.block_base = (int32_t)blocks;
+    blocks += (int64_t)((d.X + 15) / 16) * d.Ne;
+  }
+  PE_REQUIRE(blocks < INT_MAX / 8, "one-row chain step too large");
+  flops_ += flops;
+  ops_.push_back(Op{OK_KC, TP_F64, DT_F64, 0, (int)ds.size(), (int)blocks, push_bytes(ds.data(), ds.size() * sizeof(KcDesc)),
+                    flops});
+}
+
 // Householder QR of every block of the group.  Blocks that fit a
 // register-resident variant run as one grouped launch; taller blocks with at
 // most TSQR_NMAX columns are factored as a tree (TSQR): row blocks of at most
@@ -772,6 +786,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, unsigned* counters, bool
         launch_tcs(op.prec, op.out_dt, op.tile - TT_S16 + 1, op.ksm, (const TcDesc*)d, op.nd, op.grid, op.kp, s);
         break;
       case OK_K2: launch_k2((const K2Desc*)d, op.nd, op.grid, op.kp, s); break;
+      case OK_KC: launch_kc((const KcDesc*)d, op.nd, op.grid, s); break;
       case OK_KB:
         launch_kb(op.prec, op.out_dt, op.tile - TT_KB16 + 1, (const KbDesc*)d, op.nd, op.grid, op.ksm, op.kp, op.q, s);
         break;

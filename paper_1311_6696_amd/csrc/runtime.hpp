@@ -109,6 +109,8 @@ class Rec {
   void kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic = true);
   // Fused two-row column steps (float64); `flops` their algorithmic flops.
   void k2(std::vector<K2Desc> ds, double flops);
+  // Fused one-row chain steps (float64); `flops` their algorithmic flops.
+  void kc(std::vector<KcDesc> ds, double flops);
   void qr(const std::vector<QrDesc>& ds);
   void reduce(std::vector<RedDesc> ds);
   void ew(std::vector<EwDesc> ds);
