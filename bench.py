@@ -522,23 +522,44 @@ def main():
 
     if args.batch > 1:
         # the same workload, several independent lattices per call (one grouped launch per stage)
-        note(f"batched: {args.batch} lattices per call")
-        states = [binding.to_device(workload_peps("8x8_D4_chi32", seed=2000 + i)) for i in range(args.batch)]
-        for _ in range(2):
-            envs = sess.env_boundary(states, chi, "f64", H)
-            sess.expect(envs)
-        torch.cuda.synchronize()
-        nb = max(2, args.steps // 4)
-        t0 = time.perf_counter()
-        for _ in range(nb):
-            envs = sess.env_boundary(states, chi, "f64", H)
-            sess.expect(envs)
-            for e in envs:
-                e.free()
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        out["batched"] = {"lattices_per_call": args.batch, "value": nb * args.batch / tb, "unit": "env/s",
-                          "ms_per_call": 1000.0 * tb / nb}
+        note(f"batched: {args.batch} and {2 * args.batch} lattices per call")
+        states = [binding.to_device(workload_peps("8x8_D4_chi32", seed=2000 + i)) for i in range(2 * args.batch)]
+
+        def batched(dtype, nlat):
+            sub = states[:nlat]
+            for _ in range(2):
+                envs = sess.env_boundary(sub, chi, dtype, H)
+                sess.expect(envs)
+                for e in envs:
+                    e.free()
+            torch.cuda.synchronize()
+            nb = max(2, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(nb):
+                envs = sess.env_boundary(sub, chi, dtype, H)
+                res = sess.expect(envs)
+                for e in envs:
+                    e.free()
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            return nb * nlat / tb, 1000.0 * tb / nb, res
+
+        single = args.steps / dt
+        v, ms, _ = batched("f64", args.batch)
+        out["batched"] = {"lattices_per_call": args.batch, "value": v, "unit": "env/s", "ms_per_call": ms,
+                          "speedup_vs_single_f64": v / single}
+        # the batched forms against the plain single-lattice FP64 rate, each
+        # lattice's energy against its own FP64 result
+        nl = 2 * args.batch
+        v64, ms64, r64 = batched("f64", nl)
+        e64 = [energy(r) for r in r64]
+        forms = {"lattices_per_call": nl, "single_f64_env_per_s": single}
+        for dname in ("f64", "f32"):
+            vv, mm, rr = (v64, ms64, r64) if dname == "f64" else batched(dname, nl)
+            err = max(abs(energy(r) - e) / abs(e) for r, e in zip(rr, e64))
+            forms[dname] = {"value": vv, "unit": "env/s", "ms_per_call": mm, "speedup_vs_single_f64": vv / single,
+                            "max_rel_energy_err_vs_f64": err}
+        out["batched_forms"] = forms
 
     if not args.no_columns:
         # the same workload with the vertical bonds from single-column sandwiches of
