@@ -522,8 +522,8 @@ def main():
 
     if args.batch > 1:
         # the same workload, several independent lattices per call (one grouped launch per stage)
-        note(f"batched: {args.batch} and {2 * args.batch} lattices per call")
-        states = [binding.to_device(workload_peps("8x8_D4_chi32", seed=2000 + i)) for i in range(2 * args.batch)]
+        note(f"batched: {args.batch} and {4 * args.batch} lattices per call")
+        states = [binding.to_device(workload_peps("8x8_D4_chi32", seed=2000 + i)) for i in range(4 * args.batch)]
 
         def batched(dtype, nlat):
             sub = states[:nlat]
@@ -548,9 +548,9 @@ def main():
         v, ms, _ = batched("f64", args.batch)
         out["batched"] = {"lattices_per_call": args.batch, "value": v, "unit": "env/s", "ms_per_call": ms,
                           "speedup_vs_single_f64": v / single}
-        # the batched forms against the plain single-lattice FP64 rate, each
-        # lattice's energy against its own FP64 result
-        nl = 2 * args.batch
+        # the batched forms (4x the lattices per call) against the plain
+        # single-lattice FP64 rate, each lattice's energy against its own FP64 result
+        nl = 4 * args.batch
         v64, ms64, r64 = batched("f64", nl)
         e64 = [energy(r) for r in r64]
         forms = {"lattices_per_call": nl, "single_f64_env_per_s": single}

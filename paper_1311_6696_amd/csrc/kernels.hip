@@ -973,6 +973,100 @@ void launch_kb(int prec, int out_dt, int nb1, const KbDesc* d, int nd, int nbloc
   PE_HIP(hipGetLastError());
 }
 
+// Short, skinny contraction (see TskDesc): workgroup (row tile, slice)
+// stages its A block (32 x 64) and B block (64 x 32) in LDS with loads along
+// each operand's unit-stride index, and wave w forms the 16 x 16 output
+// block (w / 2, w % 2) on MFMA.  The slice's partial tile goes to the
+// workspace through device-scope stores; the last slice of the tile to
+// arrive sums all of them in slice order (its loads issued eight slices at
+// a time, before the adds) and stores C.
+__global__ __launch_bounds__(256) void tsk_kernel(const TskDesc* __restrict__ ds, int nd, unsigned* __restrict__ counters) {
+  constexpr int MT = TSK_MT, KS = TSK_KS, AP = KS + 1, BP = 32 + 1, TE = MT * 32;
+  __shared__ double As[MT * AP];
+  __shared__ double Bs[KS * BP];
+  __shared__ int sh;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].tile_base <= b) lo = mid; else hi = mid - 1;
+  }
+  const TskDesc& d = ds[lo];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int local = b - d.tile_base, t = local / d.ksplit, slice = local - t * d.ksplit;
+  const int m0 = t * MT, k0 = slice * KS;
+  const int M = d.M, N = d.N, K = d.K;
+  // A block [i][kk] and B block [kk][n]: consecutive threads along each
+  // operand's unit-stride index
+  const bool a_kfast = d.sAk == 1 || d.sAm != 1;
+  const bool b_nfast = d.sBn == 1 && d.sBk != 1;
+#pragma unroll
+  for (int j = 0; j < MT * KS / 256; ++j) {
+    const int e = tid + 256 * j;
+    const int i = a_kfast ? e / KS : e % MT, kk = a_kfast ? e % KS : e / MT;
+    const int m = m0 + i, k = k0 + kk;
+    As[i * AP + kk] = (m < M && k < K) ? d.A[m * d.sAm + k * d.sAk] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < KS * 32 / 256; ++j) {
+    const int e = tid + 256 * j;
+    const int kk = b_nfast ? e / 32 : e % KS, n = b_nfast ? e % 32 : e / KS;
+    const int k = k0 + kk;
+    Bs[kk * BP + n] = (n < N && k < K) ? d.B[k * d.sBk + n * d.sBn] : 0.0;
+  }
+  __syncthreads();
+  const int bi = w >> 1, bj = w & 1;
+  d4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < KS / 4; ++ks)   // D = B^T A^T: lanes along the rows
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(Bs[(4 * ks + lk) * BP + 16 * bj + lr],
+                                             As[(16 * bi + lr) * AP + 4 * ks + lk], c, 0, 0, 0);
+  // this lane's outputs: row 16 bi + lr, columns 16 bj + lk + 4r; partial tile n-major, m fastest
+  const int row = 16 * bi + lr;
+  double* part = d.part + ((int64_t)t * d.ksplit + slice) * TE;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    __hip_atomic_store(&part[(16 * bj + lk + 4 * r) * MT + row], c[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);   // this thread's partial is complete before the tile's counter moves
+  __syncthreads();
+  if (tid == 0)
+    sh = __hip_atomic_fetch_add(counters + d.cnt_base + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+         (unsigned)(d.ksplit - 1);
+  __syncthreads();
+  if (!sh) return;
+  // last slice of the tile: thread -> elements tid + 256 j of the tile
+  const double* tp = d.part + (int64_t)t * d.ksplit * TE;
+  constexpr int PER = TE / 256;
+  double acc[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) acc[j] = 0.0;
+  for (int q0 = 0; q0 < d.ksplit; q0 += 8) {
+    double v[8][PER];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int j = 0; j < PER; ++j)
+        v[u][j] = q0 + u < d.ksplit ? __hip_atomic_load(const_cast<double*>(&tp[(int64_t)(q0 + u) * TE + tid + 256 * j]),
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)   // in slice order (a missing slice adds zero)
+#pragma unroll
+      for (int j = 0; j < PER; ++j) acc[j] += v[u][j];
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j, rr = e % MT, n = e / MT, mm = m0 + rr;
+    if (mm < M && n < N) d.C[mm * d.sCm + n * d.sCn] = d.alpha * acc[j];
+  }
+}
+
+void launch_tsk(const TskDesc* d, int nd, int nblocks, unsigned* counters, hipStream_t s) {
+  if (nblocks <= 0) return;
+  tsk_kernel<<<nblocks, 256, 0, s>>>(d, nd, counters);
+  PE_HIP(hipGetLastError());
+}
+
 // Split-K reduction: one thread per output element (256 per workgroup,
 // MT*NT/256 workgroups per tile); the partial slices are summed in slice
 // order, so the result does not depend on scheduling.

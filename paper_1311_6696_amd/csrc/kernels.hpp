@@ -33,6 +33,25 @@ struct TcDesc {
   double* part;
 };
 
+// Short, skinny FP64 contraction C[m][n] = alpha * sum_k A[m][k] B[k][n] with
+// one stride per index (n <= 32, m and k of a few hundred to a few
+// thousand): 32 x 32 output tiles, K in slices of TSK_KS, the slices of a
+// tile summed in slice order by the last one to finish (no second launch).
+constexpr int TSK_MT = 32, TSK_KS = 64;
+struct TskDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t sAm, sAk, sBk, sBn, sCm, sCn;
+  int32_t M, N, K;
+  int32_t ksplit;       // slices of TSK_KS
+  int32_t tile_base;    // first workgroup: ceil(M / TSK_MT) * ksplit of them, slice fastest
+  int32_t cnt_base;     // first arrival counter (one per row tile)
+  double alpha;
+  double* part;         // ceil(M / TSK_MT) * ksplit partial tiles of TSK_MT * 32 doubles
+};
+void launch_tsk(const TskDesc* d_desc, int n_desc, int n_blocks, unsigned* counters, hipStream_t s);
+
 // Fused ket-bra contraction (one site's two layers applied in one launch):
 //   Y[R; dr, gs] = sum_{p, q} (sum_{lu} X[R; lu, q] K[lu; dr, p]) B[p, q; gs]
 // Each index group lists its sub-dimensions outermost first with their

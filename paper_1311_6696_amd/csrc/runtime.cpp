@@ -290,7 +290,7 @@ double kb_flops(const KbDesc& d) {
 }
 
 // -------------------------------------------------------------- recorder ----
-enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8, OK_CQ = 9, OK_KC = 10 };
+enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 5, OK_TCS = 6, OK_KB = 7, OK_K2 = 8, OK_CQ = 9, OK_KC = 10, OK_TSK = 11 };
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
@@ -372,8 +372,92 @@ static uint64_t tune_key(int prec, int out_dt, int fam, bool skinny, const std::
   return k;
 }
 
+// A contraction the short skinny kernel takes: FP64 with beta = 0, one
+// sub-dimension per index group, the narrow output side (<= 32) as n (the
+// operands swap roles when it is m), the wide side <= 4096, 128 <= K <= 8192.
+static bool tsk_from(const TcDesc& d, TskDesc& t) {
+  if (d.nm != 1 || d.nn != 1 || d.nk != 1 || d.beta != 0.0 || d.K < 128 || d.K > 8192) return false;
+  const bool swap = d.N > 32;
+  const int M = swap ? d.N : d.M, N = swap ? d.M : d.N;
+  if (N > 32 || M > 4096) return false;
+  std::memset(&t, 0, sizeof(t));
+  if (!swap) {
+    t.A = (const double*)d.A;
+    t.sAm = d.sAm[0];
+    t.sAk = d.sAk[0];
+    t.B = (const double*)d.B;
+    t.sBk = d.sBk[0];
+    t.sBn = d.sBn[0];
+    t.sCm = d.sCm[0];
+    t.sCn = d.sCn[0];
+  } else {   // C^T = B^T A^T
+    t.A = (const double*)d.B;
+    t.sAm = d.sBn[0];
+    t.sAk = d.sBk[0];
+    t.B = (const double*)d.A;
+    t.sBk = d.sAk[0];
+    t.sBn = d.sAm[0];
+    t.sCm = d.sCn[0];
+    t.sCn = d.sCm[0];
+  }
+  t.C = (double*)d.C;
+  t.M = M;
+  t.N = N;
+  t.K = d.K;
+  t.alpha = d.alpha;
+  return true;
+}
+
+void Rec::tsk(std::vector<TskDesc> ds, bool algorithmic) {
+  if (ds.empty()) return;
+  int64_t blocks = 0, parts = 0;
+  double fl = 0.0, by = 0.0;
+  for (auto& t : ds) {
+    const int tiles = (t.M + TSK_MT - 1) / TSK_MT;
+    t.ksplit = (t.K + TSK_KS - 1) / TSK_KS;
+    t.tile_base = (int32_t)blocks;
+    blocks += (int64_t)tiles * t.ksplit;
+    t.cnt_base = cq_slots_;
+    cq_slots_ += tiles;
+    parts += (int64_t)tiles * t.ksplit * TSK_MT * 32;
+    fl += 2.0 * t.M * (double)t.N * t.K;
+    by += 8.0 * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N);
+  }
+  PE_REQUIRE(blocks < INT_MAX, "too many tiles in one launch");
+  // the partial buffer is shared with the split-K contractions: launches run
+  // in stream order and each finishes its sums before the next starts
+  if ((size_t)parts > part_cap_) {
+    part_cap_ = std::max((size_t)parts, part_cap_ * 2);
+    part_buf_ = (double*)scratch_->alloc(sizeof(double) * part_cap_);
+  }
+  int64_t off = 0;
+  for (auto& t : ds) {
+    t.part = part_buf_ + off;
+    off += (int64_t)((t.M + TSK_MT - 1) / TSK_MT) * t.ksplit * TSK_MT * 32;
+  }
+  Op op{OK_TSK, TP_F64, DT_F64, 0, (int)ds.size(), (int)blocks, push_bytes(ds.data(), ds.size() * sizeof(TskDesc)),
+        algorithmic ? fl : 0.0};
+  op.bytes = by;
+  if (algorithmic) flops_ += fl;
+  ops_.push_back(op);
+}
+
 void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   if (ds.empty()) return;
+  if (prec == TP_F64 && out_dt == DT_F64 && scratch_ && !ctx_->tuning) {
+    std::vector<TskDesc> ts;
+    std::vector<TcDesc> rest;
+    for (const auto& d : ds) {
+      TskDesc t;
+      if (tsk_from(d, t)) ts.push_back(t);
+      else rest.push_back(d);
+    }
+    if (!ts.empty()) {
+      tsk(std::move(ts), algorithmic);
+      ds.swap(rest);
+      if (ds.empty()) return;
+    }
+  }
   // the descriptors of one group are independent, so families (and the
   // skinny-kernel members of a family) may run as separate launches
   std::vector<TcDesc> fam[N_FAMILIES];
@@ -787,6 +871,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, unsigned* counters, bool
         break;
       case OK_K2: launch_k2((const K2Desc*)d, op.nd, op.grid, op.kp, s); break;
       case OK_KC: launch_kc((const KcDesc*)d, op.nd, op.grid, s); break;
+      case OK_TSK: launch_tsk((const TskDesc*)d, op.nd, op.grid, counters, s); break;
       case OK_KB:
         launch_kb(op.prec, op.out_dt, op.tile - TT_KB16 + 1, (const KbDesc*)d, op.nd, op.grid, op.ksm, op.kp, op.q, s);
         break;

@@ -111,6 +111,8 @@ class Rec {
   void k2(std::vector<K2Desc> ds, double flops);
   // Fused one-row chain steps (float64); `flops` their algorithmic flops.
   void kc(std::vector<KcDesc> ds, double flops);
+  // Short, skinny FP64 contractions (see TskDesc).
+  void tsk(std::vector<TskDesc> ds, bool algorithmic);
   void qr(const std::vector<QrDesc>& ds);
   void reduce(std::vector<RedDesc> ds);
   void ew(std::vector<EwDesc> ds);
@@ -155,7 +157,7 @@ class Rec {
   std::vector<uint8_t> blob_;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> aux_;   // dst, (blob offset, bytes)
   int partials_ = 0;
-  int cq_slots_ = 0;             // CholeskyQR2 arrival counters of this recording (zeroed at issue)
+  int cq_slots_ = 0;             // arrival counters of this recording (CholeskyQR2, skinny split-K; zeroed at issue)
   double* part_buf_ = nullptr;   // split-K partial tiles (scratch)
   size_t part_cap_ = 0;
   double flops_ = 0.0;
