@@ -2746,14 +2746,16 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
     k2_body<CH, false>(d, e, S);
 }
 
-// One-row chain step: wave w of a workgroup takes x = 16 * xt + w for the
+// One-row chain step: wave w of a workgroup takes x = KC_W * xt + w for the
 // workgroup's (xt, e); the top boundary slab of e and both sites are staged
 // in LDS once per workgroup, the wave's row of E is read from global memory
 // (shared by the Ne workgroups of one xt, which run on one XCD).
-__global__ __launch_bounds__(K2_T) void kc_kernel(const KcDesc* __restrict__ ds, int nd, int nblocks) {
+constexpr int KC_T = 64 * KC_W;   // threads per workgroup
+
+__global__ __launch_bounds__(KC_T) void kc_kernel(const KcDesc* __restrict__ ds, int nd, int nblocks) {
   __shared__ double Te[K2_CHI * 16];
   __shared__ double Ks[16 * 32], Bs[32 * 16];
-  __shared__ double Priv[K2_W * K2_PRIV];
+  __shared__ double Priv[KC_W * K2_PRIV];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   double* Pw = Priv + w * K2_PRIV;
@@ -2768,7 +2770,7 @@ __global__ __launch_bounds__(K2_T) void kc_kernel(const KcDesc* __restrict__ ds,
   const KcDesc& d = ds[lo];
   const int local = v - d.block_base, xt = local / d.Ne, e = local - xt * d.Ne;
   const int A = d.A, A4 = (A + 3) & ~3;
-  for (int i = tid; i < 512; i += K2_T) {
+  for (int i = tid; i < 512; i += KC_T) {
     {   // Ks[(l,u)][(d,r,p)]
       const int k = i >> 5, n = i & 31, l = k >> 2, u = k & 3, dd = n >> 3, r = (n >> 1) & 3, p = n & 1;
       const int64_t* t = d.ss[0];
@@ -2780,13 +2782,13 @@ __global__ __launch_bounds__(K2_T) void kc_kernel(const KcDesc* __restrict__ ds,
       Bs[i] = d.s[1][p * t[0] + m * t[1] + vv * t[2] + sx * t[3] + g * t[4]];
     }
   }
-  for (int i = tid; i < A4 * 16; i += K2_T) {
+  for (int i = tid; i < A4 * 16; i += KC_T) {
     const int a = i >> 4, uv = i & 15;
     Te[i] = a < A ? d.T[a * d.sT[0] + (uv >> 2) * d.sT[1] + (uv & 3) * d.sT[2] + e * d.sT[3]] : 0.0;
   }
   // this wave's x (clamped for the loads; waves past X store nothing) and
   // its lane's row (l, m) = lr of E, a = 4 ks + lk
-  const int x = 16 * xt + w;
+  const int x = KC_W * xt + w;
   const bool act = x < d.X;
   const double* Ex = d.E + (act ? x : d.X - 1) * d.sE[0] + (lr >> 2) * d.sE[1] + (lr & 3) * d.sE[2];
   constexpr int KMAX = K2_CHI / 4;
@@ -2833,7 +2835,7 @@ __global__ __launch_bounds__(K2_T) void kc_kernel(const KcDesc* __restrict__ ds,
 void launch_kc(const KcDesc* d, int nd, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
   const int grid = (nblocks + 7) / 8 * 8;   // a multiple of the XCD count: the block order is a bijection
-  kc_kernel<<<grid, K2_T, 0, s>>>(d, nd, nblocks);
+  kc_kernel<<<grid, KC_T, 0, s>>>(d, nd, nblocks);
   PE_HIP(hipGetLastError());
 }
 

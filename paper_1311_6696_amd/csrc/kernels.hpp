@@ -114,7 +114,7 @@ void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, hipStr
 // one-row sandwich's first three contractions in one launch:
 //   Y[x][d][g][r][s][e] = sum E[x][l][m][a] T[a][u][v][e] K[p][l][u][r][d] B[p][m][v][s][g]
 // (a right-to-left step is the same with the roles of its horizontal legs
-// exchanged through the strides).  One wave per (x, e), sixteen x per
+// exchanged through the strides).  One wave per (x, e), KC_W x per
 // workgroup.
 struct KcDesc {
   const double* E;
@@ -126,8 +126,9 @@ struct KcDesc {
   int64_t ss[2][5];     // p, l, u, r, d  (bra: p, m, v, s, g)
   int64_t sY[6];        // x, d, g, r, s, e
   int32_t X, A, Ne;     // bonds x, a (<= K2_CHI) and e
-  int32_t block_base;   // first workgroup of this descriptor: ceil(X / 16) * Ne of them, e fastest
+  int32_t block_base;   // first workgroup of this descriptor: ceil(X / KC_W) * Ne of them, e fastest
 };
+constexpr int KC_W = 8;   // waves (x values) per workgroup of the one-row chain step
 void launch_kc(const KcDesc* d_desc, int n_desc, int n_blocks, hipStream_t s);
 
 // Arithmetic of a contraction.

@@ -698,7 +698,7 @@ void Rec::kc(std::vector<KcDesc> ds, double flops) {
   for (auto& d : ds) {
     PE_REQUIRE(d.X >= 1 && d.A >= 1 && d.Ne >= 1 && d.A <= K2_CHI, "one-row chain step: bond outside the fused kernel's range");
     d.block_base = (int32_t)blocks;
-    blocks += (int64_t)((d.X + 15) / 16) * d.Ne;
+    blocks += (int64_t)((d.X + KC_W - 1) / KC_W) * d.Ne;
   }
   PE_REQUIRE(blocks < INT_MAX / 8, "one-row chain step too large");
   flops_ += flops;
