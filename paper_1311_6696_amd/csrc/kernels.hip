@@ -1668,15 +1668,11 @@ __device__ __attribute__((always_inline)) inline void cq_store_r(const QrDesc& d
   }
 }
 
-// Workspace of one block (doubles): the workgroups' partial Gram tile sets,
-// R1, W1 and W2 ((NP+1)-pitched) and the two pass flags.
-__host__ __device__ inline int64_t cq_mat_off(int P, int NB) { return (int64_t)P * (NB * (NB + 1) / 2) * 256; }
-__host__ __device__ inline int64_t cq_flag_off(int P, int NB) {
-  return cq_mat_off(P, NB) + 3 * (int64_t)(16 * NB) * (16 * NB + 1);
-}
+// Workspace of one block (doubles): the workgroups' partial Gram tile sets
+// of pass 1, then those of pass 2.
 size_t cq_ws_doubles(int m, int n) {
   const int NB = n <= 16 ? 1 : 2, P = (m + CQ_ROWS - 1) / CQ_ROWS;
-  return (size_t)cq_flag_off(P, NB) + 2;
+  return (size_t)2 * P * (NB * (NB + 1) / 2) * 256;
 }
 
 // The block whose workgroup range holds workgroup b, and b's index in it.
@@ -1699,8 +1695,8 @@ __device__ inline QrDesc cq_rows(const QrDesc& d, int p) {
   return q;
 }
 
-// Data that workgroups of one block exchange (partial Gram sets, factors,
-// flags) is written and read with device-scope accesses, which bypass the
+// Data that workgroups of one block exchange (their partial Gram sets) is
+// written and read with device-scope accesses, which bypass the
 // per-XCD L2 caches' stale copies, so no cache-wide write-back or
 // invalidation is needed: a writer waits for its stores to complete before
 // the counter moves, and a reader loads after it has seen the counter move.
@@ -1721,8 +1717,8 @@ __device__ inline unsigned cq_arrive(unsigned* c, int* sh) {
   return old;
 }
 
-// Wait until the counter reaches `target` (the last workgroup of the pass
-// has published its factor).  Every workgroup of a launch is resident (at
+// Wait until the counter reaches `target` (every workgroup of the block has
+// stored its partial Gram set).  Every workgroup of a launch is resident (at
 // most CQ_MAXWG of them, one per compute unit), so the wait ends; the polls
 // are bounded all the same, and a wait that runs out returns false.
 __device__ inline bool cq_wait(unsigned* c, unsigned target, int* sh) {
@@ -1741,14 +1737,6 @@ __device__ inline bool cq_wait(unsigned* c, unsigned target, int* sh) {
   const bool ok = *sh != 0;
   __syncthreads();
   return ok;
-}
-
-// Publication of a factor by the last workgroup: its device-scope stores
-// complete, then the counter moves.
-__device__ inline void cq_publish(unsigned* c) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // A wait that ran out: this workgroup's rows of Q become NaN, which the
@@ -1808,15 +1796,21 @@ constexpr int CQ_CPW = CQ_ROWS / 32;   // row chunks of 4 per wave (eight waves)
 static_assert(CQ_CPW % 4 == 0, "whole 16-row tiles per wave");
 
 // One launch per group of blocks, all workgroups resident.  A block's
-// counter (zero at launch) counts the P arrivals after pass 1, +1 when W1 is
-// published, the P arrivals after pass 2 and +1 when W2 is published.  After
-// a failed check the first workgroup factors the whole block by Householder
+// counter (zero at launch) counts the P arrivals after pass 1 and the P
+// after pass 2.  Every workgroup waits for all P arrivals of a pass, sums
+// the P partial Gram sets itself in workgroup order and runs the same
+// Cholesky, so all of them hold the same factors (bit for bit) without any
+// factor being published.  After a failed check (the same in every
+// workgroup) the first workgroup factors the whole block by Householder
 // (A is untouched until pass 3) and the others leave.
 template <int NB>
 __global__ __launch_bounds__(512) void cq_kernel(const CqDesc* __restrict__ ds, int nd, unsigned* __restrict__ counters) {
   constexpr int CPW = CQ_CPW, NP = 16 * NB, LD = NP + 1, NT = NB * (NB + 1) / 2;
-  constexpr int A1 = NP * LD + 8 * NT * 256, A2 = 4 * NP * LD + 128 + NP, A3 = qr_house_lds<8, 2 * NB, 8>();
-  constexpr int AREA = A1 > A2 ? (A1 > A3 ? A1 : A3) : (A2 > A3 ? A2 : A3);
+  // LDS: G, R, W and the row buffers of the Cholesky overlap the waves'
+  // partial tile sets (consumed before each sum); R1 lies past both
+  constexpr int A1 = NP * LD + 8 * NT * 256, A2 = 3 * NP * LD + 128 + NP, A3 = qr_house_lds<8, 2 * NB, 8>();
+  constexpr int A12 = A1 > A2 ? A1 : A2;
+  constexpr int AREA = (A12 + NP * LD) > A3 ? A12 + NP * LD : A3;
   __shared__ double sm[AREA];
   __shared__ int sh;
   int p;
@@ -1825,82 +1819,66 @@ __global__ __launch_bounds__(512) void cq_kernel(const CqDesc* __restrict__ ds, 
   const int P = d.P;
   unsigned* cnt = counters + d.cnt;
   double* part = d.ws;
-  double* mat = d.ws + cq_mat_off(P, NB);   // R1, W1, W2
-  double* flags = d.ws + cq_flag_off(P, NB);
   double *Gs = sm, *Rs = sm + NP * LD, *Ws = sm + 2 * NP * LD, *rowb = sm + 3 * NP * LD;
-  double* R1s = rowb + 128 + NP;
-  double* Wb = sm;                 // W1 or W2 for the products
-  double* wpart = sm + NP * LD;    // the waves' partial tile sets
+  double* R1s = sm + A12;          // R1, kept for R = R2 R1
+  double* wpart = sm + NP * LD;    // the waves' partial tile sets (before the sum)
   const QrDesc q = cq_rows(d.q, p);
   double g[CPW][NB], x[CPW / 4][4 * NB];
   if ((d.q.sAc < 0 ? -d.q.sAc : d.q.sAc) <= (d.q.sAr < 0 ? -d.q.sAr : d.q.sAr))
     cq_load<NB, CPW, true>(q, g, x, wave, lane);
   else
     cq_load<NB, CPW, false>(q, g, x, wave, lane);
-  // ---- pass 1: G = A^T A, R1, W1
+  // ---- pass 1: G = A^T A, R1, W1 (in Ws)
   cq_gram<NB, CPW>(g, wpart, wave, lane);
   __syncthreads();
   cq_put_part<NB>(wpart, part, p, tid);
-  if (cq_arrive(cnt, &sh) == (unsigned)(P - 1)) {
-    cq_sum_parts<NB>(part, P, Gs, tid);
-    __syncthreads();
-    if (wave == 0) {
-      const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 1e-14, 0.0, lane);
-      for (int e = lane; e < NP * LD; e += 64) {
-        cq_st(&mat[e], Rs[e]);             // R1
-        cq_st(&mat[NP * LD + e], Ws[e]);   // W1
-      }
-      if (lane == 0) cq_st(&flags[0], good ? 1.0 : 0.0);
-    }
-    cq_publish(cnt);
-  }
-  if (!cq_wait(cnt, (unsigned)P + 1, &sh)) {
+  cq_arrive(cnt, &sh);
+  if (!cq_wait(cnt, (unsigned)P, &sh)) {
     cq_poison(q);
     return;
   }
-  if (cq_ld(&flags[0]) == 0.0) {
+  cq_sum_parts<NB>(part, P, Gs, tid);
+  __syncthreads();
+  if (wave == 0) {
+    const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 1e-14, 0.0, lane);
+    if (lane == 0) sh = good;
+  }
+  __syncthreads();
+  if (!sh) {
     if (p == 0) qr_house<8, 2 * NB, 8>(d.q, sm);
     return;
   }
+  for (int e = tid; e < NP * LD; e += 512) R1s[e] = Rs[e];
   // ---- pass 2: Q1 = A W1 (kept in registers), G2 = Q1^T Q1, W2, R = R2 R1
-  for (int e = tid; e < NP * LD; e += 512) Wb[e] = cq_ld(&mat[NP * LD + e]);
-  __syncthreads();
-  cq_right<NB, CPW>(x, Wb, g, lane);
+  cq_right<NB, CPW>(x, Ws, g, lane);
+  __syncthreads();   // W1 and R1 are read before the partial tiles reuse the area
   cq_gram<NB, CPW>(g, wpart, wave, lane);
   __syncthreads();
-  cq_put_part<NB>(wpart, part, p, tid);
-  if (cq_arrive(cnt, &sh) == 2 * (unsigned)P) {
-    cq_sum_parts<NB>(part, P, Gs, tid);
-    for (int e = tid; e < NP * LD; e += 512) R1s[e] = cq_ld(&mat[e]);
-    __syncthreads();
-    if (wave == 0) {
-      const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 0.5, 1e-2, lane);
-      for (int e = lane; e < NP * LD; e += 64) cq_st(&mat[2 * NP * LD + e], Ws[e]);   // W2
-      if (lane == 0) {
-        cq_st(&flags[1], good ? 1.0 : 0.0);
-        sh = good;
-      }
-    }
-    __syncthreads();
-    if (sh && d.q.R) cq_store_r<NB>(d.q, Rs, R1s, wave, lane);
-    cq_publish(cnt);
-  }
-  if (!cq_wait(cnt, 2 * (unsigned)P + 2, &sh)) {
+  // this pass's partial sets go to the second half of the block's area
+  cq_put_part<NB>(wpart, part + (int64_t)P * NT * 256, p, tid);
+  cq_arrive(cnt, &sh);
+  if (!cq_wait(cnt, 2 * (unsigned)P, &sh)) {
     cq_poison(q);
     return;
   }
-  if (cq_ld(&flags[1]) == 0.0) {
+  cq_sum_parts<NB>(part + (int64_t)P * NT * 256, P, Gs, tid);
+  __syncthreads();
+  if (wave == 0) {
+    const bool good = cq_chol<NB>(Gs, Rs, Ws, rowb, d.q.n, 0.5, 1e-2, lane);
+    if (lane == 0) sh = good;
+  }
+  __syncthreads();
+  if (!sh) {
     if (p == 0) qr_house<8, 2 * NB, 8>(d.q, sm);
     return;
   }
+  if (p == 0 && d.q.R) cq_store_r<NB>(d.q, Rs, R1s, wave, lane);
   // ---- pass 3: Q = Q1 W2
-  for (int e = tid; e < NP * LD; e += 512) Wb[e] = cq_ld(&mat[2 * NP * LD + e]);
-  __syncthreads();
   cq_to_rows<NB, CPW>(g, x, lane);
   if ((d.q.sQc < 0 ? -d.q.sQc : d.q.sQc) <= (d.q.sQr < 0 ? -d.q.sQr : d.q.sQr))
-    cq_store_q<NB, CPW, true>(q, x, Wb, wave, lane);
+    cq_store_q<NB, CPW, true>(q, x, Ws, wave, lane);
   else
-    cq_store_q<NB, CPW, false>(q, x, Wb, wave, lane);
+    cq_store_q<NB, CPW, false>(q, x, Ws, wave, lane);
 }
 
 __global__ void cq_clear_kernel(unsigned* c, int n) {
@@ -2710,15 +2688,21 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
       __builtin_amdgcn_wave_barrier();   // the block is read before the next x rewrites it
     }
   }
-  // ---- store: this lane's rows (R,S) = lane & 15 of block (r,s) = w; columns y
+  // ---- store: this lane's rows (R,S) = lane & 15 of block (r,s) = w; columns y.
+  // The lane index is re-read through an empty asm so that the store
+  // addresses are formed here: hoisted above the x loop they would stay live
+  // through it and spill.
   {
-    const int r = w >> 2, sx = w & 3, R = lr >> 2, S = lr & 3;
+    int t2 = threadIdx.x;
+    asm volatile("" : "+v"(t2));
+    const int w2 = t2 >> 6, l2 = t2 & 63, lr2 = l2 & 15, lk2 = l2 >> 4;
+    const int r = w2 >> 2, sx = w2 & 3, R = lr2 >> 2, S = lr2 & 3;
     const int64_t rowoff = R * d.sO[1] + S * d.sO[2] + r * d.sO[3] + sx * d.sO[4] + e * d.sO[5];
 #pragma unroll
     for (int c = 0; c < CH / 16; ++c)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int y = 16 * c + lk + 4 * j;
+        const int y = 16 * c + lk2 + 4 * j;
         if (c < nct && y < Y) d.O[rowoff + y * d.sO[0]] = out[c][j];
       }
   }
