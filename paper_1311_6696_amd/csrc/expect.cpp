@@ -707,6 +707,9 @@ void row_sandwiches(Ctx& ctx, Rec& rec, Arena& call, Scratch& scr, const std::ve
   std::map<std::pair<peps_env*, int>, size_t> job_of;
   std::vector<RJob> fresh;
   std::vector<size_t> fresh_at;
+  // the new sandwiches' buffers: one arena per environment, handed to the
+  // environment only once the sandwiches exist (released if they fail)
+  std::map<peps_env*, std::unique_ptr<Arena>> held;
   for (size_t i = 0; i < keys.size(); ++i) {
     auto it = job_of.find(keys[i]);
     if (it == job_of.end()) {
@@ -716,7 +719,9 @@ void row_sandwiches(Ctx& ctx, Rec& rec, Arena& call, Scratch& scr, const std::ve
       if (c != e->row_env.end()) {
         rj.push_back(*static_cast<const RJob*>(c->second.get()));
       } else {
-        fresh.push_back(make_row_job(e, e, false, keys[i].second, e->arena, esz));
+        auto& a = held[e];
+        if (!a) a = std::make_unique<Arena>(&e->ctx->pool);
+        fresh.push_back(make_row_job(e, e, false, keys[i].second, *a, esz));
         fresh_at.push_back(rj.size());
         rj.push_back(fresh.back());
       }
@@ -726,6 +731,7 @@ void row_sandwiches(Ctx& ctx, Rec& rec, Arena& call, Scratch& scr, const std::ve
   if (fresh.empty()) return;
   std::vector<R2Job> r2;
   column_envs(rec, call, scr, fresh, r2, prec, cdt, esz, ctx.scratch_budget);
+  for (auto& h : held) h.first->arena.adopt(*h.second);
   for (size_t k = 0; k < fresh.size(); ++k) {
     const RJob& j = fresh[k];
     j.e->row_env[j.r] = std::make_shared<RJob>(j);

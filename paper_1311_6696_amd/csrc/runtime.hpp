@@ -59,6 +59,12 @@ class Arena {
     blocks_.clear();
   }
   size_t used() const { return used_; }
+  // Take over the blocks of `o` (an arena on the same pool), leaving it empty.
+  void adopt(Arena& o) {
+    PE_REQUIRE(pool_ && o.pool_ == pool_, "arenas of different pools");
+    blocks_.insert(blocks_.end(), o.blocks_.begin(), o.blocks_.end());
+    o.blocks_.clear();
+  }
 
  private:
   Pool* pool_ = nullptr;

@@ -410,3 +410,20 @@ def test_bond_fit_with_stored_tensors_equals_site_and_bond_env(sess):
     for x, y in ((n1, Ns[0][0]), (n2, Ns[1][0]), (b1, bl), (b2, br)):
         x, y = x.cpu().numpy(), y.cpu().numpy()
         assert np.abs(x - y).max() < 1e-12 * np.abs(y).max()
+
+
+def test_vertical_bond_fit_with_stored_tensors_equals_site_and_bond_env(sess):
+    """dir 1 (column sandwiches): substitutes equal to the stored tensors give
+    the site environments and the gated-bond environments of the vertical
+    bond (GPU against GPU)."""
+    say("vertical bond fit with the stored tensors")
+    A = make_peps(4, 4, 2, "near_product", 433)
+    env = sess.env_boundary([binding.to_device(A)], 4, "f64", 4, columns=True)[0]
+    G = _dev(_heisenberg_gate(0.1))
+    (n1, b1, n2, b2), = sess.bond_fit([(env, 1, 2, 1, G, _dev(A[1][2]), _dev(A[2][2]))])[0]
+    (bl, br), = sess.bond_env([(env, 1, 2, G, 1)])[0]
+    Ns, _ = sess.site_env([(env, 1, 2, 1), (env, 2, 2, 1)])
+    env.free()
+    for x, y in ((n1, Ns[0][0]), (n2, Ns[1][0]), (b1, bl), (b2, br)):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.abs(x - y).max() < 1e-12 * np.abs(y).max()
