@@ -218,6 +218,42 @@ inline EwDesc ew_desc(int kind, const void* src, int sdt, void* dst, int ddt, in
   return e;
 }
 
+// Small FP64 result arrays spread over device buffers, gathered into one
+// buffer by a single copy launch recorded ahead of the flush, so that the
+// host reads all of them back with one transfer instead of one per array.
+struct Gather {
+  struct Item {
+    const double* src;
+    size_t off, n;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  double* buf = nullptr;
+  std::vector<double> host;
+  size_t add(const double* d, size_t n) {
+    items.push_back({d, total, n});
+    total += n;
+    return total - n;
+  }
+  void record(Rec& rec, Arena& arena) {
+    if (!total) return;
+    buf = (double*)arena.alloc(total * sizeof(double));
+    std::vector<EwDesc> ds;
+    ds.reserve(items.size());
+    for (const Item& it : items) ds.push_back(ew_desc(EW_COPY, it.src, DT_F64, buf + it.off, DT_F64, (int64_t)it.n));
+    rec.ew(ds);
+  }
+  // after the recorder ran: one transfer, then a wait
+  void read(hipStream_t s) {
+    host.assign(total, 0.0);
+    if (total) dev::d2h(host.data(), buf, total * sizeof(double), s);
+    dev::sync(s);
+  }
+  std::vector<double> slice(size_t off, size_t n) const {
+    return std::vector<double>(host.begin() + off, host.begin() + off + n);
+  }
+};
+
 inline RedDesc red_desc(const void* x, const void* y, int64_t n, double* out, int dt) {
   RedDesc r;
   std::memset(&r, 0, sizeof(r));

@@ -50,6 +50,31 @@ struct RJob {
   double* dots;  // D[0..Lc], sz nums [Lc], bond nums [3*(Lc-1)]
 };
 
+// Runs what `rec` holds and reads each job's Lc+1 overlaps and left/right
+// squared step norms back in one transfer.
+void run_and_read_dots(Rec& rec, Arena& call, const std::vector<RJob>& rj, hipStream_t s,
+                       std::vector<std::vector<double>>& hd, std::vector<std::vector<double>>& hl,
+                       std::vector<std::vector<double>>& hr) {
+  Gather g;
+  std::vector<std::array<size_t, 3>> off(rj.size());
+  for (size_t k = 0; k < rj.size(); ++k) {
+    const size_t n = (size_t)rj[k].Lc + 1;
+    off[k] = {g.add(rj[k].dots, n), g.add(rj[k].nuL, n), g.add(rj[k].nuR, n)};
+  }
+  g.record(rec, call);
+  rec.run(call);
+  g.read(s);
+  hd.resize(rj.size());
+  hl.resize(rj.size());
+  hr.resize(rj.size());
+  for (size_t k = 0; k < rj.size(); ++k) {
+    const size_t n = (size_t)rj[k].Lc + 1;
+    hd[k] = g.slice(off[k][0], n);
+    hl[k] = g.slice(off[k][1], n);
+    hr[k] = g.slice(off[k][2], n);
+  }
+}
+
 struct R2Job {
   peps_env* e;
   int r, Lc;
@@ -591,7 +616,20 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
     }
     rec.reduce(rd);
   }
+  Gather g;
+  std::vector<std::array<size_t, 3>> o1(rj.size());
+  std::vector<std::array<size_t, 2>> o2(r2.size());
+  for (size_t i = 0; i < rj.size(); ++i) {
+    const size_t Lc = rj[i].Lc;
+    o1[i] = {g.add(rj[i].dots, Lc + 1 + Lc + 3 * Lc), g.add(rj[i].nuL, Lc + 1), g.add(rj[i].nuR, Lc + 1)};
+  }
+  for (size_t i = 0; i < r2.size(); ++i) {
+    const size_t Lc = r2[i].Lc;
+    o2[i] = {g.add(r2[i].dots, Lc + 1 + 3 * Lc), g.add(r2[i].nuL, Lc + 1)};
+  }
+  g.record(rec, call);
   rec.run(call);
+  g.read(ctx.stream);
 
   // ------------------------------------------------- host arithmetic ----
   out.assign(envs.size(), ExpectOut());
@@ -609,25 +647,19 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
     }
     eo.log_norm = NAN;
   }
-  auto fetch = [&](const double* d, size_t n) {
-    std::vector<double> h(n);
-    dev::d2h(h.data(), d, n * sizeof(double), ctx.stream);
-    return h;
-  };
   std::vector<std::vector<double>> hdots(rj.size()), hnuL(rj.size()), hnuR(rj.size());
   std::vector<std::vector<double>> h2dots(r2.size()), h2nuL(r2.size());
   for (size_t i = 0; i < rj.size(); ++i) {
-    const int Lc = rj[i].Lc;
-    hdots[i] = fetch(rj[i].dots, Lc + 1 + Lc + 3 * Lc);
-    hnuL[i] = fetch(rj[i].nuL, Lc + 1);
-    hnuR[i] = fetch(rj[i].nuR, Lc + 1);
+    const size_t Lc = rj[i].Lc;
+    hdots[i] = g.slice(o1[i][0], Lc + 1 + Lc + 3 * Lc);
+    hnuL[i] = g.slice(o1[i][1], Lc + 1);
+    hnuR[i] = g.slice(o1[i][2], Lc + 1);
   }
   for (size_t i = 0; i < r2.size(); ++i) {
-    const int Lc = r2[i].Lc;
-    h2dots[i] = fetch(r2[i].dots, Lc + 1 + 3 * Lc);
-    h2nuL[i] = fetch(r2[i].nuL, Lc + 1);
+    const size_t Lc = r2[i].Lc;
+    h2dots[i] = g.slice(o2[i][0], Lc + 1 + 3 * Lc);
+    h2nuL[i] = g.slice(o2[i][1], Lc + 1);
   }
-  dev::sync(ctx.stream);
   for (size_t i = 0; i < rj.size(); ++i) {
     const RJob& j = rj[i];
     peps_env* e = j.e;
@@ -825,19 +857,8 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
     rd.push_back(red_desc(j.L[c + 1], j.R[c + 1], env_elems(j, c + 1), j.dots + c + 1, cdt));
   }
   rec.reduce(rd);
-  rec.run(call);
-
-  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
-  for (size_t k = 0; k < rj.size(); ++k) {
-    const int Lc = rj[k].Lc;
-    hd[k].resize(Lc + 1);
-    hl[k].resize(Lc + 1);
-    hr[k].resize(Lc + 1);
-    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
-  }
-  dev::sync(ctx.stream);
+  std::vector<std::vector<double>> hd, hl, hr;
+  run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);
   log_z.assign(req.size(), 0.0);
   sign.assign(req.size(), 1.0);
   double* w2 = (double*)call.alloc(sizeof(double) * req.size());
@@ -1028,19 +1049,8 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
     }
     rec.reduce(rd);
   }
-  rec.run(call);
-
-  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
-  for (size_t k = 0; k < rj.size(); ++k) {
-    const int Lc = rj[k].Lc;
-    hd[k].resize(Lc + 1);
-    hl[k].resize(Lc + 1);
-    hr[k].resize(Lc + 1);
-    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
-  }
-  dev::sync(ctx.stream);
+  std::vector<std::vector<double>> hd, hl, hr;
+  run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);
   // b_left / (sqrt(nuR[c+1]) |w_c|), b_right / (sqrt(nuL[c+1]) |w_c+1|), with
   // w_k = sqrt(nuL[k+1]) <L[k+1], R[k+1]> (= sum_p A N A of site k): the
   // scaling of the sites' norm environments
@@ -1129,15 +1139,17 @@ void plan_overlap(Ctx& ctx, std::vector<OvReq>& req) {
     rec.tc(TP_F64, DT_F64, st2);
     rec.flush(call);
   }
-  rec.run(call);
+  Gather g;
   for (size_t i = 0; i < req.size(); ++i)
     for (int t = 0; t < 3; ++t) {
       const Chain& c = ch[3 * i + t];
-      double v = 0.0;
-      dev::d2h(&v, c.e[c.x->leg.size() & 1], sizeof(double), ctx.stream);
-      dev::sync(ctx.stream);
-      req[i].out[t] = v;
+      g.add((const double*)c.e[c.x->leg.size() & 1], 1);
     }
+  g.record(rec, call);
+  rec.run(call);
+  g.read(ctx.stream);
+  for (size_t i = 0; i < req.size(); ++i)
+    for (int t = 0; t < 3; ++t) req[i].out[t] = g.host[3 * i + t];
 }
 
 }  // namespace pe
@@ -1318,19 +1330,8 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
     }
     rec.reduce(rd);
   }
-  rec.run(call);
-
-  std::vector<std::vector<double>> hd(rj.size()), hl(rj.size()), hr(rj.size());
-  for (size_t k = 0; k < rj.size(); ++k) {
-    const int Lc = rj[k].Lc;
-    hd[k].resize(Lc + 1);
-    hl[k].resize(Lc + 1);
-    hr[k].resize(Lc + 1);
-    dev::d2h(hd[k].data(), rj[k].dots, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hl[k].data(), rj[k].nuL, sizeof(double) * (Lc + 1), ctx.stream);
-    dev::d2h(hr[k].data(), rj[k].nuR, sizeof(double) * (Lc + 1), ctx.stream);
-  }
-  dev::sync(ctx.stream);
+  std::vector<std::vector<double>> hd, hl, hr;
+  run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);
   // the gated bond's scale factors of the two sites (the stored state's)
   double* s2 = (double*)call.alloc(sizeof(double) * 2 * req.size());
   std::vector<EwDesc> fill, scale;

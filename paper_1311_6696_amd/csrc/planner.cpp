@@ -359,10 +359,12 @@ void plan_als(Rec& rec, Arena& call, Ctx& ctx, std::vector<AJob*>& js, const Opt
   }
   std::vector<double> w(2 * js.size());
   while (!act.empty()) {
+    Gather g;
+    for (AJob* j : act) g.add(j->omega + (j->H - 2), 2);
+    g.record(rec, call);
     rec.flush(call);
-    for (size_t i = 0; i < act.size(); ++i)
-      dev::d2h(&w[2 * i], act[i]->omega + (act[i]->H - 2), 2 * sizeof(double), ctx.stream);
-    dev::sync(ctx.stream);
+    g.read(ctx.stream);
+    std::copy(g.host.begin(), g.host.end(), w.begin());
     std::vector<AJob*> next;
     for (size_t i = 0; i < act.size(); ++i) {
       AJob* j = act[i];
@@ -538,17 +540,24 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
   size_t nlog = 0;
   for (peps_env* e : envs) nlog += 2 * (size_t)e->lat.Lr;
   double* logs = (double*)call.alloc(sizeof(double) * std::max<size_t>(nlog, 1));
+  // every side's list of omega pointers in one device copy
+  std::vector<const double*> w;
+  std::vector<size_t> first;
   size_t at = 0;
   for (peps_env* e : envs) {
     for (int side = 0; side < 2; ++side) {
       std::vector<Mps>& vec = side == 0 ? e->top : e->bot;
-      std::vector<const double*> w;
+      first.push_back(w.size());
       for (size_t k = 1; k < vec.size(); ++k) w.push_back(vec[k].omega + (vec[k].n_omega - 1));
-      EwDesc d = ew_desc(EW_LOGACC, nullptr, DT_F64, logs + at, DT_F64, (int64_t)w.size());
-      d.src = w.empty() ? nullptr : rec.aux(call, w.data(), w.size() * sizeof(const double*));
+      EwDesc d = ew_desc(EW_LOGACC, nullptr, DT_F64, logs + at, DT_F64, (int64_t)(w.size() - first.back()));
       acc.push_back(d);
       at += e->lat.Lr;
     }
+  }
+  if (!w.empty()) {
+    const double** wd = (const double**)rec.aux(call, w.data(), w.size() * sizeof(const double*));
+    for (size_t i = 0; i < acc.size(); ++i)
+      if (acc[i].n) acc[i].src = wd + first[i];
   }
   rec.ew(acc);
   rec.run(call);
