@@ -113,8 +113,8 @@ void check_finite(Ctx& C, const peps_state* st, int n_states, const std::vector<
       chk.push_back(e);
     }
   }
-  rec.ew(clear);
-  rec.ew(chk);
+  rec.ew(std::move(clear));
+  rec.ew(std::move(chk));
   rec.run(tmp);
   double f = 0.0;
   dev::d2h(&f, flag, sizeof(double), C.stream);
@@ -153,7 +153,7 @@ void pack_state(Rec& rec, Arena& arena, const peps_state& s, int cdt, std::vecto
     }
     out.push_back(std::move(st));
   }
-  rec.ew(ew);
+  rec.ew(std::move(ew));
 }
 
 // The transposed lattice of `e` (rows <-> columns, left/right legs <-> up/down
@@ -192,7 +192,7 @@ void* make_one(Rec& rec, Arena& arena, int cdt) {
   void* p = arena.alloc(16);
   std::vector<EwDesc> ew{ew_desc(EW_FILL, nullptr, cdt, p, cdt, 1)};
   ew[0].a = 1.0;
-  rec.ew(ew);
+  rec.ew(std::move(ew));
   return p;
 }
 

@@ -73,7 +73,7 @@ struct St {
   // right-to-left chain, whose horizontal legs swap roles.
   bool add_chain(int stage, const TV& out, const TV& E, const TV& T, const TV& Ak, const TV& Ab, int dt, bool right) {
     if (prec != TP_F64 || dt != DT_F64) return false;
-    const std::vector<int64_t> site{2, 4, 4, 4, 4};
+    const Dims site{2, 4, 4, 4, 4};
     if (Ak.dim != site || Ab.dim != site || E.dim[1] != 4 || E.dim[2] != 4 || T.dim[1] != 4 || T.dim[2] != 4) return false;
     const int64_t A = E.dim[3], Ne = right ? T.dim[0] : T.dim[3];
     if (A > K2_CHI || A != (right ? T.dim[3] : T.dim[0])) return false;
@@ -106,9 +106,9 @@ struct St {
   }
   void record(Rec& rec, int prec_, int cdt) {
     for (size_t i = 0; i < s.size(); ++i) {
-      rec.kc(c[i], cflops[i]);
-      rec.tc(prec_, cdt, s[i]);
-      rec.kb(prec_, cdt, k[i]);
+      rec.kc(std::move(c[i]), cflops[i]);
+      rec.tc(prec_, cdt, std::move(s[i]));
+      rec.kb(prec_, cdt, std::move(k[i]));
     }
   }
 };
@@ -241,7 +241,7 @@ struct Gather {
     std::vector<EwDesc> ds;
     ds.reserve(items.size());
     for (const Item& it : items) ds.push_back(ew_desc(EW_COPY, it.src, DT_F64, buf + it.off, DT_F64, (int64_t)it.n));
-    rec.ew(ds);
+    rec.ew(std::move(ds));
   }
   // after the recorder ran: one transfer, then a wait
   void read(hipStream_t s) {

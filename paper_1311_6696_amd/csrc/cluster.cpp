@@ -162,7 +162,7 @@ extern "C" peps_status peps_cluster_env(peps_ctx* ctx, const peps_state* st, int
       }
     }
     rec.sep(seps);
-    rec.ew(casts);
+    rec.ew(std::move(casts));
     rec.run(tmp);
     // window environments
     auto sigma = [&](int i, int dir, int k, int c) -> const void* {

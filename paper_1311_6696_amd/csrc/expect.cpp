@@ -236,8 +236,8 @@ void normalise(Rec& rec, const std::vector<std::pair<TV, double*>>& outs) {
     e.sptr = o.second;
     ew.push_back(e);
   }
-  rec.reduce(rd);
-  rec.ew(ew);
+  rec.reduce(std::move(rd));
+  rec.ew(std::move(ew));
 }
 
 // One single-row sandwich job: row r of e between T_{r-1} and B_{r+1}, its
@@ -375,8 +375,8 @@ void column_envs(Rec& rec, Arena& call, Scratch& scr, std::vector<RJob>& rj, std
       }
       st1.record(rec, prec, cdt);
       st2.record(rec, prec, cdt);
-      rec.tc(prec, cdt, fin);
-      rec.k2(k2s, k2f);
+      rec.tc(prec, cdt, std::move(fin));
+      rec.k2(std::move(k2s), k2f);
       normalise(rec, outs);
       rec.flush(call);
     }
@@ -469,7 +469,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
       op.push_back(tc_build(env2v(j, j.R[j.Lc], j.Lc, "xLMlma", cdt), dense(L.rho[j.r + 1], cdt, "LM", {b2, b2}),
                             dense(L.rho[j.r], cdt, "lm", {b1, b1})));
     }
-    rec.tc(prec, cdt, op, false);
+    rec.tc(prec, cdt, std::move(op), false);
   }
 
   // ------------------------------------- phase 1: column environments ----
@@ -580,8 +580,8 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
         }
         st1.record(rec, prec, cdt);
         st2.record(rec, prec, cdt);
-        rec.tc(prec, cdt, fin);
-        rec.k2(k2s, k2f);
+        rec.tc(prec, cdt, std::move(fin));
+        rec.k2(std::move(k2s), k2f);
         for (void* p : tmp) scr.put(p);
         rec.flush(call);
       }
@@ -614,7 +614,7 @@ void plan_expect(Ctx& ctx, std::vector<peps_env*>& envs, std::vector<ExpectOut>&
           if (Y2[i][c][t])
             rd.push_back(red_desc(Y2[i][c][t], j.R[c + 1], env2_elems(j, c + 1), j.dots + Lc + 1 + 3 * c + t, cdt));
     }
-    rec.reduce(rd);
+    rec.reduce(std::move(rd));
   }
   Gather g;
   std::vector<std::array<size_t, 3>> o1(rj.size());
@@ -844,9 +844,9 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
       s3.push_back(tc_build(n, y2, R));
       flops += tc_flops(s1.back()) + tc_flops(s2.back()) + tc_flops(s3.back());
     }
-    rec.tc(prec, cdt, s1);
-    rec.tc(prec, cdt, s2);
-    rec.tc(prec, cdt, s3);
+    rec.tc(prec, cdt, std::move(s1));
+    rec.tc(prec, cdt, std::move(s2));
+    rec.tc(prec, cdt, std::move(s3));
     for (void* p : tmp) scr.put(p);
     rec.flush(call);
   }
@@ -856,7 +856,7 @@ void plan_site_env(Ctx& ctx, std::vector<SiteReq>& req, std::vector<double>& log
     const int c = req[i].c;
     rd.push_back(red_desc(j.L[c + 1], j.R[c + 1], env_elems(j, c + 1), j.dots + c + 1, cdt));
   }
-  rec.reduce(rd);
+  rec.reduce(std::move(rd));
   std::vector<std::vector<double>> hd, hl, hr;
   run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);
   log_z.assign(req.size(), 0.0);
@@ -925,7 +925,7 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
         gate[i] = g;
       }
     }
-    if (!cv.empty()) rec.ew(cv);
+    if (!cv.empty()) rec.ew(std::move(cv));
   }
 
   // Per bond (c, c+1) of row r:
@@ -1030,7 +1030,7 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
                         wr, Z));
       }
     }
-    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
+    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, std::move(st[k]));
     for (void* p : tmp) scr.put(p);
     rec.flush(call);
   }
@@ -1047,7 +1047,7 @@ void plan_bond_env(Ctx& ctx, std::vector<BondReq>& req, double& flops) {
         rd.push_back(red_desc(j.L[k], j.R[k], env_elems(j, k), j.dots + k, cdt));
       }
     }
-    rec.reduce(rd);
+    rec.reduce(std::move(rd));
   }
   std::vector<std::vector<double>> hd, hl, hr;
   run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);
@@ -1121,7 +1121,7 @@ void plan_overlap(Ctx& ctx, std::vector<OvReq>& req) {
       init.push_back(f);
       ch.push_back(c);
     }
-  rec.ew(init);
+  rec.ew(std::move(init));
   for (int s = 0; s < maxLc; ++s) {
     std::vector<TcDesc> st1, st2;
     for (Chain& c : ch) {
@@ -1135,8 +1135,8 @@ void plan_overlap(Ctx& ctx, std::vector<OvReq>& req) {
       st1.push_back(tc_build(y1, E, X));
       st2.push_back(tc_build(dense(c.e[(s + 1) & 1], DT_F64, "zw", {bx1, by1}), y1, Y));
     }
-    rec.tc(TP_F64, DT_F64, st1);
-    rec.tc(TP_F64, DT_F64, st2);
+    rec.tc(TP_F64, DT_F64, std::move(st1));
+    rec.tc(TP_F64, DT_F64, std::move(st2));
     rec.flush(call);
   }
   Gather g;
@@ -1231,7 +1231,7 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
       }
     }
     st.record(rec, prec, cdt);
-    rec.tc(prec, cdt, fin);
+    rec.tc(prec, cdt, std::move(fin));
     flops += st.flops;
     for (void* p : tmp) scr.put(p);
     rec.flush(call);
@@ -1311,7 +1311,7 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
       add(1, tc_build(y2, y1, Bk));
       add(2, tc_build(n, y2, Rk));
     }
-    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, st[k]);
+    for (int k = 0; k < 5; ++k) rec.tc(prec, cdt, std::move(st[k]));
     for (void* p : tmp) scr.put(p);
     rec.flush(call);
   }
@@ -1328,7 +1328,7 @@ void plan_bond_fit(Ctx& ctx, std::vector<FitReq>& req, double& flops) {
         rd.push_back(red_desc(j.L[k], j.R[k], env_elems(j, k), j.dots + k, cdt));
       }
     }
-    rec.reduce(rd);
+    rec.reduce(std::move(rd));
   }
   std::vector<std::vector<double>> hd, hl, hr;
   run_and_read_dots(rec, call, rj, ctx.stream, hd, hl, hr);

@@ -16,12 +16,12 @@ namespace pe {
 // ---------------------------------------------------------------- Scratch ---
 void* Scratch::get(size_t bytes) {
   if (bytes < 256) bytes = 256;
-  auto it = free_.lower_bound(bytes);
-  if (it != free_.end() && it->first <= 2 * bytes) {
-    void* p = it->second;
-    free_.erase(it);
-    return p;
-  }
+  for (auto it = free_.lower_bound(bytes); it != free_.end() && it->first <= 2 * bytes; ++it)
+    if (!it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      return p;
+    }
   void* p = arena_.alloc(bytes);
   size_[p] = bytes;
   held_ += bytes;
@@ -31,7 +31,7 @@ void* Scratch::get(size_t bytes) {
 void Scratch::put(void* p) {
   if (!p) return;
   auto it = size_.find(p);
-  if (it != size_.end()) free_.emplace(it->second, p);
+  if (it != size_.end()) free_[it->second].push_back(p);
 }
 
 namespace {
@@ -86,7 +86,7 @@ void cast_copies(Rec& rec, std::vector<AJob*>& js, const Opts& o, int c_only = -
       if (c_only >= 0 && c != c_only) continue;
       ew.push_back(ew_desc(EW_COPY, j->X[c], DT_F64, j->Xc[c], DT_F32, j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]));
     }
-  rec.ew(ew);
+  rec.ew(std::move(ew));
 }
 
 TV Tview(const AJob& j, int c, const char* lbl, int cdt) {
@@ -145,12 +145,12 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       TV X = dense(j->X[c], DT_F64, "xdgy", {j->bout[c], j->Dd[c], j->Dd[c], j->bout[c + 1]});
       fin.push_back(tc_build(X, y3, F));
     }
-    rec.ew(fills);
+    rec.ew(std::move(fills));
     for (size_t i = 0; i < st.s.size(); ++i) {
-      rec.tc(prec, cdt, st.s[i], false);
-      rec.kb(prec, cdt, st.k[i], false);
+      rec.tc(prec, cdt, std::move(st.s[i]), false);
+      rec.kb(prec, cdt, std::move(st.k[i]), false);
     }
-    rec.tc(prec, DT_F64, fin, false);
+    rec.tc(prec, DT_F64, std::move(fin), false);
     for (void* p : tmp) scr.put(p);
   }
   // left-canonical form by QR; R moves into the next tensor
@@ -170,7 +170,7 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
       if (cdt == DT_F64) j->Xc[c + 1] = nx;
     }
     rec.qr(qrs);
-    rec.tc(TP_F64, DT_F64, mv, false);
+    rec.tc(TP_F64, DT_F64, std::move(mv), false);
   }
   std::vector<RedDesc> rd;
   std::vector<EwDesc> sc;
@@ -182,8 +182,8 @@ void plan_exact(Rec& rec, Scratch& scr, std::vector<AJob*>& js, const Opts& o) {
     e.sptr = j->omega;
     sc.push_back(e);
   }
-  rec.reduce(rd);
-  rec.ew(sc);
+  rec.reduce(std::move(rd));
+  rec.ew(std::move(sc));
   cast_copies(rec, js, o);
 }
 
@@ -214,7 +214,7 @@ void als_start(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
         e.key = splitmix_stream_state(j->env->opts.seed, q);
         f.push_back(e);
       }
-    rec.ew(f);
+    rec.ew(std::move(f));
   }
   for (int s = 0; s + 1 < maxLc; ++s) {
     std::vector<QrDesc> qrs;
@@ -232,7 +232,7 @@ void als_start(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
       if (cdt == DT_F64) j->Xc[c - 1] = nx;
     }
     rec.qr(qrs);
-    rec.tc(TP_F64, DT_F64, mv, false);
+    rec.tc(TP_F64, DT_F64, std::move(mv), false);
   }
   cast_copies(rec, js, o);
   for (int s = 0; s + 1 < maxLc; ++s) {
@@ -247,7 +247,7 @@ void als_start(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
       j->env->flops += st.flops - f0 + tc_flops(env.back());
     }
     st.record(rec, prec, cdt);
-    rec.tc(prec, cdt, env);
+    rec.tc(prec, cdt, std::move(env));
   }
   for (AJob* j : js) j->H = 0;
 }
@@ -308,7 +308,7 @@ void als_halfsweep(Rec& rec, std::vector<AJob*>& js, const Opts& o, int h) {
       }
     }
     st.record(rec, prec, cdt);
-    rec.tc(prec, DT_F64, site);
+    rec.tc(prec, DT_F64, std::move(site));
     rec.qr(qrs);
     if (cdt != DT_F64) {
       std::vector<EwDesc> ew;
@@ -317,9 +317,9 @@ void als_halfsweep(Rec& rec, std::vector<AJob*>& js, const Opts& o, int h) {
         ew.push_back(ew_desc(EW_COPY, j->X[c], DT_F64, j->Xc[c], DT_F32,
                              j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1]));
       }
-      rec.ew(ew);
+      rec.ew(std::move(ew));
     }
-    rec.tc(prec, cdt, env);
+    rec.tc(prec, cdt, std::move(env));
   }
   std::vector<RedDesc> rd;
   for (AJob* j : js) {
@@ -327,7 +327,7 @@ void als_halfsweep(Rec& rec, std::vector<AJob*>& js, const Opts& o, int h) {
     rd.push_back(red_desc(j->N, nullptr, j->bout[c] * j->Dd[c] * j->Dd[c] * j->bout[c + 1], j->omega + h, DT_F64));
     j->H = h + 1;
   }
-  rec.reduce(rd);
+  rec.reduce(std::move(rd));
 }
 
 // Normalise each job's centre tensor (site Lc-1 after an odd number of
@@ -340,7 +340,7 @@ void als_finish(Rec& rec, std::vector<AJob*>& js, const Opts& o) {
     e.sptr = j->omega + (j->H - 1);
     sc.push_back(e);
   }
-  rec.ew(sc);
+  rec.ew(std::move(sc));
   cast_copies(rec, js, o);
 }
 
@@ -559,7 +559,7 @@ void plan_boundaries(Ctx& ctx, std::vector<peps_env*>& envs) {
     for (size_t i = 0; i < acc.size(); ++i)
       if (acc[i].n) acc[i].src = wd + first[i];
   }
-  rec.ew(acc);
+  rec.ew(std::move(acc));
   rec.run(call);
   std::vector<double> hl(std::max<size_t>(nlog, 1));
   dev::d2h(hl.data(), logs, sizeof(double) * nlog, ctx.stream);

@@ -16,7 +16,7 @@ class Scratch {
 
  private:
   Arena& arena_;
-  std::multimap<size_t, void*> free_;
+  std::map<size_t, std::vector<void*>> free_;   // by exact size
   std::unordered_map<void*, size_t> size_;
   size_t held_ = 0;
 };

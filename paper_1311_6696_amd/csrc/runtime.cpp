@@ -17,7 +17,8 @@ static size_t size_class(size_t b) {
 }
 
 Pool::~Pool() {
-  for (auto& kv : free_) dev::free(kv.second);
+  for (auto& kv : free_)
+    for (void* p : kv.second) dev::free(p);
   for (auto& kv : size_of_) (void)kv;   // blocks still in use are leaked deliberately
 }
 
@@ -25,9 +26,9 @@ void* Pool::alloc(size_t bytes) {
   const size_t sc = size_class(bytes);
   auto it = free_.find(sc);
   void* p;
-  if (it != free_.end()) {
-    p = it->second;
-    free_.erase(it);
+  if (it != free_.end() && !it->second.empty()) {
+    p = it->second.back();
+    it->second.pop_back();
   } else {
     try {
       p = dev::malloc(sc);
@@ -46,14 +47,15 @@ void Pool::release(void* p) {
   auto it = size_of_.find(p);
   if (it == size_of_.end()) return;
   in_use_ -= it->second;
-  free_.emplace(it->second, p);
+  free_[it->second].push_back(p);
 }
 
 void Pool::trim() {
-  for (auto& kv : free_) {
-    size_of_.erase(kv.second);
-    dev::free(kv.second);
-  }
+  for (auto& kv : free_)
+    for (void* p : kv.second) {
+      size_of_.erase(p);
+      dev::free(p);
+    }
   free_.clear();
 }
 
@@ -92,7 +94,7 @@ void* Ctx::pinned_get(size_t bytes) {
 void Ctx::pinned_put(void* p, size_t) { pinned_free.emplace(pinned_size[p], p); }
 
 // ----------------------------------------------------------------- views ----
-TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_t>& dims) {
+TV dense(const void* p, int dt, const std::string& idx, const Dims& dims) {
   PE_REQUIRE(idx.size() == dims.size(), "view rank mismatch for '" + idx + "'");
   TV v;
   v.p = p;
@@ -118,8 +120,9 @@ namespace {
 struct Sub {
   int64_t dim, s1, s2;
 };
-void merge_subs(std::vector<Sub>& v) {
-  std::vector<Sub> out;
+using Subs = SmallVec<Sub, 16>;
+void merge_subs(Subs& v) {
+  Subs out;
   for (const Sub& s : v) {
     if (!out.empty() && out.back().s1 == s.s1 * s.dim && out.back().s2 == s.s2 * s.dim) {
       out.back().dim *= s.dim;
@@ -130,11 +133,14 @@ void merge_subs(std::vector<Sub>& v) {
     }
   }
   if (out.empty()) out.push_back({1, 0, 0});
-  v.swap(out);
+  v = out;
 }
 int find_idx(const TV& t, char c) {
-  const size_t p = t.idx.find(c);
-  return p == std::string::npos ? -1 : (int)p;
+  const char* s = t.idx.data();
+  const int n = (int)t.idx.size();
+  for (int i = 0; i < n; ++i)
+    if (s[i] == c) return i;
+  return -1;
 }
 }  // namespace
 
@@ -151,7 +157,7 @@ TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha, double beta
   const bool x_is_a = (cin == 0) || find_idx(X, cin) >= 0;
   const TV& A = x_is_a ? X : Y;
   const TV& B = x_is_a ? Y : X;
-  std::vector<Sub> Ms, Ns, Ks;
+  Subs Ms, Ns, Ks;
   for (size_t i = 0; i < C.idx.size(); ++i) {
     const char c = C.idx[i];
     const int ia = find_idx(A, c), ib = find_idx(B, c);
@@ -234,7 +240,7 @@ KbDesc kb_build(const TV& Y, const TV& X, const TV& K, const TV& B) {
   d.B = B.p;
   d.Y = const_cast<void*>(Y.p);
   auto group = [](KbGroup& g, const TV& t0, const TV& t1, const TV& order, const TV& excl1, const TV& excl2) {
-    std::vector<Sub> subs;
+    Subs subs;
     for (size_t i = 0; i < order.idx.size(); ++i) {
       const char c = order.idx[i];
       const int i0 = find_idx(t0, c), i1 = find_idx(t1, c);
@@ -294,8 +300,8 @@ enum OpKind { OK_TC = 0, OK_QR = 1, OK_RED = 2, OK_EW = 3, OK_SEP = 4, OK_TCR = 
 
 size_t Rec::push_bytes(const void* p, size_t n) {
   const size_t off = (blob_.size() + 15) / 16 * 16;
-  blob_.resize(off + n);
-  std::memcpy(blob_.data() + off, p, n);
+  blob_.resize(off);
+  blob_.insert(blob_.end(), (const uint8_t*)p, (const uint8_t*)p + n);
   return off;
 }
 
@@ -461,11 +467,23 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
   // the descriptors of one group are independent, so families (and the
   // skinny-kernel members of a family) may run as separate launches
   std::vector<TcDesc> fam[N_FAMILIES];
-  for (const auto& d : ds) fam[tile_family(d)].push_back(d);
+  {
+    const int f0 = tile_family(ds[0]);
+    bool one = true;
+    for (size_t i = 1; i < ds.size() && one; ++i) one = tile_family(ds[i]) == f0;
+    if (one) fam[f0].swap(ds);
+    else
+      for (const auto& d : ds) fam[tile_family(d)].push_back(d);
+  }
   for (int f = 0; f < N_FAMILIES; ++f) {
     if (fam[f].empty()) continue;
     std::vector<TcDesc> sk, rest;
-    for (const auto& d : fam[f]) ((f != 2 && skinny_fits(d)) ? sk : rest).push_back(d);
+    size_t nsk = 0;
+    for (const auto& d : fam[f]) nsk += (f != 2 && skinny_fits(d)) ? 1 : 0;
+    if (nsk == 0) rest.swap(fam[f]);
+    else if (nsk == fam[f].size()) sk.swap(fam[f]);
+    else
+      for (const auto& d : fam[f]) ((f != 2 && skinny_fits(d)) ? sk : rest).push_back(d);
     const uint64_t key[2] = {sk.empty() ? 0 : tune_key(prec, out_dt, f, true, sk),
                              rest.empty() ? 0 : tune_key(prec, out_dt, f, false, rest)};
     bool tuned = ctx_->tuning && scratch_ && !plain_;
@@ -474,10 +492,16 @@ void Rec::tc(int prec, int out_dt, std::vector<TcDesc> ds, bool algorithmic) {
     if (!tuned) {
       // heuristic: the skinny members in one skinny launch when they fill the
       // chip, everything else in one tiled launch
-      if (!sk.empty() && tcs_launch(prec, out_dt, sk, algorithmic)) fam[f].swap(rest);
-      if (fam[f].empty()) continue;
-      const int tile = pick_tile(f, fam[f]);
-      tc_launch(prec, out_dt, tile, std::move(fam[f]), algorithmic, true);
+      // (a declined skinny launch leaves the descriptors as they were; all
+      // of them then go to the tiled launch, in their original order)
+      std::vector<TcDesc>* tiled;
+      if (!sk.empty() && tcs_launch(prec, out_dt, sk, algorithmic)) tiled = &rest;
+      else if (sk.empty()) tiled = &rest;
+      else if (rest.empty()) tiled = &sk;
+      else tiled = &fam[f];
+      if (tiled->empty()) continue;
+      const int tile = pick_tile(f, *tiled);
+      tc_launch(prec, out_dt, tile, std::move(*tiled), algorithmic, true);
       continue;
     }
     for (int part = 0; part < 2; ++part) {
@@ -1002,7 +1026,14 @@ void Rec::run(Arena& arena) {
   pinned_.clear();
 }
 
+Rec::Rec(Ctx* c, Arena* scratch) : ctx_(c), scratch_(scratch) {
+  blob_.swap(ctx_->blob_spare);   // its capacity, not its contents
+  blob_.clear();
+}
+
 Rec::~Rec() {
+  blob_.clear();
+  if (blob_.capacity() > ctx_->blob_spare.capacity()) ctx_->blob_spare.swap(blob_);
   if (!pinned_.empty() || !events_.empty()) {
     try {
       dev::sync(ctx_->stream);

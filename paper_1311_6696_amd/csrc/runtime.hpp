@@ -1,6 +1,7 @@
 // Host runtime of libpepsenv: memory pool, op recorder, tensor views and the
 // environment data structures.
 #pragma once
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <unordered_map>
@@ -22,7 +23,7 @@ class Pool {
   size_t bytes_in_use() const { return in_use_; }
 
  private:
-  std::multimap<size_t, void*> free_;
+  std::unordered_map<size_t, std::vector<void*>> free_;   // per size class
   std::unordered_map<void*, size_t> size_of_;
   size_t in_use_ = 0;
 };
@@ -73,20 +74,62 @@ class Arena {
   size_t cap_ = 0, used_ = 0;
 };
 
+// A vector of at most N elements held in place: the dimensions and strides
+// of views and the sub-dimension lists of descriptors, formed by the
+// hundred thousand per batched call, cost no heap allocation.
+template <class T, int N>
+struct SmallVec {
+  T v[N];
+  int n = 0;
+  SmallVec() = default;
+  SmallVec(std::initializer_list<T> l) {
+    for (const T& x : l) push_back(x);
+  }
+  SmallVec(const std::vector<T>& l) {
+    for (const T& x : l) push_back(x);
+  }
+  size_t size() const { return (size_t)n; }
+  bool empty() const { return n == 0; }
+  T& operator[](size_t i) { return v[i]; }
+  const T& operator[](size_t i) const { return v[i]; }
+  T* begin() { return v; }
+  T* end() { return v + n; }
+  const T* begin() const { return v; }
+  const T* end() const { return v + n; }
+  T& back() { return v[n - 1]; }
+  void push_back(const T& x) {
+    PE_REQUIRE(n < N, "more than " + std::to_string(N) + " entries in a fixed-capacity list");
+    v[n++] = x;
+  }
+  void assign(size_t k, const T& x) {
+    n = 0;
+    for (size_t i = 0; i < k; ++i) push_back(x);
+  }
+  void clear() { n = 0; }
+  bool operator==(const SmallVec& o) const {
+    if (n != o.n) return false;
+    for (int i = 0; i < n; ++i)
+      if (!(v[i] == o.v[i])) return false;
+    return true;
+  }
+  bool operator!=(const SmallVec& o) const { return !(*this == o); }
+};
+using Dims = SmallVec<int64_t, 12>;
+
 // ------------------------------------------------------------------ views ---
 // A strided tensor view with one character label per index.
 struct TV {
   const void* p = nullptr;
   int dt = DT_F64;
   std::string idx;
-  std::vector<int64_t> dim, str;
+  Dims dim, str;
   int64_t size() const {
     int64_t n = 1;
     for (auto d : dim) n *= d;
     return n;
   }
 };
-TV dense(const void* p, int dt, const std::string& idx, const std::vector<int64_t>& dims);
+TV dense(const void* p, int dt, const std::string& idx, const Dims& dims);
 TV relabel(TV v, const std::string& idx);
 // C = alpha * contraction(X, Y) + beta * C, every index in exactly two views.
 TcDesc tc_build(const TV& C, const TV& X, const TV& Y, double alpha = 1.0, double beta = 0.0);
@@ -103,7 +146,7 @@ struct Ctx;
 class Rec {
  public:
   // `scratch` (optional) provides record-time workspace, e.g. split-K partials.
-  explicit Rec(Ctx* c, Arena* scratch = nullptr) : ctx_(c), scratch_(scratch) {}
+  explicit Rec(Ctx* c, Arena* scratch = nullptr);
   // Plain issue: no graph capture, profiling events, autotuning or pinned
   // staging (descriptors are copied from host memory and waited for), so
   // that with fixed arenas the recorder allocates no device or pinned memory.
@@ -205,6 +248,7 @@ struct Ctx {
   int graph_count = 0;
   hipStream_t capture_stream = nullptr;   // graphs are recorded here (the caller's may be the null stream)
   void clear_graphs();
+  std::vector<uint8_t> blob_spare;              // a recorder's descriptor buffer, kept for the next one
   std::multimap<size_t, void*> pinned_free;     // pinned staging buffers by capacity
   std::unordered_map<void*, size_t> pinned_size;
   ~Ctx();
