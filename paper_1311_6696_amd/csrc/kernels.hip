@@ -2526,12 +2526,15 @@ struct K2Smem {
   double Bx[2][16 * CH];
   double Y2[2][16 * 256];
   double Priv[K2_W * K2_PRIV];   // per wave: its block or its ket rows
+  int last;                      // this workgroup is the last slice of its output value
 };
 
-// One workgroup's column step (output value e of descriptor d).  FULL: the
-// descriptor's bonds a and y equal CH, so no partial tile is masked.
+// One workgroup's column step (output value e of descriptor d, x slice sl).
+// FULL: the descriptor's bonds a and y equal CH, so no partial tile is masked.
 template <int CH, bool FULL>
-__device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, const int e, K2Smem<CH>& S) {
+__device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, const int e, const int sl,
+                                                              unsigned* counters, K2Smem<CH>& S) {
+  static_assert(CH / 4 * K2_T == K2_PART || CH != K2_CHI, "partial result size");
   double* Te = S.Te;
   double *K1s = S.K1s, *B1s = S.B1s, *K2s = S.K2s, *B2s = S.B2s;
   double(*Bx)[16 * CH] = S.Bx;
@@ -2616,11 +2619,14 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
       }
     }
   };
-  load_l(0);
-  load_b(0);
+  const int x0 = (int)((int64_t)sl * X / d.ns), x1 = (int)((int64_t)(sl + 1) * X / d.ns);
+  if (x0 < x1) {
+    load_l(x0);
+    load_b(x0);
+  }
   __syncthreads();
 
-  for (int x = 0; x < X; ++x) {
+  for (int x = x0; x < x1; ++x) {
     // ---- row 1 for this wave's block o = (L, M): y1[(l,m)][(u,v)] = sum_a Lin[x,L,M,l,m,a] T[a,u,v,e]
     //      into the block [q=(m,v)][k=(l,u)], then ket and bra
     {
@@ -2638,7 +2644,7 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
         Pw[(m * 4 + vv) * K2_QP + l * 4 + u] = acc[j];
       }
     }
-    if (x + 1 < X) load_l(x + 1);   // in flight during the rows and the bottom boundary
+    if (x + 1 < x1) load_l(x + 1);   // in flight during the rows and the bottom boundary
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const d4_t y2 = k2_row<false>(Pw, K1s, B1s, Pw, lr, lk);
@@ -2658,7 +2664,7 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
 #pragma unroll
     for (int j = 0; j < NBX; ++j)
       if (tid + K2_T * j < 16 * CH) Bxx[tid + K2_T * j] = bxf[j];
-    if (x + 1 < X) load_b(x + 1);   // in flight during row 2 and the bottom boundary
+    if (x + 1 < x1) load_b(x + 1);   // in flight during row 2 and the bottom boundary
     __syncthreads();
     // ---- row 2 for this wave's block o = (r, s), then the bottom boundary:
     //      out[(r,s)][(R,S)][y] += sum_(D,G) y3[(r,s)][(R,S)][(D,G)] Bx[(D,G)][y]
@@ -2688,6 +2694,43 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
       __builtin_amdgcn_wave_barrier();   // the block is read before the next x rewrites it
     }
   }
+  // ---- x slices: this slice's partial result, device-scope stores (read by
+  // whichever workgroup finishes the value last, on any XCD); the last one
+  // sums the ns partials in slice order, so the result does not depend on
+  // the order in which the slices finish.
+  if (d.ns > 1) {
+    int t1 = threadIdx.x;
+    asm volatile("" : "+v"(t1));
+    double* part = d.part + ((int64_t)e * d.ns + sl) * K2_PART;
+#pragma unroll
+    for (int c = 0; c < CH / 16; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        __hip_atomic_store(&part[(c * 4 + j) * K2_T + t1], out[c][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's partial is complete before the counter moves
+    __syncthreads();
+    if (t1 == 0)
+      S.last = __hip_atomic_fetch_add(counters + d.cnt_base + e, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               (unsigned)(d.ns - 1);
+    __syncthreads();
+    if (!S.last) return;
+    const double* tp = d.part + (int64_t)e * d.ns * K2_PART;
+#pragma unroll
+    for (int c = 0; c < CH / 16; ++c) out[c] = k2_zero();
+    for (int q = 0; q < d.ns; ++q) {
+      double v[CH / 16][4];
+#pragma unroll
+      for (int c = 0; c < CH / 16; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          v[c][j] = __hip_atomic_load(const_cast<double*>(&tp[(int64_t)q * K2_PART + (c * 4 + j) * K2_T + t1]),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int c = 0; c < CH / 16; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[c][j] += v[c][j];
+    }
+  }
   // ---- store: this lane's rows (R,S) = lane & 15 of block (r,s) = w; columns y.
   // The lane index is re-read through an empty asm so that the store
   // addresses are formed here: hoisted above the x loop they would stay live
@@ -2710,7 +2753,8 @@ __device__ __attribute__((always_inline)) inline void k2_body(const K2Desc& d, c
 
 
 template <int CH>
-__global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds, int nd, int nblocks) {
+__global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds, int nd, int nblocks,
+                                                  unsigned* counters) {
   __shared__ K2Smem<CH> S;
   // XCD-aware order: consecutive virtual blocks (the e values of one
   // descriptor) go to one XCD, so they share the incoming environment in L2
@@ -2723,11 +2767,13 @@ __global__ __launch_bounds__(K2_T) void k2_kernel(const K2Desc* __restrict__ ds,
     if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
   }
   const K2Desc& d = ds[lo];
-  const int e = v - d.block_base;
+  // slice-major within a descriptor: consecutive workgroups take the same x
+  // slice of successive output values and share its rows of L in L2
+  const int u = v - d.block_base, sl = u / d.E, e = u - sl * d.E;
   if (d.A == CH && d.Y == CH)
-    k2_body<CH, true>(d, e, S);
+    k2_body<CH, true>(d, e, sl, counters, S);
   else
-    k2_body<CH, false>(d, e, S);
+    k2_body<CH, false>(d, e, sl, counters, S);
 }
 
 // One-row chain step: wave w of a workgroup takes x = KC_W * xt + w for the
@@ -2823,11 +2869,11 @@ void launch_kc(const KcDesc* d, int nd, int nblocks, hipStream_t s) {
   PE_HIP(hipGetLastError());
 }
 
-void launch_k2(const K2Desc* d, int nd, int nblocks, int chmax, hipStream_t s) {
+void launch_k2(const K2Desc* d, int nd, int nblocks, int chmax, unsigned* counters, hipStream_t s) {
   if (nblocks <= 0) return;
   const int grid = (nblocks + 7) / 8 * 8;   // a multiple of the XCD count: the block order is a bijection
   if (chmax > K2_CHI) throw Error(ST_INVALID, "two-row column step: bond above the fused kernel's limit");
-  k2_kernel<K2_CHI><<<grid, K2_T, 0, s>>>(d, nd, nblocks);
+  k2_kernel<K2_CHI><<<grid, K2_T, 0, s>>>(d, nd, nblocks, counters);
   PE_HIP(hipGetLastError());
 }
 

@@ -104,11 +104,20 @@ struct K2Desc {
   int64_t sO[6];        // y, R, S, r, s, e
   int64_t ss[4][5];
   int32_t X, A, E, Y;   // bonds: x (L, Bb), a (L, T), e (T, O), y (Bb, O), each <= K2_CHI
-  int32_t block_base;   // first workgroup (output value e = 0) of this descriptor
-  int32_t pad;
+  int32_t block_base;   // first workgroup of this descriptor (slice 0 of output value e = 0)
+  // x slices per output value (filled when the op is recorded): with ns > 1
+  // workgroup (sl, e) sums x over its slice only and writes the partial
+  // result to part[(e*ns + sl)*K2_PART ...]; the last slice of e to finish
+  // (arrival counter cnt_base + e) adds the ns partials in slice order and
+  // stores O.  ns == 1: the workgroup stores O directly.
+  int32_t ns;
+  int32_t cnt_base, pad;
+  double* part;
 };
-// chmax: the largest bond (A or Y) of the launch's descriptors.
-void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, hipStream_t s);
+constexpr int K2_PART = K2_CHI / 4 * 1024;   // partial result of one (e, slice): 1024 threads x K2_CHI/4 values
+// chmax: the largest bond (A or Y) of the launch's descriptors; counters:
+// the arrival counters of the sliced descriptors (zero at launch).
+void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, unsigned* counters, hipStream_t s);
 
 // One-row chain step (D = 4, d = 2, float64), the ALS site step's and the
 // one-row sandwich's first three contractions in one launch:

@@ -693,21 +693,64 @@ void Rec::kb(int prec, int out_dt, std::vector<KbDesc> ds, bool algorithmic) {
 
 void Rec::k2(std::vector<K2Desc> ds, double flops) {
   if (ds.empty()) return;
-  int64_t blocks = 0;
+  int64_t units = 0;
   double by = 0.0;
-  int chmax = 1;
+  int chmax = 1, xmin = INT_MAX;
   for (auto& d : ds) {
     chmax = std::max(chmax, std::max(d.A, d.Y));
     PE_REQUIRE(d.X >= 1 && d.A >= 1 && d.E >= 1 && d.Y >= 1 && d.X <= K2_CHI && d.A <= K2_CHI && d.E <= K2_CHI &&
                    d.Y <= K2_CHI,
                "two-row column step: bond outside the fused kernel's range");
-    d.block_base = (int32_t)blocks;
-    blocks += d.E;
+    units += d.E;
+    xmin = std::min(xmin, d.X);
     // algorithmic bytes: the incoming environment, both boundary tensors, four sites, the outgoing environment
     by += 8.0 * ((double)d.X * 256 * d.A + (double)d.A * 16 * d.E + (double)d.X * 16 * d.Y + 4 * 512.0 +
                  (double)d.Y * 256 * d.E);
   }
+  // x slices.  One workgroup per output value fills the chip's compute
+  // units (one workgroup each) in rounds; when the last round would run
+  // mostly empty, each value's x range is cut into ns slices.  Model, in
+  // units of one value's full x loop: rounds * (1/ns + eps) for the slices
+  // plus 2 eps ns for the last slice's sum over the partials, eps the cost
+  // of one partial result's trip through memory.
+  constexpr int CUS = 256;
+  constexpr double EPS = 0.01;
+  int ns = 1;
+  if (scratch_ && units < 8 * CUS) {
+    double best = std::ceil((double)units / CUS);
+    for (int s = 2; s <= 8 && 2 * s <= xmin; ++s) {
+      const double c = std::ceil((double)units * s / CUS) * (1.0 / s + EPS) + 2.0 * EPS * s;
+      if (c < best - 1e-9) {
+        best = c;
+        ns = s;
+      }
+    }
+  }
+  int64_t blocks = 0, parts = 0;
+  for (auto& d : ds) {
+    d.ns = ns;
+    d.block_base = (int32_t)blocks;
+    blocks += (int64_t)d.E * ns;
+    d.cnt_base = cq_slots_;
+    d.part = nullptr;
+    if (ns > 1) {
+      cq_slots_ += d.E;
+      parts += (int64_t)d.E * ns * K2_PART;
+    }
+  }
   PE_REQUIRE(blocks < INT_MAX / 8, "fused two-row step too large");
+  if (parts > 0) {
+    // shared with the other split launches of this recorder (stream order)
+    if ((size_t)parts > part_cap_) {
+      part_cap_ = std::max((size_t)parts, part_cap_ * 2);
+      part_buf_ = (double*)scratch_->alloc(sizeof(double) * part_cap_);
+    }
+    int64_t off = 0;
+    for (auto& d : ds) {
+      d.part = part_buf_ + off;
+      off += (int64_t)d.E * ns * K2_PART;
+    }
+  }
   Op op{OK_K2, TP_F64, DT_F64, TT_K2, (int)ds.size(), (int)blocks, push_bytes(ds.data(), ds.size() * sizeof(K2Desc)),
         flops};
   op.bytes = by;
@@ -893,7 +936,7 @@ void Rec::issue(const uint8_t* dblob, double* partials, unsigned* counters, bool
       case OK_TCS:
         launch_tcs(op.prec, op.out_dt, op.tile - TT_S16 + 1, op.ksm, (const TcDesc*)d, op.nd, op.grid, op.kp, s);
         break;
-      case OK_K2: launch_k2((const K2Desc*)d, op.nd, op.grid, op.kp, s); break;
+      case OK_K2: launch_k2((const K2Desc*)d, op.nd, op.grid, op.kp, counters, s); break;
       case OK_KC: launch_kc((const KcDesc*)d, op.nd, op.grid, s); break;
       case OK_TSK: launch_tsk((const TskDesc*)d, op.nd, op.grid, counters, s); break;
       case OK_KB:
