@@ -559,6 +559,22 @@ def main():
             err = max(abs(energy(r) - e) / abs(e) for r, e in zip(rr, e64))
             forms[dname] = {"value": vv, "unit": "env/s", "ms_per_call": mm, "speedup_vs_single_f64": vv / single,
                             "max_rel_energy_err_vs_f64": err}
+        # the dominant kernel of the batched FP64 call (same rule as the headline's roofline)
+        sess.ctx.profile(True)
+        envs = sess.env_boundary(states[:nl], chi, "f64", H)
+        sess.expect(envs)
+        for e in envs:
+            e.free()
+        torch.cuda.synchronize()
+        bfl, bkms, bnl, _ = sess.ctx.stats()
+        sess.ctx.profile(False)
+        bd = int(np.argmax(bfl))
+        if bnl[bd] > 0 and bkms[bd] > 0:
+            rate = bfl[bd] / (bkms[bd] * 1e-3) / 1e12
+            forms["f64"]["dominant_kernel"] = {"kernel": binding.variant_name(bd), "achieved": rate,
+                                               "peak": PEAK["f64"], "unit": "TFLOP/s", "frac": rate / PEAK["f64"],
+                                               "launches": int(bnl[bd]),
+                                               "avg_launch_us": 1000.0 * bkms[bd] / bnl[bd]}
         out["batched_forms"] = forms
 
     if not args.no_columns:

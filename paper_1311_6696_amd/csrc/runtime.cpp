@@ -714,7 +714,7 @@ void Rec::k2(std::vector<K2Desc> ds, double flops) {
   // plus 2 eps ns for the last slice's sum over the partials, eps the cost
   // of one partial result's trip through memory.
   constexpr int CUS = 256;
-  constexpr double EPS = 0.01;
+  constexpr double EPS = 0.03;
   int ns = 1;
   if (scratch_ && units < 8 * CUS) {
     double best = std::ceil((double)units / CUS);
