@@ -218,7 +218,7 @@ def side_instances(sess, binding, torch):
     states = [binding.to_device(insts[k]) for k in keep]
     chis = [pairs[k][1] ** 2 for k in keep]
     ref = None
-    for dt in ("f64", "bf16"):
+    for dt in ("f64", "f32", "bf16"):
         note(f"batched instances {dt}")
 
         def run():
