@@ -39,7 +39,8 @@ def kernel_slug(name):
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` on this workload from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
-    known size); None when there is none or the kernel source changed since."""
+    known size); None when there is none or the kernel or recorder source
+    changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel_slug(kernel)}__{WORKLOAD_TAG}.md")
     if not os.path.exists(path):
@@ -49,9 +50,12 @@ def measured_traffic(kernel):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    src = os.path.join(ROOT, "paper_1311_6696_amd", "csrc", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernels.hip sha256") != digest or "traffic bytes per launch" not in fields:
+    # the kernel's source and the recorder's, which fixes its launch shapes
+    for name in ("kernels.hip", "runtime.cpp"):
+        src = os.path.join(ROOT, "paper_1311_6696_amd", "csrc", name)
+        if fields.get(f"{name} sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+    if "traffic bytes per launch" not in fields:
         return None
     return float(fields["traffic bytes per launch"])
 def run_steps(sess, dev_state, chi, dtype, halfsweeps, n, split=None, columns=False):
