@@ -2798,7 +2798,7 @@ __global__ __launch_bounds__(KC_T) void kc_kernel(const KcDesc* __restrict__ ds,
     if (ds[mid].block_base <= v) lo = mid; else hi = mid - 1;
   }
   const KcDesc& d = ds[lo];
-  const int local = v - d.block_base, xt = local / d.Ne, e = local - xt * d.Ne;
+  const int local = v - d.block_base, xq = local / d.Ne, e = local - xq * d.Ne;
   const int A = d.A, A4 = (A + 3) & ~3;
   for (int i = tid; i < 512; i += KC_T) {
     {   // Ks[(l,u)][(d,r,p)]
@@ -2816,48 +2816,53 @@ __global__ __launch_bounds__(KC_T) void kc_kernel(const KcDesc* __restrict__ ds,
     const int a = i >> 4, uv = i & 15;
     Te[i] = a < A ? d.T[a * d.sT[0] + (uv >> 2) * d.sT[1] + (uv & 3) * d.sT[2] + e * d.sT[3]] : 0.0;
   }
-  // this wave's x (clamped for the loads; waves past X store nothing) and
-  // its lane's row (l, m) = lr of E, a = 4 ks + lk
-  const int x = KC_W * xt + w;
-  const bool act = x < d.X;
-  const double* Ex = d.E + (act ? x : d.X - 1) * d.sE[0] + (lr >> 2) * d.sE[1] + (lr & 3) * d.sE[2];
   constexpr int KMAX = K2_CHI / 4;
-  double lxf[KMAX];
+  const int ngroups = (d.X + KC_W - 1) / KC_W;
+  for (int r = 0; r < d.xr; ++r) {
+    const int xt = xq * d.xr + r;
+    if (xt >= ngroups) break;   // the same for every wave of the workgroup
+    // this wave's x (clamped for the loads; waves past X store nothing) and
+    // its lane's row (l, m) = lr of E, a = 4 ks + lk
+    const int x = KC_W * xt + w;
+    const bool act = x < d.X;
+    const double* Ex = d.E + (act ? x : d.X - 1) * d.sE[0] + (lr >> 2) * d.sE[1] + (lr & 3) * d.sE[2];
+    double lxf[KMAX];
 #pragma unroll
-  for (int ks = 0; ks < KMAX; ++ks) {
-    if (4 * ks < A4) {
-      const int a = 4 * ks + lk, ac = a < A ? a : A - 1;
-      const double val = Ex[ac * d.sE[3]];
-      lxf[ks] = a < A ? val : 0.0;
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (4 * ks < A4) {
+        const int a = 4 * ks + lk, ac = a < A ? a : A - 1;
+        const double val = Ex[ac * d.sE[3]];
+        lxf[ks] = a < A ? val : 0.0;
+      }
     }
-  }
-  __syncthreads();
-  // y1[(l,m)][(u,v)] = sum_a E[x,l,m,a] T[a,u,v,e] into the block [q=(m,v)][k=(l,u)]
-  {
-    d4_t acc = k2_zero(), acc2 = k2_zero();
+    if (r == 0) __syncthreads();   // the staged sites and slab
+    // y1[(l,m)][(u,v)] = sum_a E[x,l,m,a] T[a,u,v,e] into the block [q=(m,v)][k=(l,u)]
+    {
+      d4_t acc = k2_zero(), acc2 = k2_zero();
 #pragma unroll
-    for (int ks = 0; ks < KMAX; ks += 2) {
-      if (4 * ks < A4) acc = k2_mma(lxf[ks], Te[(4 * ks + lk) * 16 + lr], acc);
-      if (4 * ks + 4 < A4) acc2 = k2_mma(lxf[ks + 1], Te[(4 * ks + 4 + lk) * 16 + lr], acc2);
+      for (int ks = 0; ks < KMAX; ks += 2) {
+        if (4 * ks < A4) acc = k2_mma(lxf[ks], Te[(4 * ks + lk) * 16 + lr], acc);
+        if (4 * ks + 4 < A4) acc2 = k2_mma(lxf[ks + 1], Te[(4 * ks + 4 + lk) * 16 + lr], acc2);
+      }
+      acc += acc2;
+      const int l = lr >> 2, m = lr & 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int uv = lk + 4 * j, u = uv >> 2, vv = uv & 3;
+        Pw[(m * 4 + vv) * K2_QP + l * 4 + u] = acc[j];
+      }
     }
-    acc += acc2;
-    const int l = lr >> 2, m = lr & 3;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const d4_t y2 = k2_row<false>(Pw, Ks, Bs, Pw, lr, lk);   // [(d,r)][(g,s)]
+    if (act) {
+      const int dd = lr >> 2, rr = lr & 3;
+      const int64_t base = x * d.sY[0] + dd * d.sY[1] + rr * d.sY[3] + e * d.sY[5];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int uv = lk + 4 * j, u = uv >> 2, vv = uv & 3;
-      Pw[(m * 4 + vv) * K2_QP + l * 4 + u] = acc[j];
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  const d4_t y2 = k2_row<false>(Pw, Ks, Bs, Pw, lr, lk);   // [(d,r)][(g,s)]
-  if (act) {
-    const int dd = lr >> 2, r = lr & 3;
-    const int64_t base = x * d.sY[0] + dd * d.sY[1] + r * d.sY[3] + e * d.sY[5];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gs = lk + 4 * j, g = gs >> 2, sx = gs & 3;
-      d.Y[base + g * d.sY[2] + sx * d.sY[4]] = y2[j];
+      for (int j = 0; j < 4; ++j) {
+        const int gs = lk + 4 * j, g = gs >> 2, sx = gs & 3;
+        d.Y[base + g * d.sY[2] + sx * d.sY[4]] = y2[j];
+      }
     }
   }
 }

@@ -124,7 +124,8 @@ void launch_k2(const K2Desc* d_desc, int n_desc, int n_blocks, int chmax, unsign
 //   Y[x][d][g][r][s][e] = sum E[x][l][m][a] T[a][u][v][e] K[p][l][u][r][d] B[p][m][v][s][g]
 // (a right-to-left step is the same with the roles of its horizontal legs
 // exchanged through the strides).  One wave per (x, e), KC_W x per
-// workgroup.
+// workgroup and pass; a workgroup makes xr passes over consecutive groups
+// of x with the same e, reusing its staged sites and top boundary slab.
 struct KcDesc {
   const double* E;
   const double* T;
@@ -135,7 +136,9 @@ struct KcDesc {
   int64_t ss[2][5];     // p, l, u, r, d  (bra: p, m, v, s, g)
   int64_t sY[6];        // x, d, g, r, s, e
   int32_t X, A, Ne;     // bonds x, a (<= K2_CHI) and e
-  int32_t block_base;   // first workgroup of this descriptor: ceil(X / KC_W) * Ne of them, e fastest
+  int32_t block_base;   // first workgroup of this descriptor: ceil(ceil(X / KC_W) / xr) * Ne of them, e fastest
+  int32_t xr;           // groups of KC_W x values per workgroup (filled when the op is recorded)
+  int32_t pad;
 };
 constexpr int KC_W = 8;   // waves (x values) per workgroup of the one-row chain step
 void launch_kc(const KcDesc* d_desc, int n_desc, int n_blocks, hipStream_t s);

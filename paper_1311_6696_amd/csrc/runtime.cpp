@@ -763,11 +763,20 @@ void Rec::k2(std::vector<K2Desc> ds, double flops) {
 
 void Rec::kc(std::vector<KcDesc> ds, double flops) {
   if (ds.empty()) return;
+  // A workgroup stages both sites and one top boundary slab for KC_W waves'
+  // worth of work; in a launch of many workgroups (batches) it makes xr
+  // passes over consecutive x groups so that the staging is shared, while
+  // keeping at least 1024 workgroups (four per compute unit) in flight.
+  int64_t one = 0;
+  for (const auto& d : ds) one += (int64_t)((d.X + KC_W - 1) / KC_W) * d.Ne;
+  const int xr = (int)std::max<int64_t>(1, std::min<int64_t>(4, one / 1024));
   int64_t blocks = 0;
   for (auto& d : ds) {
     PE_REQUIRE(d.X >= 1 && d.A >= 1 && d.Ne >= 1 && d.A <= K2_CHI, "one-row chain step: bond outside the fused kernel's range");
     d.block_base = (int32_t)blocks;
-    blocks += (int64_t)((d.X + KC_W - 1) / KC_W) * d.Ne;
+    d.xr = xr;
+    const int64_t groups = (d.X + KC_W - 1) / KC_W;
+    blocks += (groups + xr - 1) / xr * d.Ne;
   }
   PE_REQUIRE(blocks < INT_MAX / 8, "one-row chain step too large");
   flops_ += flops;
