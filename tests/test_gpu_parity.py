@@ -169,6 +169,22 @@ def test_batched_heterogeneous(sess):
         assert max_obs_diff(r, ref) < TOL64
 
 
+def test_batched_large_launches_match_single_lattices(sess):
+    """Eight 8x8 D=4 chi=32 lattices in one call: the chain-step launches are
+    large enough for each workgroup to make several x passes and the column
+    steps run without x slices, unlike one lattice per call; every lattice's
+    observables and log-norm agree with its own single-lattice run (whose
+    parity with the oracle is checked at full size elsewhere)."""
+    say("8 x (8x8 D=4 chi=32) batched against single")
+    As = [make_peps(8, 8, 4, "near_product", 3000 + i) for i in range(8)]
+    batch, _ = run_gpu(sess, As, 32)
+    for A, rb in zip(As, batch):
+        (rs,), _ = run_gpu(sess, [A], 32)
+        # (different launch shapes sum in different orders: rounding differences only)
+        assert max_obs_diff(rb, rs) < TOL64
+        assert abs(rb["log_norm"] - rs["log_norm"]) < TOL64 * max(1.0, abs(rs["log_norm"]))
+
+
 def test_batched_per_state_chi(sess):
     """Instances of different L, D and chi = D^2 (the batched-instances
     recipe at small sizes) in one call, one options record per state."""
