@@ -156,7 +156,8 @@ class RawState:
     """A lattice given as device pointers: ``ptrs[r][c]`` and ``shapes[r][c]``
     (d, Dl, Du, Dr, Dd).  Keeps the ctypes arrays alive."""
 
-    def __init__(self, ptrs, shapes):
+    def __init__(self, ptrs, shapes, keep=None):
+        self.keep = keep   # the tensors the pointers belong to, kept alive
         self.rows, self.cols = len(ptrs), len(ptrs[0])
         flat_dims = [int(x) for row in shapes for s in row for x in s]
         self.dims = (C.c_int32 * len(flat_dims))(*flat_dims)
@@ -392,13 +393,19 @@ def to_device(A, device="cuda"):
 
 
 def state_of(tensors):
-    """RawState from nested lists of float64 device tensors."""
+    """RawState from nested lists of float64 device tensors (a RawState is
+    returned as it is, so a caller that calls repeatedly on the same lattice
+    can marshal its pointers once)."""
+    if isinstance(tensors, RawState):
+        return tensors
+    import torch
+    f64 = torch.float64
     for row in tensors:
         for t in row:
-            if not t.is_cuda or t.dtype.__str__() != "torch.float64" or not t.is_contiguous():
+            if t.dtype is not f64 or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("site tensors must be contiguous float64 GPU tensors")
     return RawState([[t.data_ptr() for t in row] for row in tensors],
-                    [[tuple(t.shape) for t in row] for row in tensors])
+                    [[tuple(t.shape) for t in row] for row in tensors], keep=tensors)
 
 
 class Session:
